@@ -1,0 +1,163 @@
+"""CPU oracle for the multi-cell chemistry path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The product library never does, and this package
+imports nothing from it: the two share no code.  Inputs come from the seeded
+generators as plain numpy arrays.
+
+The arithmetic lives in oracle.c (plain C, double precision, one cell at a
+time); this module only marshals numpy arrays through ctypes.  See oracle.c
+for what is computed and which passages of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "oracle.c")
+
+STATUS = {0: "OK", 1: "TOO_MUCH_WORK", 2: "CONV_FAIL", 3: "ERR_FAIL", 4: "NONFINITE", 5: "SINGULAR"}
+
+
+def build(src: str = SRC_PATH, out: str = LIB_PATH, extra_flags=()) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", *extra_flags,
+           "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+class _Mech(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_reactions", ctypes.c_int32),
+                ("rxn_type", ctypes.c_void_p), ("reac_ptr", ctypes.c_void_p),
+                ("reac_idx", ctypes.c_void_p), ("prod_ptr", ctypes.c_void_p),
+                ("prod_idx", ctypes.c_void_p), ("prod_yield", ctypes.c_void_p),
+                ("A", ctypes.c_void_p), ("theta", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("eta_newton", ctypes.c_double), ("safety", ctypes.c_double),
+                ("fac_min", ctypes.c_double), ("fac_max", ctypes.c_double),
+                ("fac_newton_fail", ctypes.c_double), ("h_min_rel", ctypes.c_double),
+                ("max_order", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32)]
+
+
+STATS_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_fails", np.int32),
+                        ("newton_iters", np.int32), ("f_evals", np.int32), ("jac_evals", np.int32),
+                        ("lu_count", np.int32), ("order", np.int32),
+                        ("h_last", np.float64), ("y_min", np.float64)])
+
+
+def default_opts(rtol=1e-8, atol=1.0, **kw) -> Opts:
+    """Solver constants: rtol 1e-8; atol 1 molecule cm^-3 (use ~1e-14 for O(1) tests)."""
+    o = Opts(rtol=rtol, atol=atol, eta_newton=0.03, safety=0.9, fac_min=0.2, fac_max=10.0,
+             fac_newton_fail=0.5, h_min_rel=1e-30, max_order=5, max_newton=4, max_steps=100000)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Oracle:
+    """ctypes view of liboracle.so bound to one mechanism."""
+
+    def __init__(self, mech, lib_path: str = LIB_PATH):
+        if not os.path.exists(lib_path):
+            build(out=lib_path)
+        self.lib = ctypes.CDLL(lib_path)
+        self.mech = mech
+        self._keep = [np.ascontiguousarray(a, dtype=dt) for a, dt in (
+            (mech.rxn_type, np.int32), (mech.reac_ptr, np.int32), (mech.reac_idx, np.int32),
+            (mech.prod_ptr, np.int32), (mech.prod_idx, np.int32), (mech.prod_yield, np.float64),
+            (mech.A, np.float64), (mech.theta, np.float64))]
+        p = [a.ctypes.data for a in self._keep]
+        self._m = _Mech(mech.n_species, mech.n_reactions, *p)
+        i64, vp, dbl = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+        L = self.lib
+        L.orc_rate_constants.argtypes = [vp, i64, vp, vp, vp]
+        L.orc_deriv.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.orc_jac.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.orc_solve.argtypes = [vp, i64, vp, vp, dbl, vp, vp, vp, ctypes.c_int]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_rescale_differences.argtypes = [ctypes.c_int32, vp, ctypes.c_int32, dbl]
+        L.orc_dense_solve.argtypes = [ctypes.c_int32, vp, vp]
+        L.orc_dense_solve.restype = ctypes.c_int
+
+    @property
+    def N(self):
+        return self.mech.n_species
+
+    @property
+    def R(self):
+        return self.mech.n_reactions
+
+    def _mp(self):
+        return ctypes.addressof(self._m)
+
+    def rate_constants(self, T, jscale) -> np.ndarray:
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        s = np.ascontiguousarray(jscale, dtype=np.float64)
+        C = T.shape[0]
+        k = np.empty((self.R, C))
+        self.lib.orc_rate_constants(self._mp(), C, T.ctypes.data, s.ctypes.data, k.ctypes.data)
+        return k
+
+    def deriv(self, k, y):
+        """f and its absolute-value scale, both [N][C]."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        C = y.shape[1]
+        f = np.empty((self.N, C))
+        s = np.empty((self.N, C))
+        self.lib.orc_deriv(self._mp(), C, k.ctypes.data, y.ctypes.data, f.ctypes.data, s.ctypes.data)
+        return f, s
+
+    def jac(self, k, y):
+        """Dense J and its scale, both [C][N][N] (row = f index, column = y index)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        C = y.shape[1]
+        J = np.empty((C, self.N, self.N))
+        s = np.empty((C, self.N, self.N))
+        self.lib.orc_jac(self._mp(), C, k.ctypes.data, y.ctypes.data, J.ctypes.data, s.ctypes.data)
+        return J, s
+
+    def solve(self, k, y0, dt, opts: Opts | None = None, n_threads: int = 0):
+        """One outer BDF step of length dt for every cell.
+
+        Returns (y [N][C], status [C] int32, stats structured array [C])."""
+        if opts is None:
+            opts = default_opts()
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.array(y0, dtype=np.float64, order="C", copy=True)
+        C = y.shape[1]
+        status = np.empty(C, dtype=np.int32)
+        stats = np.zeros(C, dtype=STATS_DTYPE)
+        self.lib.orc_solve(self._mp(), C, k.ctypes.data, y.ctypes.data, float(dt),
+                           ctypes.addressof(opts), status.ctypes.data, stats.ctypes.data,
+                           int(n_threads))
+        return y, status, stats
+
+    def rescale_differences(self, D, order, rho):
+        """Backward differences D [order+1][N] re-sampled at spacing rho*h."""
+        D = np.array(D, dtype=np.float64, order="C", copy=True)
+        self.lib.orc_rescale_differences(D.shape[1], D.ctypes.data, int(order), float(rho))
+        return D
+
+    def dense_solve(self, a, b):
+        """x with a x = b by Gaussian elimination with partial pivoting (None if singular)."""
+        a = np.array(a, dtype=np.float64, order="C", copy=True)
+        x = np.array(b, dtype=np.float64, order="C", copy=True)
+        if self.lib.orc_dense_solve(a.shape[0], a.ctypes.data, x.ctypes.data):
+            return None
+        return x
+
+    def max_threads(self) -> int:
+        return int(self.lib.orc_max_threads())

@@ -1,0 +1,607 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct CPU reference for the multi-cell
+ * stiff chemistry path (rate constants, f(y), J(y), one BDF outer step).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls this code.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.  It shares no source, header or table with the HIP
+ * library: it reads the mechanism as plain arrays and computes everything
+ * from the definitions, cell by cell, in double precision.
+ *
+ * What it computes (paper, Section 2 "Background"):
+ *   reaction   c_1 y_1 + ... + c_m y_m -> c_{m+1} y_{m+1} + ... + c_n y_n
+ *   tendency   (dy_i/dt)_j = -c_i r_j for reactants, +c_i r_j for products
+ *   derivative f_i = sum_j (dy_i/dt)_j
+ * Multi-cells (Section 3): every cell k has its own y_ik and f_ik and cells do
+ * not interact, so the Jacobian is block-diagonal and each cell is solved on
+ * its own.
+ *
+ * Readings where the paper is silent:
+ *   - r_j is mass action, r_j = k_j * prod over reactant slots of y_s (a
+ *     repeated reactant index is a stoichiometric multiplicity).
+ *   - k_j = A_j exp(-theta_j / T) for thermal (Arrhenius, theta = Ea/R in K),
+ *     k_j = A_j * s for photolysis (A_j is the J-rate, s a per-cell scale).
+ *   - The integrator is a quasi-constant step-size, variable-order (1..5) BDF
+ *     in backward-difference form (Shampine & Reichelt 1997, "The MATLAB ODE
+ *     Suite", kappa = 0), with a simplified Newton iteration on a freshly
+ *     evaluated Jacobian at every step attempt, the Hairer-Norsett-Wanner
+ *     starting step size, and exact landing on the end of the outer step.
+ *     The constants are inputs (orc_opts).
+ *   - Linear systems are solved by dense Gaussian elimination with partial
+ *     pivoting (a deliberately different algorithm from a sparse
+ *     static-pivot factorisation).
+ *
+ * Layout of batch arrays: [entity][n_cells], cell index fastest.
+ *
+ * Parity pins (tests): finite-difference and homogeneity checks of J against
+ * f, atom-balance conservation, hand-derived special cases, closed-form
+ * solutions of small mechanisms, scipy.linalg.expm for linear mechanisms and
+ * an independent implicit Runge-Kutta integrator (scipy Radau) on sampled
+ * cells.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t n_species, n_reactions;
+    const int32_t *rxn_type;             /* [R] 0 thermal, 1 photolysis */
+    const int32_t *reac_ptr, *reac_idx;  /* CSR over reactant slots */
+    const int32_t *prod_ptr, *prod_idx;  /* CSR over products */
+    const double *prod_yield;            /* [nprod] */
+    const double *A, *theta;             /* [R] */
+} orc_mech;
+
+typedef struct {
+    double rtol, atol;        /* weights w_i = 1 / (rtol |y_i| + atol) */
+    double eta_newton;        /* Newton convergence: rho/(1-rho)*|dy| < eta */
+    double safety;            /* step-size safety factor */
+    double fac_min, fac_max;  /* bounds of the step-size change factor */
+    double fac_newton_fail;   /* step-size factor after a Newton failure */
+    double h_min_rel;         /* failure once h < h_min_rel * dt or t + h == t */
+    int32_t max_order;        /* 1..5 */
+    int32_t max_newton;       /* Newton iterations per attempt */
+    int32_t max_steps;        /* step attempts per outer step */
+} orc_opts;
+
+typedef struct {
+    int32_t steps, rejects, newton_fails, newton_iters, f_evals, jac_evals, lu_count, order;
+    double h_last, y_min;
+} orc_stats;
+
+enum { ORC_OK = 0, ORC_TOO_MUCH_WORK = 1, ORC_CONV_FAIL = 2, ORC_ERR_FAIL = 3,
+       ORC_NONFINITE = 4, ORC_SINGULAR = 5 };
+
+#define ORC_MAXORD 5
+
+/* ------------------------------------------------------------------ rates */
+
+/* Rate constant of reaction j in a cell at temperature T with photolysis scale s. */
+static double rate_constant(const orc_mech *m, int j, double T, double s)
+{
+    if (m->rxn_type[j] == 1)
+        return m->A[j] * s;
+    return m->A[j] * exp(-m->theta[j] / T);
+}
+
+void orc_rate_constants(const orc_mech *m, int64_t n_cells, const double *T,
+                        const double *jscale, double *k)
+{
+    for (int j = 0; j < m->n_reactions; ++j)
+        for (int64_t c = 0; c < n_cells; ++c)
+            k[(int64_t)j * n_cells + c] = rate_constant(m, j, T[c], jscale[c]);
+}
+
+/* ------------------------------------------------------- one cell: f and J */
+
+/* Reaction rate r_j = k_j * prod_{reactant slots} y_s. */
+static double reaction_rate(const orc_mech *m, int j, double kj, const double *y)
+{
+    double r = kj;
+    for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p)
+        r *= y[m->reac_idx[p]];
+    return r;
+}
+
+/* f_i = sum_j nu_ij r_j, with nu_ij = (yield as product) - (count as reactant).
+ * fscale_i = sum over the same contributions of their absolute values. */
+static void cell_deriv(const orc_mech *m, const double *kc, const double *y,
+                       double *f, double *fscale)
+{
+    const int N = m->n_species;
+    for (int i = 0; i < N; ++i) {
+        f[i] = 0.0;
+        if (fscale) fscale[i] = 0.0;
+    }
+    for (int j = 0; j < m->n_reactions; ++j) {
+        const double r = reaction_rate(m, j, kc[j], y);
+        for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p) {
+            f[m->reac_idx[p]] -= r;
+            if (fscale) fscale[m->reac_idx[p]] += fabs(r);
+        }
+        for (int p = m->prod_ptr[j]; p < m->prod_ptr[j + 1]; ++p) {
+            f[m->prod_idx[p]] += m->prod_yield[p] * r;
+            if (fscale) fscale[m->prod_idx[p]] += fabs(m->prod_yield[p] * r);
+        }
+    }
+}
+
+/* Dense J[i*N + s] = d f_i / d y_s.  For reaction j and reactant slot l
+ * (species s = reac[l]) the partial of the rate product with respect to that
+ * slot is k_j times the product of the other slots; summing over the slots
+ * that hold s gives d r_j / d y_s (so 2A contributes 2 k y_A).
+ * Jscale accumulates absolute values of the same contributions. */
+static void cell_jac(const orc_mech *m, const double *kc, const double *y,
+                     double *J, double *Jscale)
+{
+    const int N = m->n_species;
+    memset(J, 0, sizeof(double) * (size_t)N * N);
+    if (Jscale) memset(Jscale, 0, sizeof(double) * (size_t)N * N);
+    for (int j = 0; j < m->n_reactions; ++j) {
+        const int b = m->reac_ptr[j], e = m->reac_ptr[j + 1];
+        for (int l = b; l < e; ++l) {
+            double part = kc[j];
+            for (int q = b; q < e; ++q)
+                if (q != l) part *= y[m->reac_idx[q]];
+            const int s = m->reac_idx[l];
+            for (int q = b; q < e; ++q) {
+                J[(size_t)m->reac_idx[q] * N + s] -= part;
+                if (Jscale) Jscale[(size_t)m->reac_idx[q] * N + s] += fabs(part);
+            }
+            for (int q = m->prod_ptr[j]; q < m->prod_ptr[j + 1]; ++q) {
+                J[(size_t)m->prod_idx[q] * N + s] += m->prod_yield[q] * part;
+                if (Jscale) Jscale[(size_t)m->prod_idx[q] * N + s] += fabs(m->prod_yield[q] * part);
+            }
+        }
+    }
+}
+
+/* ----------------------------------------------------------- batch f and J */
+
+static void gather_cell(const double *src, int n, int64_t n_cells, int64_t c, double *dst)
+{
+    for (int i = 0; i < n; ++i)
+        dst[i] = src[(int64_t)i * n_cells + c];
+}
+
+static void scatter_cell(const double *src, int n, int64_t n_cells, int64_t c, double *dst)
+{
+    for (int i = 0; i < n; ++i)
+        dst[(int64_t)i * n_cells + c] = src[i];
+}
+
+/* f and its scale for every cell.  k: [R][C], y, f, fscale: [N][C]. */
+void orc_deriv(const orc_mech *m, int64_t n_cells, const double *k, const double *y,
+               double *f, double *fscale)
+{
+    const int N = m->n_species, R = m->n_reactions;
+    double *kc = malloc(sizeof(double) * R), *yc = malloc(sizeof(double) * N);
+    double *fc = malloc(sizeof(double) * N), *sc = malloc(sizeof(double) * N);
+    for (int64_t c = 0; c < n_cells; ++c) {
+        gather_cell(k, R, n_cells, c, kc);
+        gather_cell(y, N, n_cells, c, yc);
+        cell_deriv(m, kc, yc, fc, sc);
+        scatter_cell(fc, N, n_cells, c, f);
+        if (fscale) scatter_cell(sc, N, n_cells, c, fscale);
+    }
+    free(kc); free(yc); free(fc); free(sc);
+}
+
+/* Dense Jacobian of every cell: J, Jscale: [C][N][N] (row i, column s). */
+void orc_jac(const orc_mech *m, int64_t n_cells, const double *k, const double *y,
+             double *J, double *Jscale)
+{
+    const int N = m->n_species, R = m->n_reactions;
+    double *kc = malloc(sizeof(double) * R), *yc = malloc(sizeof(double) * N);
+    for (int64_t c = 0; c < n_cells; ++c) {
+        gather_cell(k, R, n_cells, c, kc);
+        gather_cell(y, N, n_cells, c, yc);
+        cell_jac(m, kc, yc, J + (size_t)c * N * N, Jscale ? Jscale + (size_t)c * N * N : NULL);
+    }
+    free(kc); free(yc);
+}
+
+/* -------------------------------------------- dense LU with partial pivoting */
+
+/* In-place LU of the n x n row-major matrix a, row interchanges in piv.
+ * Returns 0 on success, 1 if a pivot is zero or not finite. */
+static int lu_factor(int n, double *a, int *piv)
+{
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(a[(size_t)k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            const double v = fabs(a[(size_t)i * n + k]);
+            if (v > best) { best = v; p = i; }
+        }
+        piv[k] = p;
+        if (!(best > 0.0) || !isfinite(best))
+            return 1;
+        if (p != k)
+            for (int j = 0; j < n; ++j) {
+                const double t = a[(size_t)k * n + j];
+                a[(size_t)k * n + j] = a[(size_t)p * n + j];
+                a[(size_t)p * n + j] = t;
+            }
+        const double piv_val = a[(size_t)k * n + k];
+        for (int i = k + 1; i < n; ++i) {
+            const double l = a[(size_t)i * n + k] / piv_val;
+            a[(size_t)i * n + k] = l;
+            if (l != 0.0)
+                for (int j = k + 1; j < n; ++j)
+                    a[(size_t)i * n + j] -= l * a[(size_t)k * n + j];
+        }
+    }
+    return 0;
+}
+
+/* Solve (LU) x = b in place, using the factors and interchanges of lu_factor. */
+static void lu_solve(int n, const double *a, const int *piv, double *b)
+{
+    for (int k = 0; k < n; ++k)
+        if (piv[k] != k) {
+            const double t = b[k];
+            b[k] = b[piv[k]];
+            b[piv[k]] = t;
+        }
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int j = 0; j < i; ++j)
+            s -= a[(size_t)i * n + j] * b[j];
+        b[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < n; ++j)
+            s -= a[(size_t)i * n + j] * b[j];
+        b[i] = s / a[(size_t)i * n + i];
+    }
+}
+
+/* ------------------------------------------------------------ BDF helpers */
+
+/* Weighted root-mean-square norm sqrt(mean((v_i w_i)^2)). */
+static double wrms(int n, const double *v, const double *w)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double t = v[i] * w[i];
+        s += t * t;
+    }
+    return sqrt(s / n);
+}
+
+/* gamma_j = sum_{i=1..j} 1/i, gamma_0 = 0 (BDF coefficients for kappa = 0). */
+static double bdf_gamma(int j)
+{
+    double g = 0.0;
+    for (int i = 1; i <= j; ++i)
+        g += 1.0 / i;
+    return g;
+}
+
+/* Re-sample the backward differences D[0..order] of the interpolating
+ * polynomial from spacing h to spacing rho*h.  With
+ *   R_ij(rho) = prod_{l=1..i} (l - 1 - rho*j) / l,  i, j = 0..order
+ * the values at the new points are R(rho)^T D, the differences of values at
+ * unit spacing are obtained with U = R(1) (an involution), so the new
+ * differences are (R(rho) U)^T D. */
+static void rescale_differences(int N, double *D, int order, double rho)
+{
+    double R[ORC_MAXORD + 1][ORC_MAXORD + 1], U[ORC_MAXORD + 1][ORC_MAXORD + 1];
+    double RU[ORC_MAXORD + 1][ORC_MAXORD + 1];
+    double tmp[ORC_MAXORD + 1];
+    const int n = order + 1;
+    for (int j = 0; j < n; ++j) {
+        R[0][j] = 1.0;
+        U[0][j] = 1.0;
+        for (int i = 1; i < n; ++i) {
+            R[i][j] = R[i - 1][j] * ((i - 1) - rho * j) / i;
+            U[i][j] = U[i - 1][j] * ((double)(i - 1) - (double)j) / i;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < n; ++l)
+                s += R[i][l] * U[l][j];
+            RU[i][j] = s;
+        }
+    for (int s = 0; s < N; ++s) {
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j)
+                acc += RU[j][i] * D[(size_t)j * N + s];
+            tmp[i] = acc;
+        }
+        for (int i = 0; i < n; ++i)
+            D[(size_t)i * N + s] = tmp[i];
+    }
+}
+
+static int all_finite(int n, const double *v)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+/* --------------------------------------------------------- BDF, one cell */
+
+typedef struct {
+    double *D, *f, *w, *ypred, *psi, *d, *ycur, *rhs, *J, *tmp;
+    int *piv;
+} orc_work;
+
+static void work_alloc(orc_work *wk, int N)
+{
+    wk->D = calloc((size_t)(ORC_MAXORD + 3) * N, sizeof(double));
+    wk->f = malloc(sizeof(double) * N);
+    wk->w = malloc(sizeof(double) * N);
+    wk->ypred = malloc(sizeof(double) * N);
+    wk->psi = malloc(sizeof(double) * N);
+    wk->d = malloc(sizeof(double) * N);
+    wk->ycur = malloc(sizeof(double) * N);
+    wk->rhs = malloc(sizeof(double) * N);
+    wk->tmp = malloc(sizeof(double) * N);
+    wk->J = malloc(sizeof(double) * (size_t)N * N);
+    wk->piv = malloc(sizeof(int) * N);
+}
+
+static void work_free(orc_work *wk)
+{
+    free(wk->D); free(wk->f); free(wk->w); free(wk->ypred); free(wk->psi);
+    free(wk->d); free(wk->ycur); free(wk->rhs); free(wk->tmp); free(wk->J); free(wk->piv);
+}
+
+/* Integrate y' = f(y) of one cell from t = 0 to t = dt; y is overwritten
+ * with y(dt).  Returns an ORC_* status. */
+static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
+                      const orc_opts *o, orc_stats *st, orc_work *wk)
+{
+    const int N = m->n_species;
+    const int maxord = o->max_order < 1 ? 1 : (o->max_order > ORC_MAXORD ? ORC_MAXORD : o->max_order);
+    double *D = wk->D;
+    memset(st, 0, sizeof(*st));
+    memset(D, 0, sizeof(double) * (size_t)(ORC_MAXORD + 3) * N);
+
+    /* starting step size (Hairer, Norsett & Wanner, Vol. I, Sec. II.4, p = 1) */
+    cell_deriv(m, kc, y, wk->f, NULL);
+    st->f_evals++;
+    if (!all_finite(N, y) || !all_finite(N, wk->f))
+        return ORC_NONFINITE;
+    for (int i = 0; i < N; ++i)
+        wk->w[i] = 1.0 / (o->rtol * fabs(y[i]) + o->atol);
+    const double d0 = wrms(N, y, wk->w), d1 = wrms(N, wk->f, wk->w);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+    for (int i = 0; i < N; ++i)
+        wk->ycur[i] = y[i] + h0 * wk->f[i];
+    cell_deriv(m, kc, wk->ycur, wk->tmp, NULL);
+    st->f_evals++;
+    for (int i = 0; i < N; ++i)
+        wk->rhs[i] = wk->tmp[i] - wk->f[i];
+    const double d2 = wrms(N, wk->rhs, wk->w) / h0;
+    const double dm = d1 > d2 ? d1 : d2;
+    double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
+    double h = fmin(100.0 * h0, fmin(h1, dt));
+    if (!(h > 0.0) || !isfinite(h))
+        return ORC_NONFINITE;
+
+    for (int i = 0; i < N; ++i) {
+        D[i] = y[i];
+        D[(size_t)N + i] = h * wk->f[i];
+    }
+    int order = 1, n_equal = 0, attempts = 0;
+    double t = 0.0;
+
+    while (t < dt) {
+        /* one accepted step: attempts until the error test passes */
+        int accepted = 0, landing = 0;
+        double err_norm = 0.0;
+        while (!accepted) {
+            if (attempts >= o->max_steps) {
+                for (int i = 0; i < N; ++i) y[i] = D[i];
+                st->order = order; st->h_last = h;
+                return ORC_TOO_MUCH_WORK;
+            }
+            attempts++;
+            landing = 0;
+            if (h >= dt - t) {
+                const double hn = dt - t;
+                rescale_differences(N, D, order, hn / h);
+                h = hn;
+                n_equal = 0;
+                landing = 1;
+            }
+            const double gk = bdf_gamma(order);
+            const double c = h / gk;
+            for (int i = 0; i < N; ++i) {
+                double yp = 0.0, ps = 0.0;
+                for (int j = 0; j <= order; ++j)
+                    yp += D[(size_t)j * N + i];
+                for (int j = 1; j <= order; ++j)
+                    ps += bdf_gamma(j) * D[(size_t)j * N + i];
+                wk->ypred[i] = yp;
+                wk->psi[i] = ps / gk;
+                wk->w[i] = 1.0 / (o->rtol * fabs(D[i]) + o->atol);
+                wk->d[i] = 0.0;
+            }
+            /* Newton matrix M = I - c J(ypred) */
+            cell_jac(m, kc, wk->ypred, wk->J, NULL);
+            st->jac_evals++;
+            for (size_t q = 0; q < (size_t)N * N; ++q)
+                wk->J[q] = -c * wk->J[q];
+            for (int i = 0; i < N; ++i)
+                wk->J[(size_t)i * N + i] += 1.0;
+            st->lu_count++;
+            int converged = 0, singular = lu_factor(N, wk->J, wk->piv);
+            if (!singular) {
+                double nrm_old = 0.0;
+                for (int it = 0; it < o->max_newton; ++it) {
+                    for (int i = 0; i < N; ++i)
+                        wk->ycur[i] = wk->ypred[i] + wk->d[i];
+                    cell_deriv(m, kc, wk->ycur, wk->f, NULL);
+                    st->f_evals++;
+                    if (!all_finite(N, wk->f)) break;
+                    for (int i = 0; i < N; ++i)
+                        wk->rhs[i] = c * wk->f[i] - wk->psi[i] - wk->d[i];
+                    lu_solve(N, wk->J, wk->piv, wk->rhs);
+                    st->newton_iters++;
+                    const double nrm = wrms(N, wk->rhs, wk->w);
+                    if (!isfinite(nrm)) break;
+                    double rho = 0.0;
+                    if (it >= 1) {
+                        rho = nrm / nrm_old;
+                        if (rho >= 1.0) break;
+                    }
+                    for (int i = 0; i < N; ++i)
+                        wk->d[i] += wk->rhs[i];
+                    if (nrm == 0.0 || (it >= 1 && rho / (1.0 - rho) * nrm < o->eta_newton)) {
+                        converged = 1;
+                        break;
+                    }
+                    nrm_old = nrm;
+                }
+            }
+            if (!converged) {
+                st->newton_fails++;
+                rescale_differences(N, D, order, o->fac_newton_fail);
+                h *= o->fac_newton_fail;
+                n_equal = 0;
+                if (h < o->h_min_rel * dt || t + h == t) {
+                    for (int i = 0; i < N; ++i) y[i] = D[i];
+                    st->order = order; st->h_last = h;
+                    return singular ? ORC_SINGULAR : ORC_CONV_FAIL;
+                }
+                continue;
+            }
+            /* local error estimate: d / (order + 1) */
+            err_norm = wrms(N, wk->d, wk->w) / (order + 1);
+            if (err_norm > 1.0) {
+                st->rejects++;
+                double fac = o->safety * pow(err_norm, -1.0 / (order + 1));
+                if (fac < o->fac_min) fac = o->fac_min;
+                rescale_differences(N, D, order, fac);
+                h *= fac;
+                n_equal = 0;
+                if (h < o->h_min_rel * dt || t + h == t) {
+                    for (int i = 0; i < N; ++i) y[i] = D[i];
+                    st->order = order; st->h_last = h;
+                    return ORC_ERR_FAIL;
+                }
+                continue;
+            }
+            accepted = 1;
+        }
+        /* accept: t advances, differences are updated */
+        t = landing ? dt : t + h;
+        st->steps++;
+        for (int i = 0; i < N; ++i) {
+            D[(size_t)(order + 2) * N + i] = wk->d[i] - D[(size_t)(order + 1) * N + i];
+            D[(size_t)(order + 1) * N + i] = wk->d[i];
+        }
+        for (int j = order; j >= 0; --j)
+            for (int i = 0; i < N; ++i)
+                D[(size_t)j * N + i] += D[(size_t)(j + 1) * N + i];
+        n_equal++;
+        if (t >= dt)
+            break;
+        if (n_equal < order + 1)
+            continue;
+        /* order and step-size selection after order+1 steps at constant h */
+        const double e_cur = err_norm;
+        const double e_low = order > 1 ? wrms(N, D + (size_t)order * N, wk->w) / order : INFINITY;
+        const double e_high = order < maxord ? wrms(N, D + (size_t)(order + 2) * N, wk->w) / (order + 2) : INFINITY;
+        const double r_cur = pow(e_cur, -1.0 / (order + 1));
+        const double r_low = order > 1 ? pow(e_low, -1.0 / order) : 0.0;
+        const double r_high = order < maxord ? pow(e_high, -1.0 / (order + 2)) : 0.0;
+        int new_order = order;
+        double best = r_cur;
+        if (r_low > best) { best = r_low; new_order = order - 1; }
+        if (r_high > best) { best = r_high; new_order = order + 1; }
+        double fac = o->safety * best;
+        if (fac > o->fac_max) fac = o->fac_max;
+        order = new_order;
+        rescale_differences(N, D, order, fac);
+        h *= fac;
+        n_equal = 0;
+    }
+    double ymin = INFINITY;
+    for (int i = 0; i < N; ++i) {
+        y[i] = D[i];
+        if (D[i] < ymin) ymin = D[i];
+    }
+    st->order = order;
+    st->h_last = h;
+    st->y_min = ymin;
+    return all_finite(N, y) ? ORC_OK : ORC_NONFINITE;
+}
+
+/* One outer step of length dt for every cell.  k: [R][C]; y: [N][C] in/out;
+ * status: [C]; stats: [C] (may be NULL).  n_threads <= 0: OpenMP default.
+ * Returns the number of cells whose status is not ORC_OK. */
+int orc_solve(const orc_mech *m, int64_t n_cells, const double *k, double *y, double dt,
+              const orc_opts *o, int32_t *status, orc_stats *stats, int n_threads)
+{
+    const int N = m->n_species, R = m->n_reactions;
+    int failed = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel reduction(+:failed)
+    {
+        orc_work wk;
+        work_alloc(&wk, N);
+        double *kc = malloc(sizeof(double) * R), *yc = malloc(sizeof(double) * N);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t c = 0; c < n_cells; ++c) {
+            orc_stats st;
+            gather_cell(k, R, n_cells, c, kc);
+            gather_cell(y, N, n_cells, c, yc);
+            const int s = cell_solve(m, kc, yc, dt, o, &st, &wk);
+            scatter_cell(yc, N, n_cells, c, y);
+            status[c] = s;
+            if (stats) stats[c] = st;
+            failed += s != ORC_OK;
+        }
+        free(kc); free(yc);
+        work_free(&wk);
+    }
+    return failed;
+}
+
+/* Number of OpenMP threads a parallel region would use. */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------- pieces exported for pinning */
+
+/* Re-sample the backward differences D[(order+1)][N] to spacing rho*h. */
+void orc_rescale_differences(int32_t N, double *D, int32_t order, double rho)
+{
+    rescale_differences(N, D, order, rho);
+}
+
+/* Solve the dense n x n row-major system a x = b (a is overwritten by its
+ * factors, b by x).  Returns 0, or 1 if a pivot is zero or not finite. */
+int orc_dense_solve(int32_t n, double *a, double *b)
+{
+    int *piv = malloc(sizeof(int) * (size_t)n);
+    const int s = lu_factor(n, a, piv);
+    if (!s)
+        lu_solve(n, a, piv, b);
+    free(piv);
+    return s;
+}

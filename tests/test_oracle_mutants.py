@@ -1,0 +1,187 @@
+"""The pins are strong enough: plausible mistakes planted in a copy of the
+oracle's source (compiled on the CPU into a temporary library) each make at
+least one pin fail.  The oracle itself is never modified."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as oracle_pkg
+from paper_2501_00011_amd import synth
+
+MUTANTS = {
+    "product_sign": ("f[m->prod_idx[p]] += m->prod_yield[p] * r;",
+                     "f[m->prod_idx[p]] -= m->prod_yield[p] * r;"),
+    "jac_transposed": ("J[(size_t)m->prod_idx[q] * N + s] += m->prod_yield[q] * part;",
+                       "J[(size_t)s * N + m->prod_idx[q]] += m->prod_yield[q] * part;"),
+    "jac_multiplicity_dropped": ("if (q != l) part *= y[m->reac_idx[q]];",
+                                 "if (m->reac_idx[q] != m->reac_idx[l]) part *= y[m->reac_idx[q]];"),
+    "jac_reactant_row_dropped": ("J[(size_t)m->reac_idx[q] * N + s] -= part;",
+                                 "if (q == l) J[(size_t)m->reac_idx[q] * N + s] -= part;"),
+    "arrhenius_sign": ("return m->A[j] * exp(-m->theta[j] / T);",
+                       "return m->A[j] * exp(m->theta[j] / T);"),
+    "bdf_psi_not_scaled": ("wk->psi[i] = ps / gk;", "wk->psi[i] = ps;"),
+    "bdf_gamma_index": ("g += 1.0 / i;", "g += 1.0 / (i + 1);"),
+    "bdf_rescale_sign": ("R[i][j] = R[i - 1][j] * ((i - 1) - rho * j) / i;",
+                         "R[i][j] = R[i - 1][j] * ((i - 1) + rho * j) / i;"),
+    "newton_psi_sign": ("wk->rhs[i] = c * wk->f[i] - wk->psi[i] - wk->d[i];",
+                        "wk->rhs[i] = c * wk->f[i] + wk->psi[i] - wk->d[i];"),
+    "newton_matrix_sign": ("wk->J[q] = -c * wk->J[q];", "wk->J[q] = c * wk->J[q];"),
+    "lu_back_substitution": ("b[i] = s / a[(size_t)i * n + i];", "b[i] = s;"),
+    "difference_update": ("D[(size_t)j * N + i] += D[(size_t)(j + 1) * N + i];",
+                          "D[(size_t)j * N + i] -= D[(size_t)(j + 1) * N + i];"),
+    "error_constant": ("err_norm = wrms(N, wk->d, wk->w) / (order + 1);",
+                       "err_norm = wrms(N, wk->d, wk->w) / (order + 1) * 1e-3;"),
+}
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "handworked_fj.json")
+
+
+def _build_mutant(tmp_path, name):
+    src = open(oracle_pkg.SRC_PATH).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / f"lib{name}.so"
+    oracle_pkg.build(src=str(path), out=str(lib))
+    return str(lib)
+
+
+def _pin_handworked(lib):
+    g = json.load(open(GOLDEN))
+    for case in g["cases"]:
+        rx = [(r["reac"], [tuple(p) for p in r["prod"]], r["k"], 0.0, 0) for r in case["reactions"]]
+        m = synth.mechanism_from_lists(case["n_species"], rx)
+        o = oracle_pkg.Oracle(m, lib_path=lib)
+        k = np.array([[r["k"]] for r in case["reactions"]])
+        y = np.array(case["y"])[:, None]
+        if not np.allclose(o.deriv(k, y)[0][:, 0], case["f"], rtol=1e-15, atol=0):
+            return False
+        if not np.allclose(o.jac(k, y)[0][0], case["J"], rtol=1e-15, atol=0):
+            return False
+    th = g["rate_constants"]["thermal"]
+    m = synth.mechanism_from_lists(2, [([0], [(1, 1.0)], th["A"], th["theta"], 0)])
+    k = oracle_pkg.Oracle(m, lib_path=lib).rate_constants(np.array([th["T"]]), np.array([1.0]))
+    return abs(k[0, 0] - th["k"]) <= 4e-16 * th["k"]
+
+
+def _pin_closed_forms(lib):
+    T = 60.0
+    cases = []
+    # A -> B
+    m = synth.mechanism_from_lists(2, [([0], [(1, 1.0)], 1.0, 0.0, 0)])
+    k = np.array([[0.3 / T, 4.0 / T]])
+    y0 = np.array([[1.0, 1.0], [0.0, 0.0]])
+    A = np.exp(-k[0] * T)
+    cases.append((m, k, y0, np.stack([A, 1 - A])))
+    # A + B -> C
+    m = synth.mechanism_from_lists(3, [([0, 1], [(2, 1.0)], 1.0, 0.0, 0)])
+    A0, B0 = 0.6, 1.1
+    d = B0 - A0
+    kk = np.array([[1.0 / (T * d), 4.0 / (T * d)]])
+    y0 = np.array([[A0, A0], [B0, B0], [0.0, 0.0]])
+    A = A0 * d / (B0 * np.exp(kk[0] * d * T) - A0)
+    cases.append((m, kk, y0, np.stack([A, A + d, A0 - A])))
+    for m, k, y0, exact in cases:
+        o = oracle_pkg.Oracle(m, lib_path=lib)
+        y, st, _ = o.solve(k, y0, T, oracle_pkg.default_opts(rtol=1e-8, atol=1e-14))
+        if np.any(st != 0):
+            return False
+        if not np.all(np.abs(y - exact) <= 1e-6 * np.abs(exact) + 1e-12):
+            return False
+    return True
+
+
+def _pin_fd_homogeneity_balance(lib):
+    m = synth.mech_small_thermal()
+    o = oracle_pkg.Oracle(m, lib_path=lib)
+    c = synth.make_cells(m, 2, seed=3)
+    k = o.rate_constants(c.T, c.jscale)
+    J, Js = o.jac(k, c.y0)
+    f, fs = o.deriv(k, c.y0)
+    a = m.composition.astype(np.float64)
+    if np.any(np.abs(a.T @ f) > 1e-12 * (a.T @ fs)):
+        return False
+    y = c.y0[:, :1]
+    kk = k[:, :1]
+    hs = 1e-6 * np.abs(y[:, 0])
+    for s in range(m.n_species):
+        yp, ym = y.copy(), y.copy()
+        yp[s] += hs[s]
+        ym[s] -= hs[s]
+        col = (o.deriv(kk, yp)[0][:, 0] - o.deriv(kk, ym)[0][:, 0]) / (2 * hs[s])
+        if np.any(np.abs(J[0][:, s] - col) > 1e-6 * Js[0][:, s] + 1e-14 * fs[:, 0] / hs[s]):
+            return False
+    return True
+
+
+def _pin_radau_small(lib):
+    from scipy.integrate import solve_ivp
+    m, c, dt = synth.workload("small10")
+    o = oracle_pkg.Oracle(m, lib_path=lib)
+    sel = [0, 5]
+    k = o.rate_constants(c.T[sel], c.jscale[sel])
+    y, st, _ = o.solve(k, c.y0[:, sel], dt)
+    if np.any(st != 0) or not np.all(np.isfinite(y)):
+        return False
+    good = oracle_pkg.Oracle(m)  # the unmodified oracle supplies f and J to Radau
+    for i in range(len(sel)):
+        kk = k[:, i:i + 1]
+        ref = solve_ivp(lambda t, v: good.deriv(kk, v[:, None])[0][:, 0], (0.0, dt), c.y0[:, sel[i]],
+                        method="Radau", rtol=1e-12, atol=1e-4,
+                        jac=lambda t, v: good.jac(kk, v[:, None])[0][0]).y[:, -1]
+        if np.any(np.abs(y[:, i] - ref) > 5e-6 * np.abs(ref) + 1e2):
+            return False
+    return True
+
+
+def _pin_pieces(lib):
+    """Difference re-sampling, the dense solve and the Newton count of a linear problem."""
+    o = oracle_pkg.Oracle(synth.mechanism_from_lists(3, [([0], [(1, 1.0)], 1.0, 0.0, 0)]), lib_path=lib)
+    coef = np.array([[0.5, -1.0, 2.0, 0.25], [1.0, 0.0, -3.0, 1.5], [0.1, 0.2, 0.3, 0.4]])
+    h, tn, order, rho = 0.7, 2.0, 3, 2.5
+
+    def diffs(step):
+        v = np.stack([np.polyval(c, tn - step * np.arange(order + 1)) for c in coef], axis=1)
+        return np.array([sum((-1) ** r * math.comb(j, r) * v[r] for r in range(j + 1))
+                         for j in range(order + 1)])
+
+    if not np.allclose(o.rescale_differences(diffs(h), order, rho), diffs(rho * h), rtol=1e-11, atol=1e-10):
+        return False
+    a = np.array([[0.0, 2.0, 1.0], [1.0, 1.0, 0.0], [3.0, 0.0, 4.0]])
+    b = np.array([1.0, 2.0, 3.0])
+    x = o.dense_solve(a, b)
+    if x is None or not np.allclose(x, np.linalg.solve(a, b), rtol=1e-13):
+        return False
+    m = synth.mechanism_from_lists(3, [([0], [(1, 1.0)], 1.0, 0.0, 0), ([1], [(2, 1.0)], 1.0, 0.0, 0)])
+    o = oracle_pkg.Oracle(m, lib_path=lib)
+    _, st, s = o.solve(np.array([[0.3], [40.0]]), np.array([[1.0], [0.5], [0.0]]), 60.0,
+                       oracle_pkg.default_opts(rtol=1e-8, atol=1e-14))
+    return bool(st[0] == 0 and s["newton_fails"][0] == 0 and s["newton_iters"][0] == 2 * s["lu_count"][0])
+
+
+PINS = [_pin_handworked, _pin_fd_homogeneity_balance, _pin_pieces, _pin_closed_forms, _pin_radau_small]
+
+
+def test_unmodified_oracle_passes_every_pin():
+    for pin in PINS:
+        assert pin(oracle_pkg.LIB_PATH), pin.__name__
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    lib = _build_mutant(tmp_path, name)
+    results = {}
+    for pin in PINS:
+        try:
+            with np.errstate(all="ignore"):
+                results[pin.__name__] = bool(pin(lib))
+        except (FloatingPointError, ValueError, np.linalg.LinAlgError):
+            results[pin.__name__] = False
+        if not results[pin.__name__]:
+            break
+    assert not all(results.values()), f"mutant {name} passed every pin: {results}"
+    assert math.isfinite(len(results))
