@@ -1,0 +1,178 @@
+"""Benchmark: one step = the whole hot path over one batch of synthetic cells.
+
+Step (all on cuda:0, inputs resident in HBM):
+  1. rate constants from T, P and the photolysis scale (mcc_cells_bind),
+  2. fused f and sparse J at the initial state (mcc_calc_deriv_jac),
+  3. one 180 s BDF outer step of every cell (mcc_solve_step), restarted from
+     the same initial state each step (a device-to-device copy).
+Workload: 72 species / 156 reactions (47 photolysis, 94 bimolecular,
+15 termolecular), 10,000 cells, T 220-310 K, P 100-1013 hPa, FP64.
+
+Prints one JSON line: cell-timesteps/s with a roofline object for the
+dominant kernel (the BDF solver, FP64 ALU-bound) and for the f+J kernel
+(HBM-bound), and the CPU oracle timed on a bounded sample of the same cells.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="medium10k")
+    ap.add_argument("--cells", type=int, default=None, help="override the number of cells")
+    ap.add_argument("--fj-reps", type=int, default=50, help="extra timed f+J launches for its roofline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    return ap.parse_args()
+
+
+def cpu_baseline(m, c, dt, target_s):
+    """The oracle as it stands, on all host threads it is given, on a bounded
+    sample of the same cells; cell-timesteps/s."""
+    import numpy as np
+    import oracle
+    if not os.path.exists(oracle.LIB_PATH):
+        oracle.build()
+    o = oracle.Oracle(m)
+    threads = o.max_threads()
+    # calibration on one cell per thread, then a sample sized to the target time
+    n0 = min(c.n_cells, threads)
+    sel = np.arange(n0)
+    k = o.rate_constants(c.T[sel], c.jscale[sel])
+    t0 = time.perf_counter()
+    o.solve(k, c.y0[:, sel], dt)
+    per_round = time.perf_counter() - t0
+    n = int(min(c.n_cells, max(n0, threads * max(1, int(target_s / max(per_round, 1e-6))))))
+    sel = np.arange(n)
+    k = o.rate_constants(c.T[sel], c.jscale[sel])
+    t0 = time.perf_counter()
+    _, st, _ = o.solve(k, c.y0[:, sel], dt)
+    wall = time.perf_counter() - t0
+    return {"value": n / wall, "unit": "cell-timesteps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {c.n_cells} cells, one {dt:g} s step each, "
+                      f"{wall:.1f} s wall on {threads} OpenMP threads ({int((st != 0).sum())} failed)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the cells of this workload are independent and this "
+              "build measures one GPU's share; use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2501_00011_amd import mcchem, synth
+
+    m, c, dt = synth.workload(args.workload, args.cells)
+    dev = torch.device("cuda:0")
+    mech = mcchem.Mechanism(m, device=0)
+    C = c.n_cells
+    cells = mcchem.Cells(mech, C)
+    T = torch.from_numpy(c.T).to(dev)
+    P = torch.from_numpy(c.P).to(dev)
+    s = torch.from_numpy(c.jscale).to(dev)
+    y0 = torch.from_numpy(c.y0).to(dev)
+    y = torch.empty_like(y0)
+    f = torch.empty_like(y0)
+    J = torch.empty((mech.nnz, C), dtype=torch.float64, device=dev)
+    status = torch.empty(C, dtype=torch.int32, device=dev)
+    stats = torch.empty((C, mcchem.STATS_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    opts = mcchem.default_opts()
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        cells.bind(T, P, s, stream=stream)
+        cells.deriv_jac(y0, f, J, stream=stream)
+        y.copy_(y0)
+        if ev is not None:
+            ev[0].record(stream)
+        cells.step(y, dt, opts, status, stats, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solve_ms = [a.elapsed_time(b) for a, b in evs]
+
+    st = status.cpu().numpy()
+    sn = mcchem.stats_numpy(stats)
+    oc = mech.op_counts()
+    flops = float(np.sum(sn["f_evals"].astype(np.int64) * oc["deriv_flops"]
+                         + sn["jac_evals"].astype(np.int64) * oc["newton_matrix_flops"]
+                         + sn["lu_count"].astype(np.int64) * oc["lu_flops"]
+                         + sn["newton_iters"].astype(np.int64) * oc["solve_flops"]))
+    solve_s = float(np.mean(solve_ms)) / 1e3
+    achieved_tf = flops / solve_s / 1e12
+
+    # f+J roofline: back-to-back fused launches on the same stream
+    fj_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for _ in range(3):
+        cells.deriv_jac(y0, f, J, stream=stream)
+    fj_ev[0].record(stream)
+    for _ in range(args.fj_reps):
+        cells.deriv_jac(y0, f, J, stream=stream)
+    fj_ev[1].record(stream)
+    torch.cuda.synchronize()
+    fj_s = fj_ev[0].elapsed_time(fj_ev[1]) / 1e3 / max(args.fj_reps, 1)
+    fj_gbs = oc["fj_bytes"] * C / fj_s / 1e9
+
+    result = {
+        "metric": "cell-timesteps/s (FP64, 1e-6 rel vs oracle); f+J evals/s as % HBM peak",
+        "value": C * args.steps / wall,
+        "unit": "cell-timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{m.n_species} species / {m.n_reactions} reactions, {C} cells, "
+                               f"one {dt:g} s BDF step + rate constants + fused f/J per step",
+                   "cells": C, "species": m.n_species, "reactions": m.n_reactions, "dt_s": dt,
+                   "rtol": opts.rtol, "atol": opts.atol},
+        "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
+                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "launch_ms": solve_s * 1e3, "flops_per_launch": flops},
+        "fj_roofline": {"kernel": "fj_kernel (calc_deriv_jac)", "bound": "hbm", "achieved": fj_gbs,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
+                        "traffic": None, "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
+        "solver": {"failed_cells": int((st != 0).sum()),
+                   "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),
+                   "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),
+                   "newton_per_attempt": float(sn["newton_iters"].sum() / max(sn["lu_count"].sum(), 1))},
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(m, c, dt, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * mcc.h -- C ABI of libmcchem: many independent grid cells, each integrating
+ * the same stiff mass-action chemical mechanism, on one AMD Instinct MI355X
+ * (gfx950) GPU in double precision.
+ *
+ * Paper: "Adapting atmospheric chemistry components for efficient GPU
+ * accelerators" (arXiv 2501.00011).
+ *   Section 2 (Background): the state array y holds species concentrations
+ *     and the deriv array f their time derivatives; an ODE solver integrates
+ *     y' = f(t, y) with a sparse Jacobian supplied by the chemistry; a cell
+ *     is an independent volume of atmosphere with its own state.
+ *   Section 2, reaction equations: c_1 y_1 + ... + c_m y_m -> ... + c_n y_n;
+ *     (dy_i/dt)_j = -c_i r_j for reactants and +c_i r_j for products;
+ *     f_i = sum_j (dy_i/dt)_j.
+ *   Section 3 (Implementations): Multi-cells groups the data of all cells in
+ *     one structure, f_ik = sum_j (dy_ik/dt)_j for species i of cell k; the
+ *     reaction data lives in GPU memory from initialisation on; the device
+ *     limits are checked at run time.
+ *   Section 5 (Conclusions): move the Jacobian and the solver onto the GPU and
+ *     move data only at the start and end of the solve -- which is what this
+ *     library does: state stays in device memory across f, J and solver calls.
+ *
+ * Conventions
+ *   Layout.   Per-cell arrays are [entity][ld] in row-major order with the
+ *             cell index fastest (element (e, c) at e*ld + c), ld >= n_cells.
+ *             Species arrays have n_species rows, rate constants n_reactions
+ *             rows, Jacobians nnz rows in the CSR order of mcc_mech_jac_pattern.
+ *   Memory.   Pointers documented as "device" are caller-owned device memory
+ *             (for instance from a PyTorch CUDA/HIP tensor) on the handle's
+ *             device; the library never frees them and keeps no pointer past
+ *             the call.  "host" pointers are ordinary host memory.
+ *   Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *             stream).  Calls that take a stream only enqueue work and return;
+ *             errors inside kernels surface at mcc_sync() or at the next
+ *             synchronising call.  *_create and *_destroy synchronise.
+ *   Errors.   Every call returns an mcc_status; on anything but MCC_OK a
+ *             message is available from mcc_last_error() (thread-local).
+ *             Invalid arguments are rejected before any work is enqueued.
+ *   Threads.  A handle must not be used from two threads at once; distinct
+ *             handles are independent.
+ */
+#ifndef MCC_H
+#define MCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCC_OK = 0,
+    MCC_ERR_INVALID_ARG = 1, /* null pointer, size out of range, bad option */
+    MCC_ERR_MECH = 2,        /* mechanism fails validation or exceeds device limits */
+    MCC_ERR_OOM = 3,         /* device allocation failed */
+    MCC_ERR_DEVICE = 4,      /* HIP runtime error (text in mcc_last_error) */
+    MCC_ERR_STATE = 5,       /* call out of order (e.g. solve before bind) */
+    MCC_ERR_SOLVE = 6        /* reserved: per-cell failures are reported per cell */
+} mcc_status;
+
+/* Per-cell outcome of mcc_solve_step. */
+typedef enum {
+    MCC_CELL_OK = 0,
+    MCC_CELL_TOO_MUCH_WORK = 1, /* max_steps step attempts without reaching dt */
+    MCC_CELL_CONV_FAIL = 2,     /* Newton failures drove h below its minimum */
+    MCC_CELL_ERR_FAIL = 3,      /* error-test failures drove h below its minimum */
+    MCC_CELL_NONFINITE = 4,     /* non-finite state or derivative */
+    MCC_CELL_SINGULAR = 5       /* zero/non-finite pivot drove h below its minimum */
+} mcc_cell_status;
+
+/* Reaction types. */
+enum { MCC_RXN_THERMAL = 0, MCC_RXN_PHOTOLYSIS = 1 };
+
+/* Mechanism description (host memory, read only during mcc_mech_create).
+ * Reaction j: reactant slots reac_idx[reac_ptr[j] .. reac_ptr[j+1]) (1 to 3
+ * slots; a repeated species index is a stoichiometric multiplicity) and
+ * products prod_idx[prod_ptr[j] .. prod_ptr[j+1]) with floating-point yields
+ * (0 to 8 products).  Rate r_j = k_j * prod over slots of y_s (mass action),
+ * with k_j = A_j exp(-theta_j / T) for thermal reactions (theta = Ea/R in K)
+ * and k_j = A_j * s for photolysis (A_j is the J-rate, s a per-cell scale). */
+typedef struct {
+    int32_t n_species;          /* 1 .. MCC_MAX_SPECIES */
+    int32_t n_reactions;        /* 0 .. 65535 */
+    const int32_t *rxn_type;    /* [n_reactions] MCC_RXN_* */
+    const int32_t *reac_ptr;    /* [n_reactions + 1], reac_ptr[0] = 0, non-decreasing */
+    const int32_t *reac_idx;    /* [reac_ptr[n_reactions]] species indices */
+    const int32_t *prod_ptr;    /* [n_reactions + 1] */
+    const int32_t *prod_idx;    /* [prod_ptr[n_reactions]] species indices */
+    const double *prod_yield;   /* [prod_ptr[n_reactions]] finite yields */
+    const double *A;            /* [n_reactions] finite, >= 0 */
+    const double *theta;        /* [n_reactions] finite (ignored for photolysis) */
+} mcc_mech_desc;
+
+#define MCC_MAX_SPECIES 256
+
+/* Constants of the BDF outer step (all read by every cell):
+ *   weights w_i = 1/(rtol |y_i| + atol) from the last accepted state;
+ *   Newton converged when rho/(1-rho)*|dy| < eta_newton (WRMS norm);
+ *   accepted-step factor = min(fac_max, safety * best order factor);
+ *   rejected-step factor = max(fac_min, safety * err^(-1/(k+1)));
+ *   Newton-failure factor = fac_newton_fail;
+ *   failure once h < h_min_rel * dt (or h vanishes against t);
+ *   max_order 1..5, max_newton 1..16, max_steps >= 1 step attempts. */
+typedef struct {
+    double rtol, atol, eta_newton, safety, fac_min, fac_max, fac_newton_fail, h_min_rel;
+    int32_t max_order, max_newton, max_steps, reserved;
+} mcc_solver_opts;
+
+/* Per-cell counters of one mcc_solve_step. */
+typedef struct {
+    int32_t steps, rejects, newton_fails, newton_iters, f_evals, jac_evals, lu_count, order;
+    double h_last, y_min;
+} mcc_cell_stats;
+
+typedef struct mcc_mech mcc_mech;
+typedef struct mcc_cells mcc_cells;
+
+/* Text of the last error on this thread ("" if none).  Never NULL. */
+const char *mcc_last_error(void);
+
+/* Library version string. */
+const char *mcc_version(void);
+
+/* Fill *opts with the defaults: rtol 1e-8, atol 1.0, eta_newton 0.03,
+ * safety 0.9, fac_min 0.2, fac_max 10, fac_newton_fail 0.5, h_min_rel 1e-30,
+ * max_order 5, max_newton 4, max_steps 100000. */
+mcc_status mcc_solver_opts_default(mcc_solver_opts *opts);
+
+/* Validate a mechanism, compile its tables (Jacobian pattern, gather lists,
+ * fill-reducing ordering, symbolic LU and the operation schedules of the
+ * solver) and upload them to `device` (Section 3: reaction data on the GPU
+ * from initialisation; device limits checked at run time).  Synchronous.
+ * device = -1 validates and compiles on the host only (no GPU needed): such a
+ * handle answers mcc_mech_info and mcc_mech_jac_pattern, and
+ * mcc_cells_create refuses it with MCC_ERR_STATE.
+ * Errors: MCC_ERR_INVALID_ARG (null desc/out, bad device), MCC_ERR_MECH
+ * (validation, or the per-cell solver state does not fit the device's local
+ * data share), MCC_ERR_OOM, MCC_ERR_DEVICE.  On success *out owns the tables. */
+mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out);
+
+/* Sizes of a compiled mechanism (any output pointer may be NULL):
+ * species, reactions, Jacobian nonzeros (diagonal included), LU nonzeros
+ * after fill, and the dynamic local-data-share bytes one cell of the solver
+ * uses. */
+mcc_status mcc_mech_info(const mcc_mech *mech, int32_t *n_species, int32_t *n_reactions,
+                         int32_t *nnz, int32_t *lu_nnz, int32_t *solver_lds_bytes);
+
+/* Algorithmic work of one cell for a compiled mechanism: the arithmetic the
+ * method needs (sparse, no padding), not what a kernel happens to execute.
+ * Flops count a multiply-add as 2. */
+typedef struct {
+    int64_t deriv_flops;          /* one f: sum_j arity_j products + 2 per (reaction, species) term */
+    int64_t newton_matrix_flops;  /* one M = I - c J: rate partials + 2 per J term + scaling */
+    int64_t lu_flops;             /* one sparse LU of M: 2 per update + pivot reciprocals + L scaling */
+    int64_t solve_flops;          /* one forward + backward substitution */
+    int64_t fj_bytes;             /* HBM bytes of one fused f+J: read y, k; write f, J */
+    int64_t f_bytes;              /* HBM bytes of one f: read y, k; write f */
+    int64_t j_bytes;              /* HBM bytes of one J: read y, k; write J */
+    int64_t reserved;
+} mcc_op_counts;
+
+mcc_status mcc_mech_op_counts(const mcc_mech *mech, mcc_op_counts *counts);
+
+/* Copy the Jacobian sparsity pattern (species order, CSR with sorted columns
+ * and the diagonal always present) into caller host arrays row_ptr
+ * [n_species + 1] and col_idx [nnz].  Row = tendency index i, column =
+ * concentration index s (J_is = d f_i / d y_s). */
+mcc_status mcc_mech_jac_pattern(const mcc_mech *mech, int32_t *row_ptr, int32_t *col_idx);
+
+/* Release a mechanism.  MCC_ERR_STATE if cell batches created from it are
+ * still alive (nothing is released then). */
+mcc_status mcc_mech_destroy(mcc_mech *mech);
+
+/* A batch of n_cells cells (0 allowed: every call is then a no-op) with
+ * leading dimension ld >= n_cells for every per-cell array.  Allocates the
+ * device array of rate constants [n_reactions][ld].  Synchronous. */
+mcc_status mcc_cells_create(const mcc_mech *mech, int64_t n_cells, int64_t ld, mcc_cells **out);
+
+/* Per-cell environment (device arrays [n_cells]): temperature T in K
+ * (finite, > 0), pressure P in hPa (reserved: the current reaction types do
+ * not use it, may be NULL), photolysis scale jscale (may be NULL = 1).
+ * Computes the rate constants k [n_reactions][ld] on `stream`. */
+mcc_status mcc_cells_bind(mcc_cells *cells, const double *T, const double *P,
+                          const double *jscale, void *stream);
+
+/* Device pointer to the batch's rate constants [n_reactions][ld] (owned by
+ * the batch, valid until mcc_cells_destroy; filled by mcc_cells_bind). */
+mcc_status mcc_cells_rate_constants(const mcc_cells *cells, const double **k);
+
+/* f = dy/dt for every cell (Section 2, derivative; Section 3, Multi-cells):
+ * y, f device [n_species][ld].  MCC_ERR_STATE before mcc_cells_bind. */
+mcc_status mcc_calc_deriv(const mcc_cells *cells, const double *y, double *f, void *stream);
+
+/* Sparse Jacobian J_is = d f_i / d y_s for every cell (Section 2: sparse
+ * Jacobian handed to the solver): y device [n_species][ld], jac device
+ * [nnz][ld] in the CSR order of mcc_mech_jac_pattern. */
+mcc_status mcc_calc_jac(const mcc_cells *cells, const double *y, double *jac, void *stream);
+
+/* f and J in one pass over y and k (same outputs as the two calls above). */
+mcc_status mcc_calc_deriv_jac(const mcc_cells *cells, const double *y, double *f, double *jac,
+                              void *stream);
+
+/* One outer step of length dt > 0 for every cell: each cell integrates
+ * y' = f(y) from 0 to dt on its own with the variable-order BDF method and a
+ * Newton iteration on a sparse LU of I - (h/gamma_k) J (Section 2: solver
+ * with a sparse Jacobian; Section 5: the whole solve on the GPU).
+ * y: device [n_species][ld], overwritten with y(dt).  cell_status: device
+ * int32 [n_cells] (mcc_cell_status).  stats: device mcc_cell_stats
+ * [n_cells] or NULL.  opts: host, NULL = defaults.  A cell that fails keeps
+ * its last accepted state; other cells are unaffected. */
+mcc_status mcc_solve_step(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
+                          int32_t *cell_status, mcc_cell_stats *stats, void *stream);
+
+/* Wait for all work of this batch's device and report any asynchronous error. */
+mcc_status mcc_sync(mcc_cells *cells);
+
+/* Release a batch.  Synchronous. */
+mcc_status mcc_cells_destroy(mcc_cells *cells);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCC_H */

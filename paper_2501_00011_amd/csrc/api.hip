@@ -1,0 +1,488 @@
+// C ABI of libmcchem (declared in include/mcc.h): handles, argument checks,
+// table upload and kernel launches.  All arithmetic happens in the kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mcc_internal.hpp"
+
+using namespace mcc;
+
+struct mcc_mech {
+    HostTables t;
+    int device = 0;
+    void *dev_buf = nullptr;  // every device table, sub-allocated
+    // device views
+    const int32_t *rxn_type = nullptr, *out_ptr = nullptr, *term_idx = nullptr, *fj_chunks = nullptr;
+    const double *A = nullptr, *theta = nullptr, *term_coef = nullptr;
+    const int32_t *perm = nullptr, *rx_reac = nullptr, *part = nullptr;
+    const int32_t *fg_w = nullptr, *fg_off = nullptr, *fg_idx = nullptr;
+    const double *fg_coef = nullptr;
+    const int32_t *jg_dest = nullptr, *jg_w = nullptr, *jg_off = nullptr, *jg_idx = nullptr;
+    const double *jg_coef = nullptr;
+    const int32_t *lu_diag = nullptr, *lcol_ptr = nullptr, *lcol_off = nullptr, *upd_ptr = nullptr;
+    const uint64_t *upd = nullptr;
+    const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
+    int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, off_invd = 0, lds_doubles = 0;
+    int live_batches = 0;
+};
+
+struct mcc_cells {
+    mcc_mech *mech = nullptr;
+    int64_t n_cells = 0, ld = 0;
+    double *k = nullptr;
+    bool bound = false;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mcc_status set_error(mcc_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+mcc_status ok()
+{
+    g_last_error.clear();
+    return MCC_OK;
+}
+
+mcc_status hip_error(hipError_t e, const char *what)
+{
+    return set_error(e == hipErrorOutOfMemory ? MCC_ERR_OOM : MCC_ERR_DEVICE,
+                     std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Appends host vectors to one device buffer at 256-byte aligned offsets.
+struct Packer {
+    std::vector<char> bytes;
+    template <class T>
+    size_t add(const std::vector<T> &v)
+    {
+        size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + std::max<size_t>(v.size() * sizeof(T), 8), 0);
+        if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) : ok_(hipGetDevice(&prev_) == hipSuccess)
+    {
+        if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = 0;
+    bool ok_;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *mcc_last_error(void) { return g_last_error.c_str(); }
+
+const char *mcc_version(void) { return "mcchem 0.1 (gfx950, fp64)"; }
+
+mcc_status mcc_solver_opts_default(mcc_solver_opts *o)
+{
+    if (!o) return set_error(MCC_ERR_INVALID_ARG, "opts is null");
+    o->rtol = 1e-8;
+    o->atol = 1.0;
+    o->eta_newton = 0.03;
+    o->safety = 0.9;
+    o->fac_min = 0.2;
+    o->fac_max = 10.0;
+    o->fac_newton_fail = 0.5;
+    o->h_min_rel = 1e-30;
+    o->max_order = 5;
+    o->max_newton = 4;
+    o->max_steps = 100000;
+    o->reserved = 0;
+    return ok();
+}
+
+mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out)
+{
+    if (!desc || !out) return set_error(MCC_ERR_INVALID_ARG, "desc and out must not be null");
+    *out = nullptr;
+    if (device < -1) return set_error(MCC_ERR_INVALID_ARG, "device index out of range");
+
+    mcc_mech *m = new (std::nothrow) mcc_mech;
+    if (!m) return set_error(MCC_ERR_OOM, "host allocation failed");
+    std::string err;
+    mcc_status st = compile_mechanism(desc, &m->t, &err);
+    if (st != MCC_OK) {
+        delete m;
+        return set_error(st, err);
+    }
+    HostTables &t = m->t;
+    m->device = device;
+
+    // LDS layout of one solver cell (doubles).
+    m->off_y = 0;
+    m->off_k = t.N + 1;
+    m->off_r = m->off_k + t.R;
+    m->off_p = m->off_r + t.R + 1;
+    m->off_lu = m->off_p + t.n_partials + 1;
+    m->off_invd = m->off_lu + t.lu_nnz + 2;
+    m->lds_doubles = m->off_invd + t.N;
+    if (device == -1) {  // host-only: validated and compiled, nothing uploaded
+        *out = m;
+        return ok();
+    }
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) {
+        delete m;
+        return hip_error(e, "hipGetDeviceCount");
+    }
+    if (device >= ndev) {
+        delete m;
+        return set_error(MCC_ERR_INVALID_ARG, "device index out of range");
+    }
+    DeviceGuard g(device);
+    if (!g.ok()) {
+        delete m;
+        return set_error(MCC_ERR_DEVICE, "cannot select device");
+    }
+    // Device limits (Section 3: checked at run time rather than assumed).
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (e != hipSuccess) {
+        delete m;
+        return hip_error(e, "hipDeviceGetAttribute");
+    }
+    const size_t lds_bytes = (size_t)m->lds_doubles * sizeof(double);
+    if (lds_bytes > (size_t)max_lds) {
+        delete m;
+        return set_error(MCC_ERR_MECH, "solver state of one cell needs " + std::to_string(lds_bytes) +
+                                           " bytes of LDS; the device allows " + std::to_string(max_lds));
+    }
+    if ((e = prepare_solve_kernels(max_lds)) != hipSuccess) {
+        delete m;
+        return hip_error(e, "hipFuncSetAttribute");
+    }
+
+    Packer pk;
+    const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
+    const size_t o_optr = pk.add(t.out_ptr), o_tidx = pk.add(t.term_idx), o_tcoef = pk.add(t.term_coef);
+    const size_t o_chunks = pk.add(t.fj_chunks);
+    const size_t o_perm = pk.add(t.perm), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
+    const size_t o_fgw = pk.add(t.fg_w), o_fgo = pk.add(t.fg_off), o_fgi = pk.add(t.fg_idx), o_fgc = pk.add(t.fg_coef);
+    const size_t o_jgd = pk.add(t.jg_dest), o_jgw = pk.add(t.jg_w), o_jgo = pk.add(t.jg_off);
+    const size_t o_jgi = pk.add(t.jg_idx), o_jgc = pk.add(t.jg_coef);
+    const size_t o_lud = pk.add(t.lu_diag), o_lcp = pk.add(t.lcol_ptr), o_lco = pk.add(t.lcol_off);
+    const size_t o_upp = pk.add(t.upd_ptr), o_upd = pk.add(t.upd);
+    const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
+    if ((e = hipMalloc(&m->dev_buf, pk.bytes.size())) != hipSuccess) {
+        delete m;
+        return hip_error(e, "hipMalloc (mechanism tables)");
+    }
+    if ((e = hipMemcpy(m->dev_buf, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(m->dev_buf);
+        delete m;
+        return hip_error(e, "hipMemcpy (mechanism tables)");
+    }
+    char *b = static_cast<char *>(m->dev_buf);
+    m->rxn_type = (const int32_t *)(b + o_rxn);
+    m->A = (const double *)(b + o_A);
+    m->theta = (const double *)(b + o_th);
+    m->out_ptr = (const int32_t *)(b + o_optr);
+    m->term_idx = (const int32_t *)(b + o_tidx);
+    m->term_coef = (const double *)(b + o_tcoef);
+    m->fj_chunks = (const int32_t *)(b + o_chunks);
+    m->perm = (const int32_t *)(b + o_perm);
+    m->rx_reac = (const int32_t *)(b + o_rxr);
+    m->part = (const int32_t *)(b + o_part);
+    m->fg_w = (const int32_t *)(b + o_fgw);
+    m->fg_off = (const int32_t *)(b + o_fgo);
+    m->fg_idx = (const int32_t *)(b + o_fgi);
+    m->fg_coef = (const double *)(b + o_fgc);
+    m->jg_dest = (const int32_t *)(b + o_jgd);
+    m->jg_w = (const int32_t *)(b + o_jgw);
+    m->jg_off = (const int32_t *)(b + o_jgo);
+    m->jg_idx = (const int32_t *)(b + o_jgi);
+    m->jg_coef = (const double *)(b + o_jgc);
+    m->lu_diag = (const int32_t *)(b + o_lud);
+    m->lcol_ptr = (const int32_t *)(b + o_lcp);
+    m->lcol_off = (const int32_t *)(b + o_lco);
+    m->upd_ptr = (const int32_t *)(b + o_upp);
+    m->upd = (const uint64_t *)(b + o_upd);
+    m->fwd_map = (const uint16_t *)(b + o_fwd);
+    m->bwd_map = (const uint16_t *)(b + o_bwd);
+    *out = m;
+    return ok();
+}
+
+mcc_status mcc_mech_info(const mcc_mech *m, int32_t *n_species, int32_t *n_reactions, int32_t *nnz,
+                         int32_t *lu_nnz, int32_t *solver_lds_bytes)
+{
+    if (!m) return set_error(MCC_ERR_INVALID_ARG, "mech is null");
+    if (n_species) *n_species = m->t.N;
+    if (n_reactions) *n_reactions = m->t.R;
+    if (nnz) *nnz = m->t.nnz;
+    if (lu_nnz) *lu_nnz = m->t.lu_nnz;
+    if (solver_lds_bytes) *solver_lds_bytes = m->lds_doubles * (int32_t)sizeof(double);
+    return ok();
+}
+
+mcc_status mcc_mech_op_counts(const mcc_mech *m, mcc_op_counts *counts)
+{
+    if (!m || !counts) return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    *counts = m->t.counts;
+    return ok();
+}
+
+mcc_status mcc_mech_jac_pattern(const mcc_mech *m, int32_t *row_ptr, int32_t *col_idx)
+{
+    if (!m || !row_ptr || !col_idx) return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    std::memcpy(row_ptr, m->t.row_ptr.data(), m->t.row_ptr.size() * sizeof(int32_t));
+    std::memcpy(col_idx, m->t.col_idx.data(), m->t.col_idx.size() * sizeof(int32_t));
+    return ok();
+}
+
+mcc_status mcc_mech_destroy(mcc_mech *m)
+{
+    if (!m) return ok();
+    if (m->live_batches > 0) return set_error(MCC_ERR_STATE, "cell batches created from this mechanism are alive");
+    if (m->device < 0) {
+        delete m;
+        return ok();
+    }
+    DeviceGuard g(m->device);
+    if (m->dev_buf) {
+        hipError_t e = hipFree(m->dev_buf);
+        if (e != hipSuccess) return hip_error(e, "hipFree");
+    }
+    delete m;
+    return ok();
+}
+
+mcc_status mcc_cells_create(const mcc_mech *mech, int64_t n_cells, int64_t ld, mcc_cells **out)
+{
+    if (!mech || !out) return set_error(MCC_ERR_INVALID_ARG, "mech and out must not be null");
+    *out = nullptr;
+    if (n_cells < 0 || ld < n_cells) return set_error(MCC_ERR_INVALID_ARG, "need 0 <= n_cells <= ld");
+    if (n_cells > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "n_cells exceeds 2^31-1");
+    if (mech->device < 0) return set_error(MCC_ERR_STATE, "mechanism was compiled host-only (device -1)");
+    mcc_cells *c = new (std::nothrow) mcc_cells;
+    if (!c) return set_error(MCC_ERR_OOM, "host allocation failed");
+    c->mech = const_cast<mcc_mech *>(mech);
+    c->n_cells = n_cells;
+    c->ld = ld;
+    DeviceGuard g(mech->device);
+    const size_t kbytes = (size_t)mech->t.R * (size_t)ld * sizeof(double);
+    if (kbytes > 0) {
+        hipError_t e = hipMalloc(&c->k, kbytes);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_error(e, "hipMalloc (rate constants)");
+        }
+    }
+    c->mech->live_batches++;
+    *out = c;
+    return ok();
+}
+
+mcc_status mcc_cells_bind(mcc_cells *c, const double *T, const double *P, const double *jscale, void *stream)
+{
+    (void)P;  // reserved: no current reaction type depends on pressure
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (c->n_cells > 0 && !T) return set_error(MCC_ERR_INVALID_ARG, "T is null");
+    DeviceGuard g(c->mech->device);
+    RatesParams p{};
+    p.rxn_type = c->mech->rxn_type;
+    p.A = c->mech->A;
+    p.theta = c->mech->theta;
+    p.T = T;
+    p.jscale = jscale;
+    p.k = c->k;
+    p.n_cells = c->n_cells;
+    p.ld = c->ld;
+    p.R = c->mech->t.R;
+    hipError_t e = launch_rates(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "rates kernel launch");
+    c->bound = true;
+    return ok();
+}
+
+mcc_status mcc_cells_rate_constants(const mcc_cells *c, const double **k)
+{
+    if (!c || !k) return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    *k = c->k;
+    return ok();
+}
+
+static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double *jac, void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
+    if (c->n_cells == 0) return ok();
+    if (!y) return set_error(MCC_ERR_INVALID_ARG, "y is null");
+    const HostTables &t = c->mech->t;
+    DeviceGuard g(c->mech->device);
+    FJParams p{};
+    p.out_ptr = c->mech->out_ptr;
+    p.term_idx = c->mech->term_idx;
+    p.term_coef = c->mech->term_coef;
+    p.chunks = c->mech->fj_chunks;
+    p.y = y;
+    p.k = c->k;
+    p.f = f;
+    p.jac = jac;
+    p.n_cells = c->n_cells;
+    p.ld = c->ld;
+    p.N = t.N;
+    p.n_tiles = (int)((c->n_cells + 255) / 256);
+    if (f && jac) {
+        p.chunk_begin = 0;
+        p.n_chunks = t.n_fchunks + t.n_jchunks;
+    } else if (f) {
+        p.chunk_begin = 0;
+        p.n_chunks = t.n_fchunks;
+    } else {
+        p.chunk_begin = t.n_fchunks;
+        p.n_chunks = t.n_jchunks;
+    }
+    hipError_t e = launch_fj(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "f/J kernel launch");
+    return ok();
+}
+
+mcc_status mcc_calc_deriv(const mcc_cells *c, const double *y, double *f, void *stream)
+{
+    if (c && c->n_cells > 0 && !f) return set_error(MCC_ERR_INVALID_ARG, "f is null");
+    return run_fj(c, y, f, nullptr, stream);
+}
+
+mcc_status mcc_calc_jac(const mcc_cells *c, const double *y, double *jac, void *stream)
+{
+    if (c && c->n_cells > 0 && !jac) return set_error(MCC_ERR_INVALID_ARG, "jac is null");
+    return run_fj(c, y, nullptr, jac, stream);
+}
+
+mcc_status mcc_calc_deriv_jac(const mcc_cells *c, const double *y, double *f, double *jac, void *stream)
+{
+    if (c && c->n_cells > 0 && (!f || !jac)) return set_error(MCC_ERR_INVALID_ARG, "f and jac must not be null");
+    return run_fj(c, y, f, jac, stream);
+}
+
+static bool opts_valid(const mcc_solver_opts &o, std::string *why)
+{
+    if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !std::isfinite(o.rtol) || !std::isfinite(o.atol)) {
+        *why = "need rtol >= 0 and atol > 0, both finite";
+        return false;
+    }
+    if (!(o.eta_newton > 0.0) || !(o.safety > 0.0) || !(o.fac_min > 0.0) || !(o.fac_max >= 1.0) ||
+        !(o.fac_newton_fail > 0.0 && o.fac_newton_fail < 1.0) || !(o.h_min_rel >= 0.0)) {
+        *why = "need eta_newton, safety, fac_min > 0, fac_max >= 1, 0 < fac_newton_fail < 1, h_min_rel >= 0";
+        return false;
+    }
+    if (o.max_order < 1 || o.max_order > kMaxOrder || o.max_newton < 1 || o.max_newton > 16 || o.max_steps < 1) {
+        *why = "need max_order in 1..5, max_newton in 1..16, max_steps >= 1";
+        return false;
+    }
+    return true;
+}
+
+mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
+                          mcc_cell_stats *stats, void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(MCC_ERR_INVALID_ARG, "dt must be finite and > 0");
+    mcc_solver_opts o;
+    if (opts)
+        o = *opts;
+    else
+        mcc_solver_opts_default(&o);
+    std::string why;
+    if (!opts_valid(o, &why)) return set_error(MCC_ERR_INVALID_ARG, why);
+    if (c->n_cells == 0) return ok();
+    if (!y || !cell_status) return set_error(MCC_ERR_INVALID_ARG, "y and cell_status must not be null");
+    const mcc_mech *m = c->mech;
+    DeviceGuard g(m->device);
+    SolveParams p{};
+    p.perm = m->perm;
+    p.rx_reac = m->rx_reac;
+    p.part = m->part;
+    p.fg_w = m->fg_w;
+    p.fg_off = m->fg_off;
+    p.fg_idx = m->fg_idx;
+    p.fg_coef = m->fg_coef;
+    p.jg_dest = m->jg_dest;
+    p.jg_w = m->jg_w;
+    p.jg_off = m->jg_off;
+    p.jg_idx = m->jg_idx;
+    p.jg_coef = m->jg_coef;
+    p.lu_diag = m->lu_diag;
+    p.lcol_ptr = m->lcol_ptr;
+    p.lcol_off = m->lcol_off;
+    p.upd_ptr = m->upd_ptr;
+    p.upd = m->upd;
+    p.fwd_map = m->fwd_map;
+    p.bwd_map = m->bwd_map;
+    p.N = m->t.N;
+    p.R = m->t.R;
+    p.P = m->t.n_partials;
+    p.lu_nnz = m->t.lu_nnz;
+    p.n_jpass = (int32_t)m->t.jg_w.size();
+    p.off_y = m->off_y;
+    p.off_k = m->off_k;
+    p.off_r = m->off_r;
+    p.off_p = m->off_p;
+    p.off_lu = m->off_lu;
+    p.off_invd = m->off_invd;
+    p.lds_doubles = m->lds_doubles;
+    p.k = c->k;
+    p.y = y;
+    p.status = cell_status;
+    p.stats = stats;
+    p.n_cells = c->n_cells;
+    p.ld = c->ld;
+    p.dt = dt;
+    p.opts = o;
+    hipError_t e = launch_solve(p, m->t.NS, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "solver kernel launch");
+    return ok();
+}
+
+mcc_status mcc_sync(mcc_cells *c)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    DeviceGuard g(c->mech->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
+    return ok();
+}
+
+mcc_status mcc_cells_destroy(mcc_cells *c)
+{
+    if (!c) return ok();
+    DeviceGuard g(c->mech->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (c->k) {
+        hipError_t e2 = hipFree(c->k);
+        if (e == hipSuccess) e = e2;
+    }
+    c->mech->live_batches--;
+    delete c;
+    if (e != hipSuccess) return hip_error(e, "mcc_cells_destroy");
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,528 @@
+// One BDF outer step per cell: a whole wavefront (64 lanes) integrates one
+// cell from t = 0 to t = dt, so every control decision (Newton convergence,
+// error test, step size and order) is uniform across the wavefront and cells
+// of different stiffness never make lanes diverge; the hardware dispatcher
+// hands a finished wavefront's compute unit the next cell.
+//
+// Method (variable-order BDF in backward-difference form, orders 1..5, with a
+// simplified Newton iteration on a freshly evaluated Jacobian at every step
+// attempt; Shampine & Reichelt 1997, kappa = 0; Hairer-Norsett-Wanner starting
+// step).  It is the per-cell solve of Section 2 (an implicit solver with a
+// sparse Jacobian) moved entirely onto the GPU as Section 5 proposes: the
+// state never leaves the device between f, J and linear-solver calls.
+//
+// Per-cell storage
+//   registers : position p = s*64 + lane of every per-species vector (p in
+//               the fill-reducing order), s = 0..NS-1: the backward
+//               differences D[0..7], the Newton correction, weights, ...
+//   LDS       : the evaluation point y (+ the constant 1 at index N), the
+//               cell's rate constants, reaction rates, rate partials, the LU
+//               factors (+ a zero cell and a write-only cell) and 1/U_kk.
+//   HBM       : only y in/out, k in, status and stats out.
+#include "mcc_internal.hpp"
+
+namespace mcc {
+namespace {
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return __shfl(v, 0);  // lane 0's sum on every lane: bitwise uniform
+}
+
+__device__ inline double wave_min(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
+    return __shfl(v, 0);
+}
+
+__device__ inline double lane_bcast(double v, int src_lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src_lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src_lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double bdf_gamma(int j)
+{
+    double g = 0.0;
+    for (int i = 1; i <= j; ++i) g += 1.0 / i;
+    return g;
+}
+
+template <int NS>
+struct Cell {
+    const SolveParams &p;
+    double *yv, *kv, *rv, *pv, *lu, *invd;
+    int lane;
+    int N;
+
+    __device__ Cell(const SolveParams &pp, double *smem)
+        : p(pp), yv(smem + pp.off_y), kv(smem + pp.off_k), rv(smem + pp.off_r), pv(smem + pp.off_p),
+          lu(smem + pp.off_lu), invd(smem + pp.off_invd), lane((int)threadIdx.x), N(pp.N) {}
+
+    __device__ bool valid(int s) const { return s * kWave + lane < N; }
+
+    __device__ void put_y(const double (&v)[NS])
+    {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (valid(s)) yv[s * kWave + lane] = v[s];
+        __syncthreads();
+    }
+
+    // f at v: reaction rates r_j = k_j y_a y_b y_c (lane per reaction), then
+    // f_p = sum nu r gathered per species position (lane per position).
+    __device__ void deriv(const double (&v)[NS], double (&f)[NS])
+    {
+        put_y(v);
+        const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
+        for (int j = lane; j < p.R; j += kWave) {
+            const int4 a = rx[j];
+            double r = kv[j] * yv[a.x];
+            r *= yv[a.y];
+            r *= yv[a.z];
+            rv[j] = r;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double acc = 0.0;
+            const int W = p.fg_w[s], base = p.fg_off[s] + lane;
+            for (int t = 0; t < W; ++t) acc += p.fg_coef[base + t * kWave] * rv[p.fg_idx[base + t * kWave]];
+            f[s] = acc;
+        }
+    }
+
+    // Newton matrix M = I - c J(v) written over the LU storage (fill = 0).
+    __device__ void newton_matrix(const double (&v)[NS], double c)
+    {
+        put_y(v);
+        const int4 *pt = reinterpret_cast<const int4 *>(p.part);
+        for (int q = lane; q < p.P; q += kWave) {
+            const int4 a = pt[q];
+            double d = kv[a.x] * yv[a.y];
+            d *= yv[a.z];
+            pv[q] = d;
+        }
+        __syncthreads();
+        for (int ps = 0; ps < p.n_jpass; ++ps) {
+            const int dest = p.jg_dest[ps * kWave + lane];
+            const int W = p.jg_w[ps], base = p.jg_off[ps] + lane;
+            double acc = 0.0;
+            for (int t = 0; t < W; ++t) acc += p.jg_coef[base + t * kWave] * pv[p.jg_idx[base + t * kWave]];
+            const double m = -c * acc;
+            lu[dest & 0xffff] = (dest & (1 << 30)) ? 1.0 + m : m;
+        }
+        __syncthreads();
+    }
+
+    // Right-looking LU with the static (diagonal) pivot order.  Returns true
+    // if a pivot is zero, tiny or not finite (uniform across the wavefront).
+    __device__ bool factor()
+    {
+        for (int k = 0; k < N; ++k) {
+            const double dk = lu[p.lu_diag[k]];
+            if (!(fabs(dk) >= 1e-300) || !isfinite(dk)) return true;
+            const double inv = 1.0 / dk;
+            if (lane == 0) invd[k] = inv;
+            const int l0 = p.lcol_ptr[k], l1 = p.lcol_ptr[k + 1];
+            for (int t = l0 + lane; t < l1; t += kWave) lu[p.lcol_off[t]] *= inv;
+            __syncthreads();
+            const int u0 = p.upd_ptr[k], u1 = p.upd_ptr[k + 1];
+            for (int t = u0 + lane; t < u1; t += kWave) {
+                const uint64_t w = p.upd[t];
+                const int dst = (int)(w & 0xffff), l = (int)((w >> 16) & 0xffff), u = (int)((w >> 32) & 0xffff);
+                lu[dst] -= lu[l] * lu[u];
+            }
+            __syncthreads();
+        }
+        return false;
+    }
+
+    // b <- (LU)^-1 b, b held in registers by position; the pivot value of
+    // each column is broadcast from its lane with readlane.
+    __device__ void solve(double (&b)[NS])
+    {
+#pragma unroll
+        for (int ks = 0; ks < NS; ++ks) {
+#pragma unroll 2
+            for (int kl = 0; kl < kWave; ++kl) {
+                const int k = ks * kWave + kl;
+                if (k >= N) break;
+                const double xk = lane_bcast(b[ks], kl);
+#pragma unroll
+                for (int s = ks; s < NS; ++s) {
+                    const int off = p.fwd_map[((size_t)k * NS + s) * kWave + lane];
+                    b[s] -= lu[off] * xk;
+                }
+            }
+        }
+#pragma unroll
+        for (int ks = NS - 1; ks >= 0; --ks) {
+#pragma unroll 2
+            for (int kl = kWave - 1; kl >= 0; --kl) {
+                const int k = ks * kWave + kl;
+                if (k >= N) continue;
+                const double xk = lane_bcast(b[ks], kl) * invd[k];
+                if (lane == kl) b[ks] = xk;
+#pragma unroll
+                for (int s = 0; s <= ks; ++s) {
+                    const int off = p.bwd_map[((size_t)k * NS + s) * kWave + lane];
+                    b[s] -= lu[off] * xk;
+                }
+            }
+        }
+    }
+
+    __device__ double wrms(const double (&v)[NS], const double (&w)[NS]) const
+    {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double t = v[s] * w[s];
+            acc += t * t;
+        }
+        return sqrt(wave_sum(acc) / N);
+    }
+
+    __device__ bool any_nonfinite(const double (&v)[NS]) const
+    {
+        int bad = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) bad |= valid(s) && !isfinite(v[s]);
+        return __any(bad);
+    }
+};
+
+// Re-sample the backward differences D[0..order] from spacing h to rho*h.
+// First the interpolating polynomial is evaluated at the new points,
+//   V_i = p(t_n - i rho h) = sum_j c_ij D_j,  c_ij = prod_{m=1..j} (m - 1 - rho i) / m
+// (Newton's backward-difference form), then the new differences are taken,
+//   D'_i = sum_{l<=i} (-1)^l C(i, l) V_l.
+template <int NS>
+__device__ void rescale(double (&D)[kMaxOrder + 3][NS], int order, double rho)
+{
+    constexpr int M = kMaxOrder + 1;
+    double V[M][NS];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double c = 1.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) V[i][s] = D[0][s];
+#pragma unroll
+        for (int j = 1; j < M; ++j) {
+            c *= ((j - 1) - rho * i) / j;
+            if (j <= order)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) V[i][s] += c * D[j][s];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        if (i <= order) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                double acc = 0.0;
+                double binom = 1.0;  // C(i, l)
+#pragma unroll
+                for (int l = 0; l <= i; ++l) {
+                    acc += ((l & 1) ? -binom : binom) * V[l][s];
+                    binom = binom * (i - l) / (l + 1);
+                }
+                D[i][s] = acc;
+            }
+        }
+    }
+}
+
+template <int NS>
+__global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
+{
+    extern __shared__ double smem[];
+    const int64_t cell = blockIdx.x;
+    if (cell >= p.n_cells) return;
+    Cell<NS> C(p, smem);
+    const int lane = C.lane, N = p.N;
+    const mcc_solver_opts &o = p.opts;
+    const double dt = p.dt;
+    const int maxord = o.max_order < 1 ? 1 : (o.max_order > kMaxOrder ? kMaxOrder : o.max_order);
+
+    for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
+    if (lane == 0) {
+        C.yv[N] = 1.0;
+        C.rv[p.R] = 0.0;
+        C.pv[p.P] = 0.0;
+        C.lu[p.lu_nnz] = 0.0;
+    }
+    int sp[NS];
+    double D[kMaxOrder + 3][NS], f[NS], w[NS], ypred[NS], psi[NS], d[NS], tmp[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sp[s] = C.valid(s) ? p.perm[s * kWave + lane] : 0;
+        const double y0 = C.valid(s) ? p.y[(int64_t)sp[s] * p.ld + cell] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxOrder + 3; ++j) D[j][s] = 0.0;
+        D[0][s] = y0;
+    }
+    // counters (uniform)
+    int steps = 0, rejects = 0, newton_fails = 0, newton_iters = 0, f_evals = 0, jac_evals = 0, lu_count = 0;
+    int status = MCC_CELL_OK;
+    double h = 0.0;
+    int order = 1;
+
+    // ---- starting step size -------------------------------------------------
+    C.deriv(D[0], f);
+    f_evals++;
+    bool bad = C.any_nonfinite(D[0]) || C.any_nonfinite(f);
+    if (bad) {
+        status = MCC_CELL_NONFINITE;
+        order = 0;
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
+        const double d0 = C.wrms(D[0], w), d1 = C.wrms(f, w);
+        const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) ypred[s] = D[0][s] + h0 * f[s];
+        C.deriv(ypred, tmp);
+        f_evals++;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) tmp[s] -= f[s];
+        const double d2 = C.wrms(tmp, w) / h0;
+        const double dm = d1 > d2 ? d1 : d2;
+        const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
+        h = fmin(100.0 * h0, fmin(h1, dt));
+        if (!(h > 0.0) || !isfinite(h)) {
+            status = MCC_CELL_NONFINITE;
+            order = 0;
+            h = 0.0;
+            bad = true;
+        }
+    }
+
+    if (!bad) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) D[1][s] = h * f[s];
+        int n_equal = 0, attempts = 0;
+        double t = 0.0;
+        bool done = false;
+        while (!done && t < dt) {
+            bool accepted = false, landing = false;
+            double err_norm = 0.0;
+            while (!accepted) {
+                if (attempts >= o.max_steps) {
+                    status = MCC_CELL_TOO_MUCH_WORK;
+                    done = true;
+                    break;
+                }
+                attempts++;
+                landing = false;
+                if (h >= dt - t) {
+                    const double hn = dt - t;
+                    rescale<NS>(D, order, hn / h);
+                    h = hn;
+                    n_equal = 0;
+                    landing = true;
+                }
+                const double gk = bdf_gamma(order);
+                const double c = h / gk;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    double yp = 0.0, ps = 0.0;
+#pragma unroll
+                    for (int j = 0; j <= kMaxOrder; ++j)
+                        if (j <= order) yp += D[j][s];
+#pragma unroll
+                    for (int j = 1; j <= kMaxOrder; ++j)
+                        if (j <= order) ps += bdf_gamma(j) * D[j][s];
+                    ypred[s] = yp;
+                    psi[s] = ps / gk;
+                    w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
+                    d[s] = 0.0;
+                }
+                C.newton_matrix(ypred, c);
+                jac_evals++;
+                lu_count++;
+                const bool singular = C.factor();
+                bool converged = false;
+                if (!singular) {
+                    double nrm_old = 0.0;
+                    for (int it = 0; it < o.max_newton; ++it) {
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) tmp[s] = ypred[s] + d[s];
+                        C.deriv(tmp, f);
+                        f_evals++;
+                        if (C.any_nonfinite(f)) break;
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) tmp[s] = c * f[s] - psi[s] - d[s];
+                        C.solve(tmp);
+                        newton_iters++;
+                        const double nrm = C.wrms(tmp, w);
+                        if (!isfinite(nrm)) break;
+                        double rho = 0.0;
+                        if (it >= 1) {
+                            rho = nrm / nrm_old;
+                            if (rho >= 1.0) break;
+                        }
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) d[s] += tmp[s];
+                        if (nrm == 0.0 || (it >= 1 && rho / (1.0 - rho) * nrm < o.eta_newton)) {
+                            converged = true;
+                            break;
+                        }
+                        nrm_old = nrm;
+                    }
+                }
+                if (!converged) {
+                    newton_fails++;
+                    rescale<NS>(D, order, o.fac_newton_fail);
+                    h *= o.fac_newton_fail;
+                    n_equal = 0;
+                    if (h < o.h_min_rel * dt || t + h == t) {
+                        status = singular ? MCC_CELL_SINGULAR : MCC_CELL_CONV_FAIL;
+                        done = true;
+                        break;
+                    }
+                    continue;
+                }
+                err_norm = C.wrms(d, w) / (order + 1);
+                if (err_norm > 1.0) {
+                    rejects++;
+                    double fac = o.safety * pow(err_norm, -1.0 / (order + 1));
+                    if (fac < o.fac_min) fac = o.fac_min;
+                    rescale<NS>(D, order, fac);
+                    h *= fac;
+                    n_equal = 0;
+                    if (h < o.h_min_rel * dt || t + h == t) {
+                        status = MCC_CELL_ERR_FAIL;
+                        done = true;
+                        break;
+                    }
+                    continue;
+                }
+                accepted = true;
+            }
+            if (done) break;
+            t = landing ? dt : t + h;
+            steps++;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                for (int j = 3; j < kMaxOrder + 3; ++j)
+                    if (j == order + 2) D[j][s] = d[s] - D[j - 1][s];
+#pragma unroll
+                for (int j = 2; j < kMaxOrder + 2; ++j)
+                    if (j == order + 1) D[j][s] = d[s];
+#pragma unroll
+                for (int j = kMaxOrder; j >= 0; --j)
+                    if (j <= order) D[j][s] += D[j + 1][s];
+            }
+            n_equal++;
+            if (t >= dt) break;
+            if (n_equal < order + 1) continue;
+            const double e_cur = err_norm;
+            double e_low = INFINITY, e_high = INFINITY;
+            if (order > 1) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int j = 1; j <= kMaxOrder; ++j)
+                        if (j == order) v = D[j][s];
+                    tmp[s] = v;
+                }
+                e_low = C.wrms(tmp, w) / order;
+            }
+            if (order < maxord) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int j = 3; j < kMaxOrder + 3; ++j)
+                        if (j == order + 2) v = D[j][s];
+                    tmp[s] = v;
+                }
+                e_high = C.wrms(tmp, w) / (order + 2);
+            }
+            const double r_cur = pow(e_cur, -1.0 / (order + 1));
+            const double r_low = order > 1 ? pow(e_low, -1.0 / order) : 0.0;
+            const double r_high = order < maxord ? pow(e_high, -1.0 / (order + 2)) : 0.0;
+            int new_order = order;
+            double best = r_cur;
+            if (r_low > best) { best = r_low; new_order = order - 1; }
+            if (r_high > best) { best = r_high; new_order = order + 1; }
+            double fac = o.safety * best;
+            if (fac > o.fac_max) fac = o.fac_max;
+            order = new_order;
+            rescale<NS>(D, order, fac);
+            h *= fac;
+            n_equal = 0;
+        }
+    }
+
+    double ymin = 0.0;
+    if (status != MCC_CELL_NONFINITE) {
+        double lm = INFINITY;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (C.valid(s)) {
+                p.y[(int64_t)sp[s] * p.ld + cell] = D[0][s];
+                lm = fmin(lm, D[0][s]);
+            }
+        if (status == MCC_CELL_OK) {
+            ymin = wave_min(lm);
+            bool fin = !C.any_nonfinite(D[0]);
+            if (!fin) status = MCC_CELL_NONFINITE;
+        }
+    }
+    if (lane == 0) {
+        p.status[cell] = status;
+        if (p.stats) {
+            mcc_cell_stats st;
+            st.steps = steps;
+            st.rejects = rejects;
+            st.newton_fails = newton_fails;
+            st.newton_iters = newton_iters;
+            st.f_evals = f_evals;
+            st.jac_evals = jac_evals;
+            st.lu_count = lu_count;
+            st.order = order;
+            st.h_last = h;
+            st.y_min = ymin;
+            p.stats[cell] = st;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t prepare_solve_kernels(int max_lds_bytes)
+{
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)bdf_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)bdf_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void *)bdf_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes)) != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)bdf_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+}
+
+hipError_t launch_solve(const SolveParams &p, int NS, hipStream_t s)
+{
+    if (p.n_cells == 0) return hipSuccess;
+    if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)p.n_cells), block(kWave);
+    const size_t lds = (size_t)p.lds_doubles * sizeof(double);
+    switch (NS) {
+    case 1: hipLaunchKernelGGL(bdf_kernel<1>, grid, block, lds, s, p); break;
+    case 2: hipLaunchKernelGGL(bdf_kernel<2>, grid, block, lds, s, p); break;
+    case 3: hipLaunchKernelGGL(bdf_kernel<3>, grid, block, lds, s, p); break;
+    case 4: hipLaunchKernelGGL(bdf_kernel<4>, grid, block, lds, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mcc

@@ -1,0 +1,292 @@
+"""Thin Python binding of libmcchem (include/mcc.h) over PyTorch device tensors.
+
+Argument marshalling only: every rate constant, f, J and solver step is
+computed by the HIP kernels in libmcchem.so.  There is no CPU fallback; if the
+library is missing or no GPU is present, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcchem.so")
+
+CELL_STATUS = {0: "OK", 1: "TOO_MUCH_WORK", 2: "CONV_FAIL", 3: "ERR_FAIL", 4: "NONFINITE", 5: "SINGULAR"}
+
+STATS_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_fails", np.int32),
+                        ("newton_iters", np.int32), ("f_evals", np.int32), ("jac_evals", np.int32),
+                        ("lu_count", np.int32), ("order", np.int32),
+                        ("h_last", np.float64), ("y_min", np.float64)])
+assert STATS_DTYPE.itemsize == 48
+
+
+class MccError(RuntimeError):
+    pass
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("eta_newton", ctypes.c_double),
+                ("safety", ctypes.c_double), ("fac_min", ctypes.c_double), ("fac_max", ctypes.c_double),
+                ("fac_newton_fail", ctypes.c_double), ("h_min_rel", ctypes.c_double),
+                ("max_order", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _MechDesc(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_reactions", ctypes.c_int32),
+                ("rxn_type", ctypes.c_void_p), ("reac_ptr", ctypes.c_void_p),
+                ("reac_idx", ctypes.c_void_p), ("prod_ptr", ctypes.c_void_p),
+                ("prod_idx", ctypes.c_void_p), ("prod_yield", ctypes.c_void_p),
+                ("A", ctypes.c_void_p), ("theta", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmcchem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch first: its HIP runtime then satisfies the library's libamdhip64.so.7
+    # dependency, so tensors and kernels share one runtime.
+    import torch  # noqa: F401
+    if not os.path.exists(path):
+        raise MccError(f"{path} is missing: build it with `python -m paper_2501_00011_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "mcc_last_error": ([], ctypes.c_char_p),
+        "mcc_version": ([], ctypes.c_char_p),
+        "mcc_solver_opts_default": ([vp], ctypes.c_int),
+        "mcc_mech_create": ([vp, ctypes.c_int, vp], ctypes.c_int),
+        "mcc_mech_info": ([vp, pi32, pi32, pi32, pi32, pi32], ctypes.c_int),
+        "mcc_mech_jac_pattern": ([vp, vp, vp], ctypes.c_int),
+        "mcc_mech_op_counts": ([vp, vp], ctypes.c_int),
+        "mcc_mech_destroy": ([vp], ctypes.c_int),
+        "mcc_cells_create": ([vp, i64, i64, vp], ctypes.c_int),
+        "mcc_cells_bind": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_cells_rate_constants": ([vp, vp], ctypes.c_int),
+        "mcc_calc_deriv": ([vp, vp, vp, vp], ctypes.c_int),
+        "mcc_calc_jac": ([vp, vp, vp, vp], ctypes.c_int),
+        "mcc_calc_deriv_jac": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_solve_step": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_sync": ([vp], ctypes.c_int),
+        "mcc_cells_destroy": ([vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _ = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        msg = library().mcc_last_error().decode()
+        raise MccError(f"mcc status {status}: {msg}")
+
+
+def default_opts(**kw) -> SolverOpts:
+    o = SolverOpts()
+    _check(library().mcc_solver_opts_default(ctypes.addressof(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, what, dtype=None, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise MccError(f"{what} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise MccError(f"{what} must have dtype {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise MccError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise MccError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mechanism:
+    """A compiled mechanism resident on one GPU (mcc_mech_create)."""
+
+    def __init__(self, mech, device: int = 0):
+        L = library()
+        self.source = mech
+        arrays = [np.ascontiguousarray(a, dtype=dt) for a, dt in (
+            (mech.rxn_type, np.int32), (mech.reac_ptr, np.int32), (mech.reac_idx, np.int32),
+            (mech.prod_ptr, np.int32), (mech.prod_idx, np.int32), (mech.prod_yield, np.float64),
+            (mech.A, np.float64), (mech.theta, np.float64))]
+        desc = _MechDesc(int(mech.n_species), int(mech.n_reactions), *[a.ctypes.data for a in arrays])
+        h = ctypes.c_void_p()
+        _check(L.mcc_mech_create(ctypes.addressof(desc), int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+        n, r, nnz, lu, lds = (ctypes.c_int32() for _ in range(5))
+        _check(L.mcc_mech_info(h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(nnz),
+                               ctypes.byref(lu), ctypes.byref(lds)))
+        self.n_species, self.n_reactions = n.value, r.value
+        self.nnz, self.lu_nnz, self.solver_lds_bytes = nnz.value, lu.value, lds.value
+
+    def op_counts(self) -> dict:
+        """Algorithmic flops and HBM bytes per cell (mcc_mech_op_counts)."""
+        buf = (ctypes.c_int64 * 8)()
+        _check(library().mcc_mech_op_counts(self._h, ctypes.addressof(buf)))
+        names = ["deriv_flops", "newton_matrix_flops", "lu_flops", "solve_flops",
+                 "fj_bytes", "f_bytes", "j_bytes"]
+        return dict(zip(names, list(buf)[:7]))
+
+    def jac_pattern(self):
+        rp = np.zeros(self.n_species + 1, dtype=np.int32)
+        ci = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        _check(library().mcc_mech_jac_pattern(self._h, rp.ctypes.data, ci.ctypes.data))
+        return rp, ci[:self.nnz]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().mcc_mech_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                library().mcc_mech_destroy(self._h)
+        except Exception:
+            pass
+
+
+class Cells:
+    """A batch of cells of one mechanism (mcc_cells_create); arrays are
+    float64 device tensors laid out [entity][ld], cell index fastest."""
+
+    def __init__(self, mech: Mechanism, n_cells: int, ld: int | None = None):
+        self.mech = mech
+        self.n_cells = int(n_cells)
+        self.ld = int(ld) if ld is not None else self.n_cells
+        h = ctypes.c_void_p()
+        _check(library().mcc_cells_create(mech._h, self.n_cells, self.ld, ctypes.byref(h)))
+        self._h = h
+
+    def bind(self, T, P=None, jscale=None, stream=None):
+        import torch
+        f64 = torch.float64
+        shape = (self.n_cells,)
+        tp = _dptr(T, "T", f64, shape)
+        pp = _dptr(P, "P", f64, shape) if P is not None else None
+        sp = _dptr(jscale, "jscale", f64, shape) if jscale is not None else None
+        _check(library().mcc_cells_bind(self._h, tp, pp, sp, _stream_ptr(stream)))
+
+    def rate_constants(self):
+        """Copy of the rate constants [R][ld] as a device tensor."""
+        import torch
+        k = ctypes.c_void_p()
+        _check(library().mcc_cells_rate_constants(self._h, ctypes.byref(k)))
+        out = torch.empty((self.mech.n_reactions, self.ld), dtype=torch.float64,
+                          device=f"cuda:{self.mech.device}")
+        if out.numel():
+            import ctypes as _c
+            torch.cuda.synchronize()
+            hip = _hip_runtime()
+            _check_hip(hip.hipMemcpy(_c.c_void_p(out.data_ptr()), k, out.numel() * 8, 3))
+        return out
+
+    def _yshape(self):
+        return (self.mech.n_species, self.ld)
+
+    def deriv(self, y, f=None, stream=None):
+        import torch
+        if f is None:
+            f = torch.empty(self._yshape(), dtype=torch.float64, device=y.device)
+        _check(library().mcc_calc_deriv(self._h, _dptr(y, "y", torch.float64, self._yshape()),
+                                        _dptr(f, "f", torch.float64, self._yshape()), _stream_ptr(stream)))
+        return f
+
+    def jac(self, y, jac=None, stream=None):
+        import torch
+        shape = (self.mech.nnz, self.ld)
+        if jac is None:
+            jac = torch.empty(shape, dtype=torch.float64, device=y.device)
+        _check(library().mcc_calc_jac(self._h, _dptr(y, "y", torch.float64, self._yshape()),
+                                      _dptr(jac, "jac", torch.float64, shape), _stream_ptr(stream)))
+        return jac
+
+    def deriv_jac(self, y, f=None, jac=None, stream=None):
+        import torch
+        shape = (self.mech.nnz, self.ld)
+        if f is None:
+            f = torch.empty(self._yshape(), dtype=torch.float64, device=y.device)
+        if jac is None:
+            jac = torch.empty(shape, dtype=torch.float64, device=y.device)
+        _check(library().mcc_calc_deriv_jac(self._h, _dptr(y, "y", torch.float64, self._yshape()),
+                                            _dptr(f, "f", torch.float64, self._yshape()),
+                                            _dptr(jac, "jac", torch.float64, shape), _stream_ptr(stream)))
+        return f, jac
+
+    def step(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, want_stats=True,
+             stream=None):
+        """One outer step of length dt in place on y.  Returns (status, stats)
+        device tensors: int32 [n_cells] and uint8 [n_cells, 48] (see stats_numpy)."""
+        import torch
+        if status is None:
+            status = torch.empty(self.n_cells, dtype=torch.int32, device=y.device)
+        if want_stats and stats is None:
+            stats = torch.empty((self.n_cells, STATS_DTYPE.itemsize), dtype=torch.uint8, device=y.device)
+        op = ctypes.addressof(opts) if opts is not None else None
+        sp = _dptr(stats, "stats", torch.uint8, (self.n_cells, STATS_DTYPE.itemsize)) if stats is not None else None
+        _check(library().mcc_solve_step(self._h, _dptr(y, "y", torch.float64, self._yshape()), float(dt), op,
+                                        _dptr(status, "status", torch.int32, (self.n_cells,)), sp,
+                                        _stream_ptr(stream)))
+        return status, stats
+
+    def sync(self):
+        _check(library().mcc_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().mcc_cells_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                library().mcc_cells_destroy(self._h)
+        except Exception:
+            pass
+
+
+def stats_numpy(stats) -> np.ndarray:
+    """Device stats buffer -> structured numpy array (fields of mcc_cell_stats)."""
+    raw = stats.cpu().numpy()
+    return raw.reshape(-1).view(STATS_DTYPE)
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        library()
+        _hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime already loaded with torch
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
+
+
+def _check_hip(e):
+    if e != 0:
+        raise MccError(f"hipMemcpy failed with {e}")

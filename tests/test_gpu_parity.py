@@ -1,0 +1,294 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Bars
+- rate constants: |dk| <= 8 eps |k| (exp differs by at most a few ulp);
+- f and J: |d| <= 1e-12 * S, S = sum of absolute contributions (oracle scale);
+- one outer step: |dy| <= 1e-6 |y_oracle| + 1e2 atol (rtol 1e-8, atol 1).
+The oracle and the library share no code; the seeded generator feeds both.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2501_00011_amd import mcchem, synth  # noqa: E402
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _padded(a, ld, fill=np.nan):
+    out = np.full((a.shape[0], ld), fill)
+    out[:, :a.shape[1]] = a
+    return out
+
+
+class Batch:
+    """One mechanism + cells on the GPU and the oracle beside it."""
+
+    def __init__(self, dev, mech, cells, ld=None, oracle_mod=None):
+        self.m, self.c = mech, cells
+        self.C = cells.n_cells
+        self.ld = ld or self.C
+        self.dev = dev
+        self.h = mcchem.Mechanism(mech)
+        self.cells = mcchem.Cells(self.h, self.C, self.ld)
+        self.T = _t(cells.T, dev)
+        self.P = _t(cells.P, dev)
+        self.s = _t(cells.jscale, dev)
+        self.cells.bind(self.T, self.P, self.s)
+        self.o = oracle_mod.Oracle(mech) if oracle_mod else None
+
+    def k_gpu(self):
+        torch.cuda.synchronize()
+        return self.cells.rate_constants().cpu().numpy()[:, :self.C]
+
+    def y_dev(self, y=None):
+        y = self.c.y0 if y is None else y
+        return _t(_padded(y, self.ld), self.dev)
+
+
+@pytest.mark.parametrize("name,n", [("small10", 10), ("medium10k", 777)])
+def test_rate_constants(dev, oracle_mod, name, n):
+    m, c, _ = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=n + 3, oracle_mod=oracle_mod)
+    k_ref = b.o.rate_constants(c.T, c.jscale)
+    k = b.k_gpu()
+    assert np.all(np.abs(k - k_ref) <= 8 * EPS * np.abs(k_ref))
+
+
+def _check_fj(b, f, J, y):
+    k_ref = b.o.rate_constants(b.c.T, b.c.jscale)
+    f_ref, fs = b.o.deriv(k_ref, y)
+    J_ref, Js = b.o.jac(k_ref, y)
+    assert np.all(np.abs(f - f_ref) <= 1e-12 * fs), np.max(np.abs(f - f_ref) / np.maximum(fs, 1e-300))
+    rp, ci = b.h.jac_pattern()
+    rows = np.repeat(np.arange(b.m.n_species), np.diff(rp))
+    Jr = J_ref[:, rows, ci].T   # [nnz][C]
+    Jsr = Js[:, rows, ci].T
+    assert np.all(np.abs(J - Jr) <= 1e-12 * Jsr), np.max(np.abs(J - Jr) / np.maximum(Jsr, 1e-300))
+    # the oracle's J has no entries outside the compiled pattern
+    mask = np.ones((b.m.n_species, b.m.n_species), dtype=bool)
+    mask[rows, ci] = False
+    assert np.all(J_ref[:, mask] == 0.0)
+
+
+@pytest.mark.parametrize("name,n,ld", [("small10", 10, 10), ("small10", 10, 67),
+                                       ("medium10k", 777, 800), ("medium10k", 1, 1)])
+def test_deriv_and_jac_parity(dev, oracle_mod, name, n, ld):
+    m, c, _ = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=ld, oracle_mod=oracle_mod)
+    y = b.y_dev()
+    f = torch.full((m.n_species, ld), 7.0, dtype=torch.float64, device=dev)
+    J = torch.full((b.h.nnz, ld), 7.0, dtype=torch.float64, device=dev)
+    b.cells.deriv(y, f)
+    b.cells.jac(y, J)
+    f2, J2 = b.cells.deriv_jac(y)
+    torch.cuda.synchronize()
+    fn, Jn = f.cpu().numpy(), J.cpu().numpy()
+    # padding columns are never written
+    assert np.all(fn[:, n:] == 7.0) and np.all(Jn[:, n:] == 7.0)
+    _check_fj(b, fn[:, :n], Jn[:, :n], c.y0)
+    # the fused call computes the same values bit for bit
+    np.testing.assert_array_equal(f2.cpu().numpy()[:, :n], fn[:, :n])
+    np.testing.assert_array_equal(J2.cpu().numpy()[:, :n], Jn[:, :n])
+
+
+def test_large_mechanism_fj_parity(dev, oracle_mod):
+    m = synth.mech_large()
+    c = synth.make_cells(m, 300, seed=4242)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    f, J = b.cells.deriv_jac(b.y_dev())
+    torch.cuda.synchronize()
+    _check_fj(b, f.cpu().numpy(), J.cpu().numpy(), c.y0)
+
+
+def test_full_size_fj_sampled_and_homogeneity(dev, oracle_mod):
+    """10,000 cells in the benchmark's launch: sampled cells against the
+    oracle, every cell against Euler's identity sum_s J_is y_s = sum_j ord_j nu_ij r_j."""
+    m, c, _ = synth.workload("medium10k")
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    f, J = b.cells.deriv_jac(b.y_dev())
+    torch.cuda.synchronize()
+    fn, Jn = f.cpu().numpy(), J.cpu().numpy()
+    rng = np.random.default_rng(99)
+    sel = np.sort(rng.choice(c.n_cells, 48, replace=False))
+    sub = synth.Cells(T=c.T[sel], P=c.P[sel], jscale=c.jscale[sel], y0=c.y0[:, sel])
+    bs = Batch.__new__(Batch)
+    bs.m, bs.c, bs.h, bs.o = m, sub, b.h, b.o
+    _check_fj(bs, fn[:, sel], Jn[:, sel], sub.y0)
+    # identity at every cell, with the orders taken from the mechanism
+    rp, ci = b.h.jac_pattern()
+    rows = np.repeat(np.arange(m.n_species), np.diff(rp))
+    Jy = np.zeros_like(fn)
+    np.add.at(Jy, rows, Jn * c.y0[ci])
+    k = b.k_gpu()
+    rhs = np.zeros_like(fn)
+    bound = np.zeros_like(fn)
+    for j in range(m.n_reactions):
+        reac = m.reac_idx[m.reac_ptr[j]:m.reac_ptr[j + 1]]
+        r = k[j] * np.prod(c.y0[reac], axis=0)
+        order = len(reac)
+        for s in reac:
+            rhs[s] -= order * r
+            bound[s] += order * abs(r)
+        for s, yl in zip(m.prod_idx[m.prod_ptr[j]:m.prod_ptr[j + 1]], m.prod_yield[m.prod_ptr[j]:m.prod_ptr[j + 1]]):
+            rhs[s] += order * yl * r
+            bound[s] += order * abs(yl * r)
+    assert np.all(np.abs(Jy - rhs) <= 1e-12 * bound)
+
+
+def _solve_parity(b, dt, opts_kw=None, y0=None):
+    opts_kw = opts_kw or {}
+    y0 = b.c.y0 if y0 is None else y0
+    y = b.y_dev(y0)
+    st, stats = b.cells.step(y, dt, mcchem.default_opts(**opts_kw))
+    torch.cuda.synchronize()
+    yg = y.cpu().numpy()[:, :b.C]
+    sg = st.cpu().numpy()
+    statg = mcchem.stats_numpy(stats)
+    k_ref = b.o.rate_constants(b.c.T, b.c.jscale)
+    import oracle as orc
+    yo, so, stato = b.o.solve(k_ref, y0, dt, orc.default_opts(**opts_kw))
+    return yg, sg, statg, yo, so, stato
+
+
+def _within(yg, yo, atol):
+    err = np.abs(yg - yo)
+    tol = 1e-6 * np.abs(yo) + 1e2 * atol
+    return float(np.max(err / tol))
+
+
+@pytest.mark.parametrize("name,n", [("small10", 10), ("medium10k", 96)])
+def test_solve_step_parity(dev, oracle_mod, name, n):
+    m, c, dt = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=n + 5, oracle_mod=oracle_mod)
+    yg, sg, statg, yo, so, stato = _solve_parity(b, dt)
+    assert np.all(so == 0) and np.all(sg == 0), (so, sg)
+    worst = _within(yg, yo, 1.0)
+    same = np.mean((statg["steps"] == stato["steps"]) & (statg["rejects"] == stato["rejects"]))
+    print(f"{name}: worst {worst:.3g} of the bar, identical step sequences in {same:.0%} of cells")
+    assert worst <= 1.0
+    assert np.all(statg["lu_count"] == statg["jac_evals"])
+    assert np.all(np.abs(statg["steps"] - stato["steps"]) <= 0.1 * stato["steps"] + 5)
+
+
+def test_solve_full_size_sampled(dev, oracle_mod):
+    """All 10,000 cells in one launch (as the benchmark times it); 32 sampled
+    cells against the oracle (a cell's result does not depend on the batch)."""
+    m, c, dt = synth.workload("medium10k")
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    y = b.y_dev()
+    st, stats = b.cells.step(y, dt)
+    torch.cuda.synchronize()
+    sg = st.cpu().numpy()
+    assert np.all(sg == 0), np.bincount(sg)
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(c.n_cells, 32, replace=False))
+    k_ref = b.o.rate_constants(c.T[sel], c.jscale[sel])
+    yo, so, _ = b.o.solve(k_ref, c.y0[:, sel], dt)
+    assert np.all(so == 0)
+    assert _within(y.cpu().numpy()[:, sel], yo, 1.0) <= 1.0
+    # atom conservation at every cell
+    a = m.composition.astype(np.float64)
+    before, after = a.T @ c.y0, a.T @ y.cpu().numpy()
+    assert np.all(np.abs(after - before) <= 1e-10 * before)
+
+
+def test_paper_test_mechanism_on_gpu(dev, oracle_mod):
+    """Section 4's mechanism (A gives B and C by two Arrhenius reactions, A = 1,
+    B = C = 0 plus 0.1 per flattened concentration index) against its closed form."""
+    m = synth.mechanism_from_lists(3, [([0], [(1, 1.0)], 0.05, 0.0, 0), ([0], [(2, 1.0)], 0.02, 0.0, 0)])
+    n = 100
+    y0 = (np.array([1.0, 0.0, 0.0])[None, :] + 0.1 * (np.arange(3 * n).reshape(n, 3) + 1)).T.copy()
+    cells = synth.Cells(T=np.full(n, 298.0), P=np.full(n, 1013.25), jscale=np.ones(n), y0=y0)
+    b = Batch(dev, m, cells, oracle_mod=oracle_mod)
+    y = b.y_dev()
+    st, _ = b.cells.step(y, 60.0, mcchem.default_opts(atol=1e-14))
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    A = y0[0] * math.exp(-0.07 * 60.0)
+    exact = np.stack([A, y0[1] + 0.05 / 0.07 * (y0[0] - A), y0[2] + 0.02 / 0.07 * (y0[0] - A)])
+    assert _within(y.cpu().numpy(), exact, 1e-14) <= 1.0
+
+
+def test_large_mechanism_solve_parity(dev, oracle_mod):
+    m = synth.mech_large()
+    c = synth.make_cells(m, 6, seed=515)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    yg, sg, _, yo, so, _ = _solve_parity(b, 60.0)
+    assert np.all(so == 0) and np.all(sg == 0)
+    assert _within(yg, yo, 1.0) <= 1.0
+
+
+def test_status_codes_match_oracle(dev, oracle_mod):
+    m, c, dt = synth.workload("small10")
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    _, sg, statg, _, so, stato = _solve_parity(b, dt, {"max_steps": 1})
+    assert np.all(sg == 1) and np.all(so == 1)
+    _, sg, statg, _, so, stato = _solve_parity(b, dt, {"max_newton": 1, "h_min_rel": 1e-12})
+    assert np.all(sg == 2) and np.all(so == 2)
+    np.testing.assert_array_equal(statg["newton_fails"], stato["newton_fails"])
+    y0 = c.y0.copy()
+    y0[4, 3] = np.nan
+    yg, sg, _, _, so, _ = _solve_parity(b, dt, None, y0)
+    assert sg[3] == 4 and so[3] == 4
+    assert np.all(np.delete(sg, 3) == 0)
+
+
+def test_empty_batch_and_determinism(dev, oracle_mod):
+    m, c, dt = synth.workload("small10")
+    h = mcchem.Mechanism(m)
+    empty = mcchem.Cells(h, 0, 0)
+    T0 = torch.empty(0, dtype=torch.float64, device=dev)
+    empty.bind(T0)
+    y0 = torch.empty((m.n_species, 0), dtype=torch.float64, device=dev)
+    empty.deriv(y0)
+    empty.step(y0, dt)
+    empty.sync()
+    # same inputs twice -> identical bits; permuted cells -> permuted results
+    b = Batch(dev, m, c)
+    y1, y2 = b.y_dev(), b.y_dev()
+    b.cells.step(y1, dt)
+    b.cells.step(y2, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    perm = np.array([9, 3, 0, 5])
+    sub = synth.Cells(T=c.T[perm], P=c.P[perm], jscale=c.jscale[perm], y0=c.y0[:, perm])
+    bp = Batch(dev, m, sub)
+    yp = bp.y_dev()
+    bp.cells.step(yp, dt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(yp.cpu().numpy(), y1.cpu().numpy()[:, perm])
+
+
+def test_errors_before_bind_and_bad_args(dev):
+    m, c, dt = synth.workload("small10")
+    h = mcchem.Mechanism(m)
+    cells = mcchem.Cells(h, c.n_cells)
+    y = torch.from_numpy(c.y0).to(dev)
+    with pytest.raises(mcchem.MccError, match="status 5"):
+        cells.deriv(y)
+    cells.bind(torch.from_numpy(c.T).to(dev))
+    with pytest.raises(mcchem.MccError, match="status 1"):
+        cells.step(y, -1.0)
+    with pytest.raises(mcchem.MccError, match="status 1"):
+        cells.step(y, dt, mcchem.default_opts(max_order=6))
+    with pytest.raises(mcchem.MccError, match="status 5"):
+        h.close()  # a batch is still alive
+    cells.close()
+    h.close()
