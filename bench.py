@@ -28,6 +28,29 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 
+SOLVE_SOURCES = ["paper_2501_00011_amd/csrc/kernels_solve.hip", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
+                 "paper_2501_00011_amd/csrc/mech_compile.cpp"]
+FJ_SOURCES = ["paper_2501_00011_amd/csrc/kernels_fj.hip", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
+              "paper_2501_00011_amd/csrc/mech_compile.cpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_medium10k.txt")
+
+
+def measured_traffic(kernel, sources):
+    """HBM bytes per launch measured with rocprofv3 counters for this workload,
+    or None when the kernel's sources changed since the measurement."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["traffic_bytes"] if h.hexdigest()[:16] == rec["source_sha256_16"] else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,22 +73,24 @@ def cpu_baseline(m, c, dt, target_s):
         oracle.build()
     o = oracle.Oracle(m)
     threads = o.max_threads()
-    # calibration on one cell per thread, then a sample sized to the target time
-    n0 = min(c.n_cells, threads)
-    sel = np.arange(n0)
-    k = o.rate_constants(c.T[sel], c.jscale[sel])
-    t0 = time.perf_counter()
-    o.solve(k, c.y0[:, sel], dt)
-    per_round = time.perf_counter() - t0
-    n = int(min(c.n_cells, max(n0, threads * max(1, int(target_s / max(per_round, 1e-6))))))
-    sel = np.arange(n)
-    k = o.rate_constants(c.T[sel], c.jscale[sel])
-    t0 = time.perf_counter()
-    _, st, _ = o.solve(k, c.y0[:, sel], dt)
-    wall = time.perf_counter() - t0
+    # one untimed warm-up round, then consecutive chunks until the target time
+    chunk = max(1, 4 * threads)
+    warm = min(c.n_cells, threads)
+    sel = np.arange(warm)
+    o.solve(o.rate_constants(c.T[sel], c.jscale[sel]), c.y0[:, sel], dt)
+    start, n, wall, failed = warm, 0, 0.0, 0
+    while wall < target_s and start < c.n_cells:
+        sel = np.arange(start, min(c.n_cells, start + chunk))
+        k = o.rate_constants(c.T[sel], c.jscale[sel])
+        t0 = time.perf_counter()
+        _, st, _ = o.solve(k, c.y0[:, sel], dt)
+        wall += time.perf_counter() - t0
+        failed += int((st != 0).sum())
+        n += len(sel)
+        start += len(sel)
     return {"value": n / wall, "unit": "cell-timesteps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {c.n_cells} cells, one {dt:g} s step each, "
-                      f"{wall:.1f} s wall on {threads} OpenMP threads ({int((st != 0).sum())} failed)"}
+            "sample": f"cells {warm}..{warm + n - 1} of {c.n_cells}, one {dt:g} s step each, "
+                      f"{wall:.1f} s wall on {threads} OpenMP threads ({failed} failed)"}
 
 
 def main():
@@ -159,11 +184,12 @@ def main():
                    "rtol": opts.rtol, "atol": opts.atol},
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": measured_traffic("bdf_kernel", SOLVE_SOURCES) if C == 10000 else None,
                      "launch_ms": solve_s * 1e3, "flops_per_launch": flops},
         "fj_roofline": {"kernel": "fj_kernel (calc_deriv_jac)", "bound": "hbm", "achieved": fj_gbs,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
-                        "traffic": None, "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
+                        "traffic": measured_traffic("fj_kernel", FJ_SOURCES) if C == 10000 else None, "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
         "solver": {"failed_cells": int((st != 0).sum()),
                    "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),
                    "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),

@@ -16,7 +16,7 @@
  *     one structure, f_ik = sum_j (dy_ik/dt)_j for species i of cell k; the
  *     reaction data lives in GPU memory from initialisation on; the device
  *     limits are checked at run time.
- *   Section 5 (Conclusions): move the Jacobian and the solver onto the GPU and
+ *   Section 6 (Conclusions): move the Jacobian and the solver onto the GPU and
  *     move data only at the start and end of the solve -- which is what this
  *     library does: state stays in device memory across f, J and solver calls.
  *
@@ -167,6 +167,21 @@ mcc_status mcc_mech_op_counts(const mcc_mech *mech, mcc_op_counts *counts);
  * concentration index s (J_is = d f_i / d y_s). */
 mcc_status mcc_mech_jac_pattern(const mcc_mech *mech, int32_t *row_ptr, int32_t *col_idx);
 
+/* Testing aid (host only, works on a device -1 handle): runs the solver's
+ * table-driven phases for one cell on the host exactly as the kernel
+ * sequences them -- f at y, the Newton matrix M = I - c J(y), its sparse LU
+ * and x = M^-1 b -- and counts table violations (offsets out of range,
+ * reads or writes of an entry written by another op of the same LU level).
+ * k [n_reactions], y, b, f, x [n_species] host arrays in species order.
+ * *violations receives the count (0 for a sound schedule). */
+mcc_status mcc_debug_emulate_cell(const mcc_mech *mech, const double *k, const double *y, double c,
+                                  const double *b, double *f, double *x, int32_t *violations);
+
+/* Testing aid: sizes of the solver schedule, written to out[0..7]: LU
+ * blocks, LU levels, Newton-matrix blocks, f-gather blocks of slots 0..3,
+ * and the LU multiply-add count. */
+mcc_status mcc_debug_schedule_info(const mcc_mech *mech, int64_t *out);
+
 /* Release a mechanism.  MCC_ERR_STATE if cell batches created from it are
  * still alive (nothing is released then). */
 mcc_status mcc_mech_destroy(mcc_mech *mech);
@@ -203,7 +218,7 @@ mcc_status mcc_calc_deriv_jac(const mcc_cells *cells, const double *y, double *f
 /* One outer step of length dt > 0 for every cell: each cell integrates
  * y' = f(y) from 0 to dt on its own with the variable-order BDF method and a
  * Newton iteration on a sparse LU of I - (h/gamma_k) J (Section 2: solver
- * with a sparse Jacobian; Section 5: the whole solve on the GPU).
+ * with a sparse Jacobian; Section 6: the whole solve on the GPU).
  * y: device [n_species][ld], overwritten with y(dt).  cell_status: device
  * int32 [n_cells] (mcc_cell_status).  stats: device mcc_cell_stats
  * [n_cells] or NULL.  opts: host, NULL = defaults.  A cell that fails keeps

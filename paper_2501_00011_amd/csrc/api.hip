@@ -17,14 +17,10 @@ struct mcc_mech {
     const int32_t *rxn_type = nullptr, *out_ptr = nullptr, *term_idx = nullptr, *fj_chunks = nullptr;
     const double *A = nullptr, *theta = nullptr, *term_coef = nullptr;
     const int32_t *perm = nullptr, *rx_reac = nullptr, *part = nullptr;
-    const int32_t *fg_w = nullptr, *fg_off = nullptr, *fg_idx = nullptr;
-    const double *fg_coef = nullptr;
-    const int32_t *jg_dest = nullptr, *jg_w = nullptr, *jg_off = nullptr, *jg_idx = nullptr;
-    const double *jg_coef = nullptr;
-    const int32_t *lu_diag = nullptr, *lcol_ptr = nullptr, *lcol_off = nullptr, *upd_ptr = nullptr;
-    const uint64_t *upd = nullptr;
+    const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
+    const uint64_t *lu_ops = nullptr;
     const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
-    int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, off_invd = 0, lds_doubles = 0;
+    int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, lds_doubles = 0;
     int live_batches = 0;
 };
 
@@ -137,8 +133,7 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->off_r = m->off_k + t.R;
     m->off_p = m->off_r + t.R + 1;
     m->off_lu = m->off_p + t.n_partials + 1;
-    m->off_invd = m->off_lu + t.lu_nnz + 2;
-    m->lds_doubles = m->off_invd + t.N;
+    m->lds_doubles = m->off_lu + t.lu_nnz + 2;
     if (device == -1) {  // host-only: validated and compiled, nothing uploaded
         *out = m;
         return ok();
@@ -182,11 +177,7 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     const size_t o_optr = pk.add(t.out_ptr), o_tidx = pk.add(t.term_idx), o_tcoef = pk.add(t.term_coef);
     const size_t o_chunks = pk.add(t.fj_chunks);
     const size_t o_perm = pk.add(t.perm), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
-    const size_t o_fgw = pk.add(t.fg_w), o_fgo = pk.add(t.fg_off), o_fgi = pk.add(t.fg_idx), o_fgc = pk.add(t.fg_coef);
-    const size_t o_jgd = pk.add(t.jg_dest), o_jgw = pk.add(t.jg_w), o_jgo = pk.add(t.jg_off);
-    const size_t o_jgi = pk.add(t.jg_idx), o_jgc = pk.add(t.jg_coef);
-    const size_t o_lud = pk.add(t.lu_diag), o_lcp = pk.add(t.lcol_ptr), o_lco = pk.add(t.lcol_off);
-    const size_t o_upp = pk.add(t.upd_ptr), o_upd = pk.add(t.upd);
+    const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
     const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
     if ((e = hipMalloc(&m->dev_buf, pk.bytes.size())) != hipSuccess) {
         delete m;
@@ -208,20 +199,9 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->perm = (const int32_t *)(b + o_perm);
     m->rx_reac = (const int32_t *)(b + o_rxr);
     m->part = (const int32_t *)(b + o_part);
-    m->fg_w = (const int32_t *)(b + o_fgw);
-    m->fg_off = (const int32_t *)(b + o_fgo);
-    m->fg_idx = (const int32_t *)(b + o_fgi);
-    m->fg_coef = (const double *)(b + o_fgc);
-    m->jg_dest = (const int32_t *)(b + o_jgd);
-    m->jg_w = (const int32_t *)(b + o_jgw);
-    m->jg_off = (const int32_t *)(b + o_jgo);
-    m->jg_idx = (const int32_t *)(b + o_jgi);
-    m->jg_coef = (const double *)(b + o_jgc);
-    m->lu_diag = (const int32_t *)(b + o_lud);
-    m->lcol_ptr = (const int32_t *)(b + o_lcp);
-    m->lcol_off = (const int32_t *)(b + o_lco);
-    m->upd_ptr = (const int32_t *)(b + o_upp);
-    m->upd = (const uint64_t *)(b + o_upd);
+    m->fg_ops = (const Op16 *)(b + o_fg);
+    m->nm_ops = (const Op16 *)(b + o_nm);
+    m->lu_ops = (const uint64_t *)(b + o_lu);
     m->fwd_map = (const uint16_t *)(b + o_fwd);
     m->bwd_map = (const uint16_t *)(b + o_bwd);
     *out = m;
@@ -244,6 +224,26 @@ mcc_status mcc_mech_op_counts(const mcc_mech *m, mcc_op_counts *counts)
 {
     if (!m || !counts) return set_error(MCC_ERR_INVALID_ARG, "null argument");
     *counts = m->t.counts;
+    return ok();
+}
+
+mcc_status mcc_debug_emulate_cell(const mcc_mech *m, const double *k, const double *y, double c, const double *b,
+                                  double *f, double *x, int32_t *violations)
+{
+    if (!m || (!k && m->t.R > 0) || !y || !b || !f || !x || !violations)
+        return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    *violations = emulate_cell(m->t, k, y, c, b, f, x);
+    return ok();
+}
+
+mcc_status mcc_debug_schedule_info(const mcc_mech *m, int64_t *out)
+{
+    if (!m || !out) return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    out[0] = m->t.lu_blocks;
+    out[1] = m->t.lu_steps;
+    out[2] = m->t.nm_blocks;
+    for (int q = 0; q < 4; ++q) out[3 + q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
+    out[7] = m->t.lu_updates;
     return ok();
 }
 
@@ -420,33 +420,27 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     p.perm = m->perm;
     p.rx_reac = m->rx_reac;
     p.part = m->part;
-    p.fg_w = m->fg_w;
-    p.fg_off = m->fg_off;
-    p.fg_idx = m->fg_idx;
-    p.fg_coef = m->fg_coef;
-    p.jg_dest = m->jg_dest;
-    p.jg_w = m->jg_w;
-    p.jg_off = m->jg_off;
-    p.jg_idx = m->jg_idx;
-    p.jg_coef = m->jg_coef;
-    p.lu_diag = m->lu_diag;
-    p.lcol_ptr = m->lcol_ptr;
-    p.lcol_off = m->lcol_off;
-    p.upd_ptr = m->upd_ptr;
-    p.upd = m->upd;
+    p.fg_ops = m->fg_ops;
+    p.nm_ops = m->nm_ops;
+    p.lu_ops = m->lu_ops;
     p.fwd_map = m->fwd_map;
     p.bwd_map = m->bwd_map;
+    for (int q = 0; q < kMaxSlots; ++q) {
+        p.fg_blocks[q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
+        p.fg_base[q] = q < m->t.NS ? m->t.fg_base[q] : 0;
+    }
+    p.nm_blocks = m->t.nm_blocks;
+    p.lu_blocks = m->t.lu_blocks;
+    p.NP = m->t.NP;
     p.N = m->t.N;
     p.R = m->t.R;
     p.P = m->t.n_partials;
     p.lu_nnz = m->t.lu_nnz;
-    p.n_jpass = (int32_t)m->t.jg_w.size();
     p.off_y = m->off_y;
     p.off_k = m->off_k;
     p.off_r = m->off_r;
     p.off_p = m->off_p;
     p.off_lu = m->off_lu;
-    p.off_invd = m->off_invd;
     p.lds_doubles = m->lds_doubles;
     p.k = c->k;
     p.y = y;

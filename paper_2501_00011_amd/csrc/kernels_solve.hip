@@ -8,7 +8,7 @@
 // simplified Newton iteration on a freshly evaluated Jacobian at every step
 // attempt; Shampine & Reichelt 1997, kappa = 0; Hairer-Norsett-Wanner starting
 // step).  It is the per-cell solve of Section 2 (an implicit solver with a
-// sparse Jacobian) moved entirely onto the GPU as Section 5 proposes: the
+// sparse Jacobian) moved entirely onto the GPU as Section 6 proposes: the
 // state never leaves the device between f, J and linear-solver calls.
 //
 // Per-cell storage
@@ -17,7 +17,8 @@
 //               differences D[0..7], the Newton correction, weights, ...
 //   LDS       : the evaluation point y (+ the constant 1 at index N), the
 //               cell's rate constants, reaction rates, rate partials, the LU
-//               factors (+ a zero cell and a write-only cell) and 1/U_kk.
+//               factors (1/U_kk in place of U_kk; + a zero cell and a
+//               write-only cell).
 //   HBM       : only y in/out, k in, status and stats out.
 #include "mcc_internal.hpp"
 
@@ -52,16 +53,50 @@ __device__ inline double bdf_gamma(int j)
     return g;
 }
 
+// Reads one lane's op stream, laid out [block][lane][kBlk] in global memory,
+// one block ahead of its use: the next block's loads are in flight while the
+// current block's LDS work runs, so table latency stays off the critical path.
+template <class T>
+struct Prefetcher {
+    const T *base;
+    int lane, nblk, blk;
+    T nxt[kBlk];
+
+    __device__ void start(const T *b, int ln, int nb)
+    {
+        base = b;
+        lane = ln;
+        nblk = nb;
+        blk = 0;
+        if (nb > 0) fetch(0);
+    }
+    __device__ void fetch(int bi)
+    {
+        const T *q = base + ((size_t)bi * kWave + lane) * kBlk;
+#pragma unroll
+        for (int i = 0; i < kBlk; ++i) nxt[i] = q[i];
+    }
+    __device__ void take(T (&cur)[kBlk])
+    {
+#pragma unroll
+        for (int i = 0; i < kBlk; ++i) cur[i] = nxt[i];
+        ++blk;
+        if (blk < nblk) fetch(blk);
+    }
+};
+
+__device__ inline int off_at(uint32_t v, int sh) { return (int)((v >> sh) & kOffMask); }
+
 template <int NS>
 struct Cell {
     const SolveParams &p;
-    double *yv, *kv, *rv, *pv, *lu, *invd;
+    double *yv, *kv, *rv, *pv, *lu;
     int lane;
     int N;
 
     __device__ Cell(const SolveParams &pp, double *smem)
         : p(pp), yv(smem + pp.off_y), kv(smem + pp.off_k), rv(smem + pp.off_r), pv(smem + pp.off_p),
-          lu(smem + pp.off_lu), invd(smem + pp.off_invd), lane((int)threadIdx.x), N(pp.N) {}
+          lu(smem + pp.off_lu), lane((int)threadIdx.x), N(pp.N) {}
 
     __device__ bool valid(int s) const { return s * kWave + lane < N; }
 
@@ -80,19 +115,39 @@ struct Cell {
     {
         put_y(v);
         const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
-        for (int j = lane; j < p.R; j += kWave) {
-            const int4 a = rx[j];
-            double r = kv[j] * yv[a.x];
-            r *= yv[a.y];
-            r *= yv[a.z];
-            rv[j] = r;
+        for (int j0 = 0; j0 < p.R; j0 += 4 * kWave) {
+            int4 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * kWave + lane;
+                a[u] = j < p.R ? rx[j] : make_int4(N, N, N, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * kWave + lane;
+                if (j < p.R) {
+                    double r = kv[j] * yv[a[u].x];
+                    r *= yv[a[u].y];
+                    r *= yv[a[u].z];
+                    rv[j] = r;
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            Prefetcher<Op16> st;
+            st.start(p.fg_ops + (size_t)p.fg_base[s] * kWave * kBlk, lane, p.fg_blocks[s]);
             double acc = 0.0;
-            const int W = p.fg_w[s], base = p.fg_off[s] + lane;
-            for (int t = 0; t < W; ++t) acc += p.fg_coef[base + t * kWave] * rv[p.fg_idx[base + t * kWave]];
+            for (int b = 0; b < p.fg_blocks[s]; ++b) {
+                Op16 op[kBlk];
+                st.take(op);
+                double r[kBlk];
+#pragma unroll
+                for (int i = 0; i < kBlk; ++i) r[i] = rv[op[i].meta];
+#pragma unroll
+                for (int i = 0; i < kBlk; ++i) acc += op[i].coef * r[i];
+            }
             f[s] = acc;
         }
     }
@@ -102,77 +157,168 @@ struct Cell {
     {
         put_y(v);
         const int4 *pt = reinterpret_cast<const int4 *>(p.part);
-        for (int q = lane; q < p.P; q += kWave) {
-            const int4 a = pt[q];
-            double d = kv[a.x] * yv[a.y];
-            d *= yv[a.z];
-            pv[q] = d;
+        for (int q0 = 0; q0 < p.P; q0 += 4 * kWave) {
+            int4 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * kWave + lane;
+                a[u] = q < p.P ? pt[q] : make_int4(0, N, N, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * kWave + lane;
+                if (q < p.P) {
+                    double d = kv[a[u].x] * yv[a[u].y];
+                    d *= yv[a[u].z];
+                    pv[q] = d;
+                }
+            }
         }
         __syncthreads();
-        for (int ps = 0; ps < p.n_jpass; ++ps) {
-            const int dest = p.jg_dest[ps * kWave + lane];
-            const int W = p.jg_w[ps], base = p.jg_off[ps] + lane;
-            double acc = 0.0;
-            for (int t = 0; t < W; ++t) acc += p.jg_coef[base + t * kWave] * pv[p.jg_idx[base + t * kWave]];
-            const double m = -c * acc;
-            lu[dest & 0xffff] = (dest & (1 << 30)) ? 1.0 + m : m;
+        Prefetcher<Op16> st;
+        st.start(p.nm_ops, lane, p.nm_blocks);
+        double acc = 0.0;
+        for (int b = 0; b < p.nm_blocks; ++b) {
+            Op16 op[kBlk];
+            st.take(op);
+            double x[kBlk];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) x[i] = pv[op[i].meta & kOffMask];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) {
+                const uint32_t fl = op[i].meta >> 28;
+                acc = (fl & kFirst) ? op[i].coef * x[i] : acc + op[i].coef * x[i];
+                if (fl & kLast) {
+                    const double m = -c * acc;
+                    lu[off_at(op[i].meta, kOffBits)] = (fl & kDiag) ? 1.0 + m : m;
+                }
+            }
         }
         __syncthreads();
     }
 
-    // Right-looking LU with the static (diagonal) pivot order.  Returns true
-    // if a pivot is zero, tiny or not finite (uniform across the wavefront).
+    // Level-scheduled right-looking LU with the static diagonal pivot order.
+    // Each op: acc = a[dst] (first of a chain); acc -= a[l] * a[d] * a[u]
+    // (a[d] holds 1/U_kk) or acc *= a[d] (column scaling); a[dst] = acc, or
+    // 1/acc when it completes a pivot (last of a chain).  All operands of a
+    // block are read before any of its writes: inside one level no op reads
+    // what another op of that level writes.  Returns true if a pivot is
+    // zero, tiny or not finite (uniform across the wavefront).
     __device__ bool factor()
     {
-        for (int k = 0; k < N; ++k) {
-            const double dk = lu[p.lu_diag[k]];
-            if (!(fabs(dk) >= 1e-300) || !isfinite(dk)) return true;
-            const double inv = 1.0 / dk;
-            if (lane == 0) invd[k] = inv;
-            const int l0 = p.lcol_ptr[k], l1 = p.lcol_ptr[k + 1];
-            for (int t = l0 + lane; t < l1; t += kWave) lu[p.lcol_off[t]] *= inv;
-            __syncthreads();
-            const int u0 = p.upd_ptr[k], u1 = p.upd_ptr[k + 1];
-            for (int t = u0 + lane; t < u1; t += kWave) {
-                const uint64_t w = p.upd[t];
-                const int dst = (int)(w & 0xffff), l = (int)((w >> 16) & 0xffff), u = (int)((w >> 32) & 0xffff);
-                lu[dst] -= lu[l] * lu[u];
+        Prefetcher<uint64_t> st;
+        st.start(p.lu_ops, lane, p.lu_blocks);
+        double acc = 0.0;
+        int bad = 0;
+        for (int b = 0; b < p.lu_blocks; ++b) {
+            uint64_t op[kBlk];
+            st.take(op);
+            double ad[kBlk], al[kBlk], au[kBlk], ag[kBlk];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) {
+                const uint32_t lo = (uint32_t)op[i], hi = (uint32_t)(op[i] >> 32);
+                ad[i] = lu[lo & kOffMask];
+                al[i] = lu[(lo >> kOffBits) & kOffMask];
+                au[i] = lu[((lo >> 28) | (hi << 4)) & kOffMask];
+                ag[i] = lu[(hi >> 10) & kOffMask];
             }
-            __syncthreads();
+            bool any_recip = false;
+            double res[kBlk];
+            int dst[kBlk];
+            bool store[kBlk], recip[kBlk];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) {
+                const uint32_t fl = (uint32_t)(op[i] >> 56);
+                const double a0 = (fl & kFirst) ? ad[i] : acc;
+                acc = (fl & kScale) ? a0 * ag[i] : a0 - (al[i] * ag[i]) * au[i];
+                res[i] = acc;
+                dst[i] = (int)(op[i] & kOffMask);
+                store[i] = fl & kLast;
+                recip[i] = fl & kRecip;
+                any_recip |= recip[i];
+            }
+            if (__any(any_recip)) {
+#pragma unroll
+                for (int i = 0; i < kBlk; ++i)
+                    if (recip[i]) {
+                        bad |= !(fabs(res[i]) >= 1e-300) || !isfinite(res[i]);
+                        res[i] = 1.0 / res[i];
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i)
+                if (store[i]) lu[dst[i]] = res[i];
+            const bool barrier = (op[kBlk - 1] >> 56) & kBarrier;
+            if (__builtin_amdgcn_readfirstlane((int)barrier)) __syncthreads();
         }
-        return false;
+        return __any(bad);
     }
 
-    // b <- (LU)^-1 b, b held in registers by position; the pivot value of
-    // each column is broadcast from its lane with readlane.
+    // b <- (LU)^-1 b with b held in registers by position.  Column k's value
+    // is broadcast from its lane with readlane; the LU offsets of 8 columns
+    // come with one 16-byte load per slot, one block ahead.
     __device__ void solve(double (&b)[NS])
     {
+        const int NPB = p.NP / 8;
+        const uint4 *fw = reinterpret_cast<const uint4 *>(p.fwd_map);
+        const uint4 *bw = reinterpret_cast<const uint4 *>(p.bwd_map);
 #pragma unroll
         for (int ks = 0; ks < NS; ++ks) {
-#pragma unroll 2
-            for (int kl = 0; kl < kWave; ++kl) {
-                const int k = ks * kWave + kl;
-                if (k >= N) break;
-                const double xk = lane_bcast(b[ks], kl);
+            const int b0 = ks * 8, b1 = min(NPB, ks * 8 + 8);
+            uint4 nxt[NS];
+#pragma unroll
+            for (int s = ks; s < NS; ++s) nxt[s] = fw[(size_t)(s * kWave + lane) * NPB + b0];
+            for (int blk = b0; blk < b1; ++blk) {
+                double v[NS][8];
 #pragma unroll
                 for (int s = ks; s < NS; ++s) {
-                    const int off = p.fwd_map[((size_t)k * NS + s) * kWave + lane];
-                    b[s] -= lu[off] * xk;
+                    const uint4 o = nxt[s];
+                    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                }
+                if (blk + 1 < b1)
+#pragma unroll
+                    for (int s = ks; s < NS; ++s) nxt[s] = fw[(size_t)(s * kWave + lane) * NPB + blk + 1];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int kl = (blk - b0) * 8 + i;
+                    if (ks * kWave + kl >= N) break;
+                    const double xk = lane_bcast(b[ks], kl);
+#pragma unroll
+                    for (int s = ks; s < NS; ++s) b[s] -= v[s][i] * xk;
                 }
             }
         }
 #pragma unroll
         for (int ks = NS - 1; ks >= 0; --ks) {
-#pragma unroll 2
-            for (int kl = kWave - 1; kl >= 0; --kl) {
-                const int k = ks * kWave + kl;
-                if (k >= N) continue;
-                const double xk = lane_bcast(b[ks], kl) * invd[k];
-                if (lane == kl) b[ks] = xk;
+            const int b0 = ks * 8, b1 = min(NPB, ks * 8 + 8);
+            uint4 nxt[NS];
+#pragma unroll
+            for (int s = 0; s <= ks; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NPB + b1 - 1];
+            for (int blk = b1 - 1; blk >= b0; --blk) {
+                double v[NS][8];
 #pragma unroll
                 for (int s = 0; s <= ks; ++s) {
-                    const int off = p.bwd_map[((size_t)k * NS + s) * kWave + lane];
-                    b[s] -= lu[off] * xk;
+                    const uint4 o = nxt[s];
+                    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                }
+                if (blk - 1 >= b0)
+#pragma unroll
+                    for (int s = 0; s <= ks; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NPB + blk - 1];
+#pragma unroll
+                for (int i = 7; i >= 0; --i) {
+                    const int kl = (blk - b0) * 8 + i;
+                    if (ks * kWave + kl >= N) continue;
+                    // lane kl holds 1/U_kk in v[ks][i]
+                    const double xk = lane_bcast(b[ks] * v[ks][i], kl);
+#pragma unroll
+                    for (int s = 0; s <= ks; ++s) {
+                        const double nb = b[s] - v[s][i] * xk;
+                        b[s] = (s == ks && lane == kl) ? xk : nb;
+                    }
                 }
             }
         }
@@ -257,6 +403,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
         C.rv[p.R] = 0.0;
         C.pv[p.P] = 0.0;
         C.lu[p.lu_nnz] = 0.0;
+        C.lu[p.lu_nnz + 1] = 0.0;
     }
     int sp[NS];
     double D[kMaxOrder + 3][NS], f[NS], w[NS], ypred[NS], psi[NS], d[NS], tmp[NS];

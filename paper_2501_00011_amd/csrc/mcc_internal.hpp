@@ -15,6 +15,18 @@ namespace mcc {
 constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kMaxOrder = 5;  // BDF orders 1..5
 constexpr int kMaxSlots = 4;  // species slots per lane in the solver: N <= 256
+constexpr int kBlk = 4;       // ops per lane per prefetched block of an op stream
+constexpr int kOffBits = 14;  // bits of an LDS offset inside an op
+constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
+// op flags (bits 56.. of an LU op; bits 28.. of a 16-byte op's meta word)
+constexpr uint32_t kFirst = 1, kLast = 2, kRecip = 4, kScale = 8, kBarrier = 16, kDiag = 4;
+
+// A 16-byte op of the gather streams: coefficient and packed indices/flags.
+struct alignas(16) Op16 {
+    double coef;
+    uint32_t meta;  // source index | dst << kOffBits | flags << 28
+    uint32_t pad;
+};
 
 // ---------------------------------------------------------------------------
 // Host-side compiled mechanism (built once by compile_mechanism).
@@ -43,26 +55,32 @@ struct HostTables {
     std::vector<int32_t> iperm;       // iperm[species] = p
     std::vector<int32_t> rx_reac;     // [4 * R]: permuted reactant ids (N = one), pad
     std::vector<int32_t> part;        // [4 * P]: j, o1, o2, pad (other slots, N = one)
-    // f gather, ELL per slot: width fg_w[s]; entries [s][t][lane].
-    std::vector<int32_t> fg_w, fg_off, fg_idx;
-    std::vector<double> fg_coef;
-    // Newton-matrix gather over LU entries, ELL per pass of 64 entries.
-    std::vector<int32_t> jg_dest;     // [n_pass * 64]: LU offset | diag flag
-    std::vector<int32_t> jg_w, jg_off, jg_idx;
-    std::vector<double> jg_coef;
-    // LU: per pivot k, the diagonal offset, the L column (below diagonal) and
-    // the update triples (dst, l, u) packed 16/16/16 bits.
-    std::vector<int32_t> lu_diag, lcol_ptr, lcol_off, upd_ptr;
-    std::vector<uint64_t> upd;
-    // Triangular solves: [k][slot][lane] LU offset of L(p,k) (p > k) or
-    // U(p,k) (p < k), else the zero cell.
+    // Op streams, laid out [block][lane][kBlk] so that a lane prefetches one
+    // block (kBlk consecutive ops) with wide loads.
+    // f gather: one stream per species slot (fg_blocks[s] blocks from block fg_base[s]).
+    std::vector<Op16> fg_ops;
+    std::vector<int32_t> fg_blocks, fg_base;
+    // Newton matrix: chains of terms per LU entry.
+    std::vector<Op16> nm_ops;
+    int nm_blocks = 0;
+    // LU: level-scheduled update / reciprocal / scale ops, 14-bit offsets
+    // dst | l | u | d and flags in bits 56..; barrier flag ends a level.
+    std::vector<uint64_t> lu_ops;
+    int lu_blocks = 0, lu_steps = 0;
+    // Triangular solves: [slot][lane][NP] LU offsets (NP = N rounded up to 8).
     std::vector<uint16_t> fwd_map, bwd_map;
+    int NP = 0;
+    int64_t lu_lower = 0;
     int64_t lu_updates = 0;           // multiply-adds per factorisation
     mcc_op_counts counts{};           // algorithmic work per cell
 };
 
 // Validates desc and fills t.  Returns MCC_OK or MCC_ERR_MECH with *err set.
 mcc_status compile_mechanism(const mcc_mech_desc *desc, HostTables *t, std::string *err);
+
+// Host emulation of the solver's table-driven phases (testing aid).
+int emulate_cell(const HostTables &t, const double *k, const double *y_species, double c,
+                 const double *b_species, double *f_species, double *x_species);
 
 // ---------------------------------------------------------------------------
 // Device parameter blocks (passed by value as kernel arguments).
@@ -88,16 +106,14 @@ struct FJParams {
 struct SolveParams {
     // mechanism tables (device)
     const int32_t *perm, *rx_reac, *part;
-    const int32_t *fg_w, *fg_off, *fg_idx;
-    const double *fg_coef;
-    const int32_t *jg_dest, *jg_w, *jg_off, *jg_idx;
-    const double *jg_coef;
-    const int32_t *lu_diag, *lcol_ptr, *lcol_off, *upd_ptr;
-    const uint64_t *upd;
+    const Op16 *fg_ops, *nm_ops;
+    const uint64_t *lu_ops;
     const uint16_t *fwd_map, *bwd_map;
-    int32_t N, R, P, lu_nnz, n_jpass;
+    int32_t fg_blocks[kMaxSlots], fg_base[kMaxSlots];
+    int32_t nm_blocks, lu_blocks, NP;
+    int32_t N, R, P, lu_nnz;
     // LDS layout (offsets in doubles)
-    int32_t off_y, off_k, off_r, off_p, off_lu, off_invd, lds_doubles;
+    int32_t off_y, off_k, off_r, off_p, off_lu, lds_doubles;
     // batch
     const double *k;
     double *y;

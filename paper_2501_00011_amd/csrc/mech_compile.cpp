@@ -113,6 +113,54 @@ std::vector<int32_t> markowitz_order(const std::vector<std::vector<char>> &pat)
     return order;
 }
 
+Op16 make_op16(double coef, uint32_t meta)
+{
+    Op16 o;
+    o.coef = coef;
+    o.meta = meta;
+    o.pad = 0;
+    return o;
+}
+
+uint64_t lu_op(int dst, int l, int u, int dg, uint32_t flags)
+{
+    return (uint64_t)dst | ((uint64_t)l << kOffBits) | ((uint64_t)u << (2 * kOffBits)) |
+           ((uint64_t)dg << (3 * kOffBits)) | ((uint64_t)flags << 56);
+}
+
+// Longest-first greedy assignment of op chains to the 64 lanes of a wave.
+template <class T>
+std::vector<std::vector<T>> pack_chains(std::vector<std::vector<T>> &chains)
+{
+    std::vector<int> order(chains.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return chains[a].size() > chains[b].size(); });
+    std::vector<std::vector<T>> lanes(kWave);
+    for (int c : order) {
+        int best = 0;
+        for (int l = 1; l < kWave; ++l)
+            if (lanes[l].size() < lanes[best].size()) best = l;
+        lanes[best].insert(lanes[best].end(), chains[c].begin(), chains[c].end());
+    }
+    return lanes;
+}
+
+// Pads per-lane op lists to a common multiple of kBlk and appends them in the
+// [block][lane][kBlk] layout the kernels prefetch.  Returns the block count.
+template <class T>
+int emit_blocks(std::vector<std::vector<T>> &lanes, const T &pad, std::vector<T> *out)
+{
+    size_t len = 0;
+    for (auto &l : lanes) len = std::max(len, l.size());
+    len = (len + kBlk - 1) / kBlk * kBlk;
+    for (auto &l : lanes) l.resize(len, pad);
+    const int nb = (int)(len / kBlk);
+    for (int b = 0; b < nb; ++b)
+        for (int lane = 0; lane < kWave; ++lane)
+            for (int i = 0; i < kBlk; ++i) out->push_back(lanes[lane][(size_t)b * kBlk + i]);
+    return nb;
+}
+
 }  // namespace
 
 mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string *err)
@@ -233,8 +281,8 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         for (int j = 0; j < N; ++j)
             if (lp[i][j]) lpos[i][j] = nlu++;
     t->lu_nnz = nlu;
-    if (nlu + 2 > 65535) {
-        *err = "LU fill exceeds the 16-bit offset range of the solver tables";
+    if (nlu + 2 >= (1 << kOffBits)) {
+        *err = "LU fill exceeds the 14-bit offset range of the solver tables";
         return MCC_ERR_MECH;
     }
     const int ZERO = nlu;       // LDS cell holding 0.0
@@ -253,109 +301,156 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         t->part[4 * q + 1] = parts[q].o1 < N ? t->iperm[parts[q].o1] : N;
         t->part[4 * q + 2] = parts[q].o2 < N ? t->iperm[parts[q].o2] : N;
     }
+    const int P = (int)parts.size();
+    if (P + 1 >= (1 << kOffBits)) {
+        *err = "too many rate partials for the 14-bit offsets of the solver tables";
+        return MCC_ERR_MECH;
+    }
 
-    // ---- solver: f gather per slot (rv[R] is a zero rate) -----------------
+    // ---- solver: f gather, one chain per (slot, lane) ----------------------
     std::vector<std::vector<std::pair<int, double>>> fcon(N);
     for (int j = 0; j < R; ++j)
         for (const auto &kv : net_stoich(d, j))
             if (kv.second != 0.0) fcon[t->iperm[kv.first]].push_back({j, kv.second});
-    t->fg_w.assign(t->NS, 0);
-    t->fg_off.assign(t->NS, 0);
-    t->fg_idx.clear();
-    t->fg_coef.clear();
+    t->fg_ops.clear();
+    t->fg_blocks.assign(t->NS, 0);
+    t->fg_base.assign(t->NS, 0);
     for (int s = 0; s < t->NS; ++s) {
-        int w = 0;
+        std::vector<std::vector<Op16>> lanes(kWave);
         for (int lane = 0; lane < kWave; ++lane) {
             const int p = s * kWave + lane;
-            if (p < N) w = std::max(w, (int)fcon[p].size());
+            if (p < N)
+                for (const auto &c : fcon[p]) lanes[lane].push_back(make_op16(c.second, (uint32_t)c.first));
         }
-        t->fg_w[s] = w;
-        t->fg_off[s] = (int32_t)t->fg_idx.size();
-        for (int q = 0; q < w; ++q)
-            for (int lane = 0; lane < kWave; ++lane) {
-                const int p = s * kWave + lane;
-                const bool have = p < N && q < (int)fcon[p].size();
-                t->fg_idx.push_back(have ? fcon[p][q].first : R);
-                t->fg_coef.push_back(have ? fcon[p][q].second : 0.0);
-            }
+        t->fg_base[s] = (int32_t)(t->fg_ops.size() / (kWave * kBlk));
+        t->fg_blocks[s] = emit_blocks(lanes, make_op16(0.0, (uint32_t)R), &t->fg_ops);
     }
 
     // ---- solver: Newton-matrix gather over all LU entries -----------------
-    // LU entry (p, q) <- J entry (perm[p], perm[q]) if present; fill entries get 0.
-    struct Entry { int dest; bool diag; std::vector<std::pair<int, double>> terms; };
-    std::vector<Entry> entries(nlu);
-    for (int p = 0; p < N; ++p)
-        for (int q = 0; q < N; ++q)
-            if (lpos[p][q] >= 0) entries[lpos[p][q]] = {lpos[p][q], p == q, {}};
-    for (size_t qi = 0; qi < parts.size(); ++qi) {
-        const auto nu = net_stoich(d, parts[qi].j);
-        for (const auto &kv : nu)
-            if (kv.second != 0.0) {
-                const int e = lpos[t->iperm[kv.first]][t->iperm[parts[qi].s]];
-                entries[e].terms.push_back({(int)qi, kv.second});
-            }
-    }
-    std::vector<int> eorder(nlu);
-    std::iota(eorder.begin(), eorder.end(), 0);
-    std::stable_sort(eorder.begin(), eorder.end(), [&](int a, int b) {
-        return entries[a].terms.size() > entries[b].terms.size();
-    });
-    const int n_pass = (nlu + kWave - 1) / kWave;
-    t->jg_dest.assign((size_t)n_pass * kWave, TRASH);
-    t->jg_w.assign(n_pass, 0);
-    t->jg_off.assign(n_pass, 0);
-    t->jg_idx.clear();
-    t->jg_coef.clear();
-    const int P = (int)parts.size();
-    for (int ps = 0; ps < n_pass; ++ps) {
-        int w = 0;
-        for (int lane = 0; lane < kWave; ++lane) {
-            const int x = ps * kWave + lane;
-            if (x < nlu) {
-                const Entry &en = entries[eorder[x]];
-                t->jg_dest[(size_t)ps * kWave + lane] = en.dest | (en.diag ? (1 << 30) : 0);
-                w = std::max(w, (int)en.terms.size());
+    // Chain per LU entry: acc = sum coef * partial; entry = [diag] 1 - c acc.
+    // Fill entries are chains of one zero term (they are reset every time).
+    {
+        std::vector<std::vector<std::pair<int, double>>> eterms(nlu);
+        std::vector<char> ediag(nlu, 0);
+        for (int p = 0; p < N; ++p) ediag[lpos[p][p]] = 1;
+        for (int qi = 0; qi < P; ++qi)
+            for (const auto &kv : net_stoich(d, parts[qi].j))
+                if (kv.second != 0.0)
+                    eterms[lpos[t->iperm[kv.first]][t->iperm[parts[qi].s]]].push_back({qi, kv.second});
+        std::vector<std::vector<Op16>> chains(nlu);
+        for (int e = 0; e < nlu; ++e) {
+            auto &tl = eterms[e];
+            if (tl.empty()) tl.push_back({P, 0.0});
+            for (size_t q = 0; q < tl.size(); ++q) {
+                uint32_t fl = 0;
+                if (q == 0) fl |= kFirst;
+                if (q + 1 == tl.size()) fl |= kLast | (ediag[e] ? kDiag : 0u);
+                chains[e].push_back(make_op16(tl[q].second, (uint32_t)tl[q].first | ((uint32_t)e << kOffBits) | (fl << 28)));
             }
         }
-        t->jg_w[ps] = w;
-        t->jg_off[ps] = (int32_t)t->jg_idx.size();
-        for (int q = 0; q < w; ++q)
-            for (int lane = 0; lane < kWave; ++lane) {
-                const int x = ps * kWave + lane;
-                const bool have = x < nlu && q < (int)entries[eorder[x]].terms.size();
-                t->jg_idx.push_back(have ? entries[eorder[x]].terms[q].first : P);
-                t->jg_coef.push_back(have ? entries[eorder[x]].terms[q].second : 0.0);
-            }
+        auto lanes = pack_chains(chains);
+        t->nm_ops.clear();
+        t->nm_blocks = emit_blocks(lanes, make_op16(0.0, (uint32_t)P | ((uint32_t)TRASH << kOffBits)), &t->nm_ops);
     }
 
-    // ---- solver: right-looking LU schedule -------------------------------
-    t->lu_diag.assign(N, 0);
-    t->lcol_ptr.assign(1, 0);
-    t->upd_ptr.assign(1, 0);
-    t->lcol_off.clear();
-    t->upd.clear();
-    t->lu_updates = 0;
+    // ---- solver: level-scheduled right-looking LU -------------------------
+    // Pivot k depends on every earlier pivot that updates its row or column
+    // (L(k,k') or U(k',k) structurally nonzero).  Pivots of one level only
+    // write entries no other pivot of that level reads, so a level is one
+    // step between barriers.  Entries written by several pivots of a level
+    // are summed by one lane (a chain).  1/U_kk replaces U_kk in storage as
+    // soon as U_kk is final (flag on its last update, or in step 0 if nothing
+    // updates it); column k is scaled by it one level after pivot k.
+    std::vector<int> level(N, 1);
+    int maxlev = 0;
     for (int k = 0; k < N; ++k) {
-        t->lu_diag[k] = lpos[k][k];
-        std::vector<int> rows, cols;
-        for (int i = k + 1; i < N; ++i)
-            if (lp[i][k]) rows.push_back(i);
-        for (int j = k + 1; j < N; ++j)
-            if (lp[k][j]) cols.push_back(j);
-        for (int i : rows) t->lcol_off.push_back(lpos[i][k]);
-        for (int i : rows)
-            for (int j : cols) {
-                const uint64_t dst = (uint64_t)lpos[i][j], l = (uint64_t)lpos[i][k], u = (uint64_t)lpos[k][j];
-                t->upd.push_back(dst | (l << 16) | (u << 32));
-            }
-        t->lu_updates += (int64_t)rows.size() * (int64_t)cols.size();
-        t->lcol_ptr.push_back((int32_t)t->lcol_off.size());
-        t->upd_ptr.push_back((int32_t)t->upd.size());
+        for (int q = 0; q < k; ++q)
+            if (lp[k][q] || lp[q][k]) level[k] = std::max(level[k], level[q] + 1);
+        maxlev = std::max(maxlev, level[k]);
     }
+    std::vector<int> diag_last(N, 0);  // level of the last update of (k,k)
+    for (int q = 0; q < N; ++q)
+        for (int k = q + 1; k < N; ++k)
+            if (lp[k][q] && lp[q][k]) diag_last[k] = std::max(diag_last[k], level[q]);
+    t->lu_ops.clear();
+    t->lu_updates = 0;
+    t->lu_steps = 0;
+    const uint64_t NOP = lu_op(TRASH, ZERO, ZERO, ZERO, kFirst | kLast);
+    auto emit_step = [&](std::vector<std::vector<uint64_t>> &chains) {
+        if (chains.empty()) return;
+        auto lanes = pack_chains(chains);
+        size_t len = 0;
+        for (auto &l : lanes) len = std::max(len, l.size());
+        len = (len + kBlk - 1) / kBlk * kBlk;
+        for (auto &l : lanes) {
+            while (l.size() < len) l.push_back(NOP);
+            l.back() |= (uint64_t)kBarrier << 56;
+        }
+        emit_blocks(lanes, NOP, &t->lu_ops);
+        t->lu_steps++;
+    };
+    {
+        std::vector<std::vector<uint64_t>> chains;
+        for (int k = 0; k < N; ++k)
+            if (diag_last[k] == 0) chains.push_back({lu_op(lpos[k][k], ZERO, ZERO, ZERO, kFirst | kLast | kRecip)});
+        emit_step(chains);
+    }
+    for (int L = 1; L <= maxlev + 1; ++L) {
+        std::map<int, std::vector<uint64_t>> by_dst;
+        std::vector<std::vector<uint64_t>> chains;
+        for (int k = 0; k < N; ++k) {
+            if (level[k] == L - 1)  // scale column k of a pivot finished one level ago
+                for (int i = k + 1; i < N; ++i)
+                    if (lp[i][k]) chains.push_back({lu_op(lpos[i][k], ZERO, ZERO, lpos[k][k], kFirst | kLast | kScale)});
+            if (level[k] != L) continue;
+            for (int i = k + 1; i < N; ++i) {
+                if (!lp[i][k]) continue;
+                for (int j = k + 1; j < N; ++j) {
+                    if (!lp[k][j]) continue;
+                    by_dst[lpos[i][j]].push_back(lu_op(lpos[i][j], lpos[i][k], lpos[k][j], lpos[k][k], 0));
+                    t->lu_updates++;
+                }
+            }
+        }
+        for (auto &kv : by_dst) {
+            auto &c = kv.second;
+            c.front() |= (uint64_t)kFirst << 56;
+            c.back() |= (uint64_t)kLast << 56;
+            int dst = kv.first;
+            // diagonal entry whose last update happens at this level
+            for (int k = 0; k < N; ++k)
+                if (lpos[k][k] == dst && diag_last[k] == L) c.back() |= (uint64_t)kRecip << 56;
+            chains.push_back(c);
+        }
+        emit_step(chains);
+    }
+    t->lu_blocks = (int)(t->lu_ops.size() / (kWave * kBlk));
+
+    // ---- solver: column maps for the triangular solves ---------------------
+    // [slot][lane][NP]: offset of L(p,k) (p > k) for the forward sweep; of
+    // U(p,k) (p < k) or of the stored 1/U_kk (p == k) for the backward sweep.
+    t->NP = (N + 7) / 8 * 8;
+    const size_t map_n = (size_t)t->NS * kWave * t->NP;
+    t->fwd_map.assign(map_n, (uint16_t)ZERO);
+    t->bwd_map.assign(map_n, (uint16_t)ZERO);
+    for (int s = 0; s < t->NS; ++s)
+        for (int lane = 0; lane < kWave; ++lane) {
+            const int p = s * kWave + lane;
+            if (p >= N) continue;
+            for (int k = 0; k < N; ++k) {
+                const size_t at = ((size_t)s * kWave + lane) * t->NP + k;
+                if (p > k && lp[p][k]) t->fwd_map[at] = (uint16_t)lpos[p][k];
+                if (p <= k && lp[p][k]) t->bwd_map[at] = (uint16_t)lpos[p][k];
+            }
+        }
+    t->lu_lower = 0;
+    for (int p = 0; p < N; ++p)
+        for (int q = 0; q < p; ++q) t->lu_lower += lp[p][q];
 
     // ---- algorithmic work per cell -----------------------------------------
     {
         int64_t prod_mults = 0, part_mults = 0, n_fterms = 0, n_jterms = 0, n_lower = 0, n_upper = 0;
+        (void)TRASH;
         for (int j = 0; j < R; ++j) {
             const int a = d->reac_ptr[j + 1] - d->reac_ptr[j];
             prod_mults += a;
@@ -380,19 +475,6 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         oc.reserved = 0;
     }
 
-    // ---- solver: dense column maps for the triangular solves ---------------
-    const size_t map_n = (size_t)N * t->NS * kWave;
-    t->fwd_map.assign(map_n, (uint16_t)ZERO);
-    t->bwd_map.assign(map_n, (uint16_t)ZERO);
-    for (int k = 0; k < N; ++k)
-        for (int s = 0; s < t->NS; ++s)
-            for (int lane = 0; lane < kWave; ++lane) {
-                const int p = s * kWave + lane;
-                if (p >= N) continue;
-                const size_t at = ((size_t)k * t->NS + s) * kWave + lane;
-                if (p > k && lp[p][k]) t->fwd_map[at] = (uint16_t)lpos[p][k];
-                if (p < k && lp[p][k]) t->bwd_map[at] = (uint16_t)lpos[p][k];
-            }
     return MCC_OK;
 }
 

@@ -1,0 +1,155 @@
+// Host emulation of the solver kernel's table-driven phases, for testing the
+// mechanism compiler without a GPU.  It runs the same op streams with the same
+// semantics as the kernel (one array per LDS region, 64 lanes, blocks of kBlk
+// ops whose operands are all read before any of their writes, a barrier at
+// the end of each LU level) and checks on the way that every offset is in
+// range and that no op reads or writes what another op of the same LU level
+// writes.
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "mcc_internal.hpp"
+
+namespace mcc {
+
+// Returns the number of violations found (bounds or same-level hazards).
+int emulate_cell(const HostTables &t, const double *k, const double *y_species, double c,
+                 const double *b_species, double *f_species, double *x_species)
+{
+    const int N = t.N, R = t.R, P = t.n_partials, NS = t.NS;
+    const int ZERO = t.lu_nnz, TRASH = t.lu_nnz + 1;
+    int bad = 0;
+    std::vector<double> yv(N + 1), rv(R + 1, 0.0), pv(P + 1, 0.0), lu(t.lu_nnz + 2, 0.0);
+    for (int p = 0; p < N; ++p) yv[p] = y_species[t.perm[p]];
+    yv[N] = 1.0;
+    auto chk = [&](long v, long n) {
+        if (v < 0 || v >= n) bad++;
+        return v < 0 || v >= n ? 0 : v;
+    };
+
+    // deriv: rates then the per-slot gathers
+    for (int j = 0; j < R; ++j) {
+        double r = k[j] * yv[chk(t.rx_reac[4 * j], N + 1)];
+        r *= yv[chk(t.rx_reac[4 * j + 1], N + 1)];
+        r *= yv[chk(t.rx_reac[4 * j + 2], N + 1)];
+        rv[j] = r;
+    }
+    for (int s = 0; s < NS; ++s)
+        for (int lane = 0; lane < kWave; ++lane) {
+            double acc = 0.0;
+            for (int bk = 0; bk < t.fg_blocks[s]; ++bk)
+                for (int i = 0; i < kBlk; ++i) {
+                    const Op16 &o = t.fg_ops[(((size_t)(t.fg_base[s] + bk)) * kWave + lane) * kBlk + i];
+                    acc += o.coef * rv[chk(o.meta, R + 1)];
+                }
+            const int p = s * kWave + lane;
+            if (p < N) f_species[t.perm[p]] = acc;
+        }
+
+    // Newton matrix
+    for (int q = 0; q < P; ++q) {
+        double d = k[chk(t.part[4 * q], R)] * yv[chk(t.part[4 * q + 1], N + 1)];
+        d *= yv[chk(t.part[4 * q + 2], N + 1)];
+        pv[q] = d;
+    }
+    std::vector<int> written(t.lu_nnz + 2, 0);
+    for (int lane = 0; lane < kWave; ++lane) {
+        double acc = 0.0;
+        for (int bk = 0; bk < t.nm_blocks; ++bk)
+            for (int i = 0; i < kBlk; ++i) {
+                const Op16 &o = t.nm_ops[((size_t)bk * kWave + lane) * kBlk + i];
+                const uint32_t fl = o.meta >> 28;
+                const double x = pv[chk(o.meta & kOffMask, P + 1)];
+                acc = (fl & kFirst) ? o.coef * x : acc + o.coef * x;
+                if (fl & kLast) {
+                    const int dst = chk((o.meta >> kOffBits) & kOffMask, t.lu_nnz + 2);
+                    if (dst == ZERO) bad++;
+                    if (dst < t.lu_nnz) written[dst]++;
+                    const double m = -c * acc;
+                    lu[dst] = (fl & kDiag) ? 1.0 + m : m;
+                }
+            }
+    }
+    for (int e = 0; e < t.lu_nnz; ++e)
+        if (written[e] != 1) bad++;  // every LU entry is set exactly once
+    lu[ZERO] = 0.0;
+
+    // LU: blocks of all lanes, reads before writes, barrier per level
+    std::vector<double> acc(kWave, 0.0);
+    std::set<int> operand_reads, step_writes;  // per LU level
+    for (int bk = 0; bk < t.lu_blocks; ++bk) {
+        std::vector<double> res(kWave * kBlk);
+        std::vector<int> dsts(kWave * kBlk), store(kWave * kBlk);
+        for (int lane = 0; lane < kWave; ++lane)
+            for (int i = 0; i < kBlk; ++i) {
+                const uint64_t w = t.lu_ops[((size_t)bk * kWave + lane) * kBlk + i];
+                const int dst = chk(w & kOffMask, t.lu_nnz + 2), l = chk((w >> 14) & kOffMask, t.lu_nnz + 2);
+                const int u = chk((w >> 28) & kOffMask, t.lu_nnz + 2), g = chk((w >> 42) & kOffMask, t.lu_nnz + 2);
+                const uint32_t fl = (uint32_t)(w >> 56);
+                const double a0 = (fl & kFirst) ? lu[dst] : acc[lane];
+                if (fl & kScale) {
+                    acc[lane] = a0 * lu[g];
+                    operand_reads.insert(g);
+                } else {
+                    acc[lane] = a0 - (lu[l] * lu[g]) * lu[u];
+                    operand_reads.insert(l);
+                    operand_reads.insert(u);
+                    operand_reads.insert(g);
+                }
+                double r = acc[lane];
+                if ((fl & kLast) && (fl & kRecip)) r = 1.0 / r;
+                res[lane * kBlk + i] = r;
+                dsts[lane * kBlk + i] = dst;
+                store[lane * kBlk + i] = (fl & kLast) != 0;
+            }
+        for (int q = 0; q < kWave * kBlk; ++q)
+            if (store[q]) {
+                const int dst = dsts[q];
+                if (dst != TRASH) {
+                    if (dst == ZERO || step_writes.count(dst)) bad++;  // zero cell or written twice
+                    step_writes.insert(dst);
+                }
+                lu[dst] = res[q];
+            }
+        // the barrier flag must be the same on every lane
+        const uint64_t first_lane = t.lu_ops[((size_t)bk * kWave) * kBlk + kBlk - 1];
+        for (int lane = 1; lane < kWave; ++lane)
+            if (((t.lu_ops[((size_t)bk * kWave + lane) * kBlk + kBlk - 1] ^ first_lane) >> 56) & kBarrier) bad++;
+        if ((first_lane >> 56) & kBarrier) {
+            // an operand (l, u or 1/U_kk) written in the same level is a hazard
+            for (int rd : operand_reads)
+                if (rd != TRASH && rd != ZERO && step_writes.count(rd)) bad++;
+            operand_reads.clear();
+            step_writes.clear();
+        }
+    }
+    if (!step_writes.empty()) bad++;  // the last level must end with a barrier
+
+    // triangular solves on b (positions)
+    std::vector<double> bp(N);
+    for (int p = 0; p < N; ++p) bp[p] = b_species[t.perm[p]];
+    auto map_at = [&](const std::vector<uint16_t> &m, int p, int kk) {
+        const int s = p / kWave, lane = p % kWave;
+        return (int)chk(m[((size_t)s * kWave + lane) * t.NP + kk], t.lu_nnz + 2);
+    };
+    for (int kk = 0; kk < N; ++kk) {
+        const double xk = bp[kk];
+        for (int p = 0; p < N; ++p) bp[p] -= lu[map_at(t.fwd_map, p, kk)] * xk;  // p <= kk: zero cell
+    }
+    for (int kk = N - 1; kk >= 0; --kk) {
+        const double xk = bp[kk] * lu[map_at(t.bwd_map, kk, kk)];
+        for (int p = 0; p < N; ++p) {
+            if (p == kk)
+                bp[p] = xk;
+            else
+                bp[p] -= lu[map_at(t.bwd_map, p, kk)] * xk;
+        }
+    }
+    for (int p = 0; p < N; ++p) x_species[t.perm[p]] = bp[p];
+    return bad;
+}
+
+}  // namespace mcc

@@ -67,6 +67,8 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_mech_info": ([vp, pi32, pi32, pi32, pi32, pi32], ctypes.c_int),
         "mcc_mech_jac_pattern": ([vp, vp, vp], ctypes.c_int),
         "mcc_mech_op_counts": ([vp, vp], ctypes.c_int),
+        "mcc_debug_emulate_cell": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_debug_schedule_info": ([vp, vp], ctypes.c_int),
         "mcc_mech_destroy": ([vp], ctypes.c_int),
         "mcc_cells_create": ([vp, i64, i64, vp], ctypes.c_int),
         "mcc_cells_bind": ([vp, vp, vp, vp, vp], ctypes.c_int),
@@ -149,6 +151,27 @@ class Mechanism:
         names = ["deriv_flops", "newton_matrix_flops", "lu_flops", "solve_flops",
                  "fj_bytes", "f_bytes", "j_bytes"]
         return dict(zip(names, list(buf)[:7]))
+
+    def emulate_cell(self, k, y, c, b):
+        """Host emulation of the solver phases for one cell (testing aid):
+        returns (f, x = (I - c J)^-1 b, violations)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        f = np.zeros(self.n_species)
+        x = np.zeros(self.n_species)
+        v = ctypes.c_int32()
+        _check(library().mcc_debug_emulate_cell(self._h, k.ctypes.data, y.ctypes.data, float(c), b.ctypes.data,
+                                                f.ctypes.data, x.ctypes.data, ctypes.byref(v)))
+        return f, x, v.value
+
+    def schedule_info(self) -> dict:
+        """Sizes of the solver schedule (testing aid)."""
+        buf = (ctypes.c_int64 * 8)()
+        _check(library().mcc_debug_schedule_info(self._h, ctypes.addressof(buf)))
+        v = list(buf)
+        return {"lu_blocks": v[0], "lu_levels": v[1], "nm_blocks": v[2], "fg_blocks": v[3:7],
+                "lu_updates": v[7]}
 
     def jac_pattern(self):
         rp = np.zeros(self.n_species + 1, dtype=np.int32)
