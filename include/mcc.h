@@ -179,7 +179,7 @@ mcc_status mcc_debug_emulate_cell(const mcc_mech *mech, const double *k, const d
 
 /* Testing aid: sizes of the solver schedule, written to out[0..7]: LU
  * blocks, LU levels, Newton-matrix blocks, f-gather blocks of slots 0..3,
- * and the LU multiply-add count. */
+ * and the size of the dense tail factorised in registers. */
 mcc_status mcc_debug_schedule_info(const mcc_mech *mech, int64_t *out);
 
 /* Release a mechanism.  MCC_ERR_STATE if cell batches created from it are

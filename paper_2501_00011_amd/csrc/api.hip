@@ -16,11 +16,11 @@ struct mcc_mech {
     // device views
     const int32_t *rxn_type = nullptr, *out_ptr = nullptr, *term_idx = nullptr, *fj_chunks = nullptr;
     const double *A = nullptr, *theta = nullptr, *term_coef = nullptr;
-    const int32_t *perm = nullptr, *rx_reac = nullptr, *part = nullptr;
+    const int32_t *vspecies = nullptr, *rx_reac = nullptr, *part = nullptr;
     const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
     const uint64_t *lu_ops = nullptr;
     const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
-    int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, lds_doubles = 0;
+    int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, off_tm = 0, lds_doubles = 0;
     int live_batches = 0;
 };
 
@@ -129,11 +129,12 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
 
     // LDS layout of one solver cell (doubles).
     m->off_y = 0;
-    m->off_k = t.N + 1;
+    m->off_k = t.NV + 1;
     m->off_r = m->off_k + t.R;
     m->off_p = m->off_r + t.R + 1;
     m->off_lu = m->off_p + t.n_partials + 1;
-    m->lds_doubles = m->off_lu + t.lu_nnz + 2;
+    m->off_tm = m->off_lu + t.lu_nnz + 2;
+    m->lds_doubles = m->off_tm + (kMaxOrder + 1) * (kMaxOrder + 1);
     if (device == -1) {  // host-only: validated and compiled, nothing uploaded
         *out = m;
         return ok();
@@ -176,7 +177,7 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
     const size_t o_optr = pk.add(t.out_ptr), o_tidx = pk.add(t.term_idx), o_tcoef = pk.add(t.term_coef);
     const size_t o_chunks = pk.add(t.fj_chunks);
-    const size_t o_perm = pk.add(t.perm), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
+    const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
     const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
     if ((e = hipMalloc(&m->dev_buf, pk.bytes.size())) != hipSuccess) {
@@ -196,7 +197,7 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->term_idx = (const int32_t *)(b + o_tidx);
     m->term_coef = (const double *)(b + o_tcoef);
     m->fj_chunks = (const int32_t *)(b + o_chunks);
-    m->perm = (const int32_t *)(b + o_perm);
+    m->vspecies = (const int32_t *)(b + o_perm);
     m->rx_reac = (const int32_t *)(b + o_rxr);
     m->part = (const int32_t *)(b + o_part);
     m->fg_ops = (const Op16 *)(b + o_fg);
@@ -243,7 +244,7 @@ mcc_status mcc_debug_schedule_info(const mcc_mech *m, int64_t *out)
     out[1] = m->t.lu_steps;
     out[2] = m->t.nm_blocks;
     for (int q = 0; q < 4; ++q) out[3 + q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
-    out[7] = m->t.lu_updates;
+    out[7] = m->t.M;
     return ok();
 }
 
@@ -417,7 +418,7 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     const mcc_mech *m = c->mech;
     DeviceGuard g(m->device);
     SolveParams p{};
-    p.perm = m->perm;
+    p.vspecies = m->vspecies;
     p.rx_reac = m->rx_reac;
     p.part = m->part;
     p.fg_ops = m->fg_ops;
@@ -428,10 +429,12 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     for (int q = 0; q < kMaxSlots; ++q) {
         p.fg_blocks[q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
         p.fg_base[q] = q < m->t.NS ? m->t.fg_base[q] : 0;
+        p.slot_cols[q] = q < m->t.NS ? m->t.slot_cols[q] : 0;
     }
     p.nm_blocks = m->t.nm_blocks;
     p.lu_blocks = m->t.lu_blocks;
-    p.NP = m->t.NP;
+    p.NV = m->t.NV;
+    p.tail_base = m->t.tail_base;
     p.N = m->t.N;
     p.R = m->t.R;
     p.P = m->t.n_partials;
@@ -441,6 +444,7 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     p.off_r = m->off_r;
     p.off_p = m->off_p;
     p.off_lu = m->off_lu;
+    p.off_tm = m->off_tm;
     p.lds_doubles = m->lds_doubles;
     p.k = c->k;
     p.y = y;
@@ -450,7 +454,7 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     p.ld = c->ld;
     p.dt = dt;
     p.opts = o;
-    hipError_t e = launch_solve(p, m->t.NS, (hipStream_t)stream);
+    hipError_t e = launch_solve(p, m->t.NS, m->t.M, (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "solver kernel launch");
     return ok();
 }

@@ -12,41 +12,44 @@
 // state never leaves the device between f, J and linear-solver calls.
 //
 // Per-cell storage
-//   registers : position p = s*64 + lane of every per-species vector (p in
-//               the fill-reducing order), s = 0..NS-1: the backward
-//               differences D[0..7], the Newton correction, weights, ...
-//   LDS       : the evaluation point y (+ the constant 1 at index N), the
-//               cell's rate constants, reaction rates, rate partials, the LU
-//               factors (1/U_kk in place of U_kk; + a zero cell and a
-//               write-only cell).
+//   registers : every per-species vector at virtual index v = s*64 + lane,
+//               s = 0..NS-1 (the mechanism compiler maps species to v): the
+//               backward differences D[0..7], the Newton correction, ...;
+//               during the factorisation also the dense tail of the LU
+//               (lane = row).
+//   LDS       : the evaluation point y by virtual index (+ the constant 1),
+//               the cell's rate constants, reaction rates, rate partials, the
+//               LU factors (1/U_kk in place of U_kk; the tail block
+//               column-major; + a zero cell and a write-only cell), and the
+//               6 x 6 transform of a step-size change.
 //   HBM       : only y in/out, k in, status and stats out.
 #include "mcc_internal.hpp"
 
 namespace mcc {
 namespace {
 
-__device__ inline double wave_sum(double v)
+__device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
     return __shfl(v, 0);  // lane 0's sum on every lane: bitwise uniform
 }
 
-__device__ inline double wave_min(double v)
+__device__ __forceinline__ double wave_min(double v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
     return __shfl(v, 0);
 }
 
-__device__ inline double lane_bcast(double v, int src_lane)
+__device__ __forceinline__ double lane_bcast(double v, int src_lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src_lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src_lane);
     return __hiloint2double(hi, lo);
 }
 
-__device__ inline double bdf_gamma(int j)
+__device__ __forceinline__ double bdf_gamma(int j)
 {
     double g = 0.0;
     for (int i = 1; i <= j; ++i) g += 1.0 / i;
@@ -62,7 +65,7 @@ struct Prefetcher {
     int lane, nblk, blk;
     T nxt[kBlk];
 
-    __device__ void start(const T *b, int ln, int nb)
+    __device__ __forceinline__ void start(const T *b, int ln, int nb)
     {
         base = b;
         lane = ln;
@@ -70,13 +73,13 @@ struct Prefetcher {
         blk = 0;
         if (nb > 0) fetch(0);
     }
-    __device__ void fetch(int bi)
+    __device__ __forceinline__ void fetch(int bi)
     {
         const T *q = base + ((size_t)bi * kWave + lane) * kBlk;
 #pragma unroll
         for (int i = 0; i < kBlk; ++i) nxt[i] = q[i];
     }
-    __device__ void take(T (&cur)[kBlk])
+    __device__ __forceinline__ void take(T (&cur)[kBlk])
     {
 #pragma unroll
         for (int i = 0; i < kBlk; ++i) cur[i] = nxt[i];
@@ -85,33 +88,41 @@ struct Prefetcher {
     }
 };
 
-__device__ inline int off_at(uint32_t v, int sh) { return (int)((v >> sh) & kOffMask); }
+__device__ __forceinline__ int off_at(uint32_t v, int sh) { return (int)((v >> sh) & kOffMask); }
 
-template <int NS>
+template <int NS, int M>
 struct Cell {
     const SolveParams &p;
-    double *yv, *kv, *rv, *pv, *lu;
+    double *yv, *kv, *rv, *pv, *lu, *tm;
     int lane;
     int N;
+    bool vld[NS];
 
     __device__ Cell(const SolveParams &pp, double *smem)
         : p(pp), yv(smem + pp.off_y), kv(smem + pp.off_k), rv(smem + pp.off_r), pv(smem + pp.off_p),
-          lu(smem + pp.off_lu), lane((int)threadIdx.x), N(pp.N) {}
+          lu(smem + pp.off_lu), tm(smem + pp.off_tm), lane((int)threadIdx.x), N(pp.N)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) vld[s] = pp.vspecies[s * kWave + lane] >= 0;
+    }
 
-    __device__ bool valid(int s) const { return s * kWave + lane < N; }
+    __device__ __forceinline__ bool valid(int s) const { return vld[s]; }
 
-    __device__ void put_y(const double (&v)[NS])
+    // order of slot s in the elimination order: the front slots 1.. come
+    // before the dense tail in slot 0
+    static constexpr int ord(int s) { return M > 0 ? (s == 0 ? NS - 1 : s - 1) : s; }
+
+    __device__ __forceinline__ void put_y(const double (&v)[NS])
     {
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
-            if (valid(s)) yv[s * kWave + lane] = v[s];
+        for (int s = 0; s < NS; ++s) yv[s * kWave + lane] = v[s];
         __syncthreads();
     }
 
     // f at v: reaction rates r_j = k_j y_a y_b y_c (lane per reaction), then
-    // f_p = sum nu r gathered per species position (lane per position).
-    __device__ void deriv(const double (&v)[NS], double (&f)[NS])
+    // f_v = sum nu r gathered per virtual index (lane per index).
+    __device__ __forceinline__ void deriv(const double (&v)[NS], double (&f)[NS])
     {
         put_y(v);
         const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
@@ -120,7 +131,7 @@ struct Cell {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + u * kWave + lane;
-                a[u] = j < p.R ? rx[j] : make_int4(N, N, N, 0);
+                a[u] = j < p.R ? rx[j] : make_int4(p.NV, p.NV, p.NV, 0);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -153,7 +164,7 @@ struct Cell {
     }
 
     // Newton matrix M = I - c J(v) written over the LU storage (fill = 0).
-    __device__ void newton_matrix(const double (&v)[NS], double c)
+    __device__ __forceinline__ void newton_matrix(const double (&v)[NS], double c)
     {
         put_y(v);
         const int4 *pt = reinterpret_cast<const int4 *>(p.part);
@@ -162,7 +173,7 @@ struct Cell {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u * kWave + lane;
-                a[u] = q < p.P ? pt[q] : make_int4(0, N, N, 0);
+                a[u] = q < p.P ? pt[q] : make_int4(0, p.NV, p.NV, 0);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -197,14 +208,15 @@ struct Cell {
         __syncthreads();
     }
 
-    // Level-scheduled right-looking LU with the static diagonal pivot order.
-    // Each op: acc = a[dst] (first of a chain); acc -= a[l] * a[d] * a[u]
-    // (a[d] holds 1/U_kk) or acc *= a[d] (column scaling); a[dst] = acc, or
-    // 1/acc when it completes a pivot (last of a chain).  All operands of a
-    // block are read before any of its writes: inside one level no op reads
-    // what another op of that level writes.  Returns true if a pivot is
-    // zero, tiny or not finite (uniform across the wavefront).
-    __device__ bool factor()
+    // Front pivots: level-scheduled right-looking sparse LU with the static
+    // diagonal pivot order.  Each op: acc = a[dst] (first of a chain);
+    // acc -= a[l] * a[d] * a[u] (a[d] holds 1/U_kk) or acc *= a[d] (column
+    // scaling); a[dst] = acc, or 1/acc when it completes a pivot (last of a
+    // chain).  All operands of a block are read before any of its writes:
+    // inside one level no op reads what another op of that level writes.
+    // Then the dense tail.  Returns true if a pivot is zero, tiny or not
+    // finite (uniform across the wavefront).
+    __device__ __forceinline__ bool factor()
     {
         Prefetcher<uint64_t> st;
         st.start(p.lu_ops, lane, p.lu_blocks);
@@ -251,80 +263,134 @@ struct Cell {
             const bool barrier = (op[kBlk - 1] >> 56) & kBarrier;
             if (__builtin_amdgcn_readfirstlane((int)barrier)) __syncthreads();
         }
-        return __any(bad);
+        const bool front_bad = __any(bad);
+        const bool tail_bad = dense_tail();
+        return front_bad || tail_bad;
     }
 
-    // b <- (LU)^-1 b with b held in registers by position.  Column k's value
-    // is broadcast from its lane with readlane; the LU offsets of 8 columns
-    // come with one 16-byte load per slot, one block ahead.
-    __device__ void solve(double (&b)[NS])
+    // Dense tail (the Schur complement left by the front pivots): lane r
+    // holds row r in registers; pivot row k is broadcast one value at a time
+    // with readlane.  1/U_kk replaces U_kk; the factors go back to the
+    // column-major LDS block (consecutive lanes, consecutive addresses).
+    __device__ __forceinline__ bool dense_tail()
     {
-        const int NPB = p.NP / 8;
+        if constexpr (M == 0) {
+            return false;
+        } else {
+            const bool in = lane < M;
+            double a[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) a[c] = in ? lu[p.tail_base + c * M + lane] : 0.0;
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const double ukk = lane_bcast(a[k], k);
+                bad |= !(fabs(ukk) >= 1e-300) || !isfinite(ukk);
+                const double inv = 1.0 / ukk;
+                if (lane > k && in) {
+                    const double l = a[k] * inv;
+                    a[k] = l;
+#pragma unroll
+                    for (int c = k + 1; c < M; ++c) a[c] -= l * lane_bcast(a[c], k);
+                }
+                if (lane == k) a[k] = inv;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                if (in) lu[p.tail_base + c * M + lane] = a[c];
+            __syncthreads();
+            return bad;
+        }
+    }
+
+    // b <- (LU)^-1 b with b held in registers by virtual index.  Columns are
+    // swept in elimination order (front slots, then the tail in slot 0);
+    // each column's value is broadcast from its lane with readlane; the LU
+    // offsets of 8 columns come with one 16-byte load per slot, one block
+    // ahead.
+    __device__ __forceinline__ void solve(double (&b)[NS])
+    {
+        const int NVB = p.NV / 8;
         const uint4 *fw = reinterpret_cast<const uint4 *>(p.fwd_map);
         const uint4 *bw = reinterpret_cast<const uint4 *>(p.bwd_map);
 #pragma unroll
-        for (int ks = 0; ks < NS; ++ks) {
-            const int b0 = ks * 8, b1 = min(NPB, ks * 8 + 8);
+        for (int t = 0; t < NS; ++t) {
+            const int ks = M > 0 ? (t + 1) % NS : t;
+            const int ncol = p.slot_cols[ks];
+            const int b0 = ks * 8, b1 = ks * 8 + (ncol + 7) / 8;
+            if (b0 >= b1) continue;
             uint4 nxt[NS];
 #pragma unroll
-            for (int s = ks; s < NS; ++s) nxt[s] = fw[(size_t)(s * kWave + lane) * NPB + b0];
+            for (int s = 0; s < NS; ++s)
+                if (ord(s) >= ord(ks)) nxt[s] = fw[(size_t)(s * kWave + lane) * NVB + b0];
             for (int blk = b0; blk < b1; ++blk) {
                 double v[NS][8];
 #pragma unroll
-                for (int s = ks; s < NS; ++s) {
-                    const uint4 o = nxt[s];
-                    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+                for (int s = 0; s < NS; ++s)
+                    if (ord(s) >= ord(ks)) {
+                        const uint4 o = nxt[s];
+                        const uint32_t w[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
-                }
+                        for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                    }
                 if (blk + 1 < b1)
 #pragma unroll
-                    for (int s = ks; s < NS; ++s) nxt[s] = fw[(size_t)(s * kWave + lane) * NPB + blk + 1];
+                    for (int s = 0; s < NS; ++s)
+                        if (ord(s) >= ord(ks)) nxt[s] = fw[(size_t)(s * kWave + lane) * NVB + blk + 1];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int kl = (blk - b0) * 8 + i;
-                    if (ks * kWave + kl >= N) break;
+                    if (kl >= ncol) break;
                     const double xk = lane_bcast(b[ks], kl);
 #pragma unroll
-                    for (int s = ks; s < NS; ++s) b[s] -= v[s][i] * xk;
+                    for (int s = 0; s < NS; ++s)
+                        if (ord(s) >= ord(ks)) b[s] -= v[s][i] * xk;
                 }
             }
         }
 #pragma unroll
-        for (int ks = NS - 1; ks >= 0; --ks) {
-            const int b0 = ks * 8, b1 = min(NPB, ks * 8 + 8);
+        for (int t = NS - 1; t >= 0; --t) {
+            const int ks = M > 0 ? (t + 1) % NS : t;
+            const int ncol = p.slot_cols[ks];
+            const int b0 = ks * 8, b1 = ks * 8 + (ncol + 7) / 8;
+            if (b0 >= b1) continue;
             uint4 nxt[NS];
 #pragma unroll
-            for (int s = 0; s <= ks; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NPB + b1 - 1];
+            for (int s = 0; s < NS; ++s)
+                if (ord(s) <= ord(ks)) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + b1 - 1];
             for (int blk = b1 - 1; blk >= b0; --blk) {
                 double v[NS][8];
 #pragma unroll
-                for (int s = 0; s <= ks; ++s) {
-                    const uint4 o = nxt[s];
-                    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+                for (int s = 0; s < NS; ++s)
+                    if (ord(s) <= ord(ks)) {
+                        const uint4 o = nxt[s];
+                        const uint32_t w[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
-                }
+                        for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                    }
                 if (blk - 1 >= b0)
 #pragma unroll
-                    for (int s = 0; s <= ks; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NPB + blk - 1];
+                    for (int s = 0; s < NS; ++s)
+                        if (ord(s) <= ord(ks)) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + blk - 1];
 #pragma unroll
                 for (int i = 7; i >= 0; --i) {
                     const int kl = (blk - b0) * 8 + i;
-                    if (ks * kWave + kl >= N) continue;
+                    if (kl >= ncol) continue;
                     // lane kl holds 1/U_kk in v[ks][i]
                     const double xk = lane_bcast(b[ks] * v[ks][i], kl);
 #pragma unroll
-                    for (int s = 0; s <= ks; ++s) {
-                        const double nb = b[s] - v[s][i] * xk;
-                        b[s] = (s == ks && lane == kl) ? xk : nb;
-                    }
+                    for (int s = 0; s < NS; ++s)
+                        if (ord(s) <= ord(ks)) {
+                            const double nb = b[s] - v[s][i] * xk;
+                            b[s] = (s == ks && lane == kl) ? xk : nb;
+                        }
                 }
             }
         }
     }
 
-    __device__ double wrms(const double (&v)[NS], const double (&w)[NS]) const
+    __device__ __forceinline__ double wrms(const double (&v)[NS], const double (&w)[NS]) const
     {
         double acc = 0.0;
 #pragma unroll
@@ -335,7 +401,7 @@ struct Cell {
         return sqrt(wave_sum(acc) / N);
     }
 
-    __device__ bool any_nonfinite(const double (&v)[NS]) const
+    __device__ __forceinline__ bool any_nonfinite(const double (&v)[NS]) const
     {
         int bad = 0;
 #pragma unroll
@@ -344,54 +410,55 @@ struct Cell {
     }
 };
 
-// Re-sample the backward differences D[0..order] from spacing h to rho*h.
-// First the interpolating polynomial is evaluated at the new points,
-//   V_i = p(t_n - i rho h) = sum_j c_ij D_j,  c_ij = prod_{m=1..j} (m - 1 - rho i) / m
-// (Newton's backward-difference form), then the new differences are taken,
-//   D'_i = sum_{l<=i} (-1)^l C(i, l) V_l.
+// Re-sample the backward differences D[0..order] from spacing h to rho*h:
+//   D'_i = sum_j T_ij D_j,  T_ij = sum_l R_jl U_li,
+//   R_jl = prod_{m=1..j} (m - 1 - rho l) / m,  U_li = prod_{m=1..l} (m - 1 - i) / m
+// (the interpolating polynomial's values at the new spacing, R, turned back
+// into differences by U = R(1), an involution).  Lane (i, j) of the first 36
+// lanes computes T_ij into LDS; every lane then applies T to its entries
+// with broadcast reads.
 template <int NS>
-__device__ void rescale(double (&D)[kMaxOrder + 3][NS], int order, double rho)
+__device__ __forceinline__ void rescale(double (&D)[kMaxOrder + 3][NS], int order, double rho, double *tm)
 {
-    constexpr int M = kMaxOrder + 1;
-    double V[M][NS];
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        double c = 1.0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) V[i][s] = D[0][s];
-#pragma unroll
-        for (int j = 1; j < M; ++j) {
-            c *= ((j - 1) - rho * i) / j;
-            if (j <= order)
-#pragma unroll
-                for (int s = 0; s < NS; ++s) V[i][s] += c * D[j][s];
+    constexpr int M6 = kMaxOrder + 1;
+    const int lane = (int)threadIdx.x;
+    __syncthreads();
+    if (lane < M6 * M6) {
+        const int i = lane / M6, j = lane % M6;
+        double acc = 0.0;
+        for (int l = 0; l <= order; ++l) {
+            double r = 1.0, u = 1.0;
+            for (int m = 1; m <= j; ++m) r *= ((m - 1) - rho * l) / m;
+            for (int m = 1; m <= l; ++m) u *= (double)((m - 1) - i) / m;
+            acc += r * u;
         }
+        tm[lane] = acc;
     }
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-        if (i <= order) {
+    for (int s = 0; s < NS; ++s) {
+        double out[M6];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                double acc = 0.0;
-                double binom = 1.0;  // C(i, l)
+        for (int i = 0; i < M6; ++i) {
+            double acc = 0.0;
 #pragma unroll
-                for (int l = 0; l <= i; ++l) {
-                    acc += ((l & 1) ? -binom : binom) * V[l][s];
-                    binom = binom * (i - l) / (l + 1);
-                }
-                D[i][s] = acc;
-            }
+            for (int j = 0; j < M6; ++j)
+                if (j <= order) acc += tm[i * M6 + j] * D[j][s];
+            out[i] = acc;
         }
+#pragma unroll
+        for (int i = 0; i < M6; ++i)
+            D[i][s] = i <= order ? out[i] : D[i][s];
     }
 }
 
-template <int NS>
+template <int NS, int M>
 __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
 {
     extern __shared__ double smem[];
     const int64_t cell = blockIdx.x;
     if (cell >= p.n_cells) return;
-    Cell<NS> C(p, smem);
+    Cell<NS, M> C(p, smem);
     const int lane = C.lane, N = p.N;
     const mcc_solver_opts &o = p.opts;
     const double dt = p.dt;
@@ -399,7 +466,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
 
     for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
     if (lane == 0) {
-        C.yv[N] = 1.0;
+        C.yv[p.NV] = 1.0;
         C.rv[p.R] = 0.0;
         C.pv[p.P] = 0.0;
         C.lu[p.lu_nnz] = 0.0;
@@ -409,7 +476,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
     double D[kMaxOrder + 3][NS], f[NS], w[NS], ypred[NS], psi[NS], d[NS], tmp[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        sp[s] = C.valid(s) ? p.perm[s * kWave + lane] : 0;
+        sp[s] = C.valid(s) ? p.vspecies[s * kWave + lane] : 0;
         const double y0 = C.valid(s) ? p.y[(int64_t)sp[s] * p.ld + cell] : 0.0;
 #pragma unroll
         for (int j = 0; j < kMaxOrder + 3; ++j) D[j][s] = 0.0;
@@ -470,7 +537,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                 landing = false;
                 if (h >= dt - t) {
                     const double hn = dt - t;
-                    rescale<NS>(D, order, hn / h);
+                    rescale<NS>(D, order, hn / h, C.tm);
                     h = hn;
                     n_equal = 0;
                     landing = true;
@@ -482,10 +549,10 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                     double yp = 0.0, ps = 0.0;
 #pragma unroll
                     for (int j = 0; j <= kMaxOrder; ++j)
-                        if (j <= order) yp += D[j][s];
+                        yp += j <= order ? D[j][s] : 0.0;
 #pragma unroll
                     for (int j = 1; j <= kMaxOrder; ++j)
-                        if (j <= order) ps += bdf_gamma(j) * D[j][s];
+                        ps += j <= order ? bdf_gamma(j) * D[j][s] : 0.0;
                     ypred[s] = yp;
                     psi[s] = ps / gk;
                     w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
@@ -526,7 +593,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                 }
                 if (!converged) {
                     newton_fails++;
-                    rescale<NS>(D, order, o.fac_newton_fail);
+                    rescale<NS>(D, order, o.fac_newton_fail, C.tm);
                     h *= o.fac_newton_fail;
                     n_equal = 0;
                     if (h < o.h_min_rel * dt || t + h == t) {
@@ -541,7 +608,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                     rejects++;
                     double fac = o.safety * pow(err_norm, -1.0 / (order + 1));
                     if (fac < o.fac_min) fac = o.fac_min;
-                    rescale<NS>(D, order, fac);
+                    rescale<NS>(D, order, fac, C.tm);
                     h *= fac;
                     n_equal = 0;
                     if (h < o.h_min_rel * dt || t + h == t) {
@@ -560,13 +627,13 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
             for (int s = 0; s < NS; ++s) {
 #pragma unroll
                 for (int j = 3; j < kMaxOrder + 3; ++j)
-                    if (j == order + 2) D[j][s] = d[s] - D[j - 1][s];
+                    D[j][s] = j == order + 2 ? d[s] - D[j - 1][s] : D[j][s];
 #pragma unroll
                 for (int j = 2; j < kMaxOrder + 2; ++j)
-                    if (j == order + 1) D[j][s] = d[s];
+                    D[j][s] = j == order + 1 ? d[s] : D[j][s];
 #pragma unroll
                 for (int j = kMaxOrder; j >= 0; --j)
-                    if (j <= order) D[j][s] += D[j + 1][s];
+                    D[j][s] = j <= order ? D[j][s] + D[j + 1][s] : D[j][s];
             }
             n_equal++;
             if (t >= dt) break;
@@ -579,7 +646,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                     double v = 0.0;
 #pragma unroll
                     for (int j = 1; j <= kMaxOrder; ++j)
-                        if (j == order) v = D[j][s];
+                        v += j == order ? D[j][s] : 0.0;
                     tmp[s] = v;
                 }
                 e_low = C.wrms(tmp, w) / order;
@@ -590,7 +657,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                     double v = 0.0;
 #pragma unroll
                     for (int j = 3; j < kMaxOrder + 3; ++j)
-                        if (j == order + 2) v = D[j][s];
+                        v += j == order + 2 ? D[j][s] : 0.0;
                     tmp[s] = v;
                 }
                 e_high = C.wrms(tmp, w) / (order + 2);
@@ -605,7 +672,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
             double fac = o.safety * best;
             if (fac > o.fac_max) fac = o.fac_max;
             order = new_order;
-            rescale<NS>(D, order, fac);
+            rescale<NS>(D, order, fac, C.tm);
             h *= fac;
             n_equal = 0;
         }
@@ -647,29 +714,36 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
 
 }  // namespace
 
+#define MCC_SOLVE_VARIANTS(X) \
+    X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 32) X(2, 32) X(3, 32) X(4, 32) \
+    X(1, 48) X(2, 48) X(3, 48) X(4, 48) X(1, 64) X(2, 64) X(3, 64) X(4, 64)
+
 hipError_t prepare_solve_kernels(int max_lds_bytes)
 {
-    hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)bdf_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void *)bdf_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes)) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void *)bdf_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes)) != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)bdf_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+    hipError_t e = hipSuccess;
+#define MCC_SET_LDS(ns, m)                                                                                    \
+    if (e == hipSuccess)                                                                                     \
+        e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                max_lds_bytes);
+    MCC_SOLVE_VARIANTS(MCC_SET_LDS)
+#undef MCC_SET_LDS
+    return e;
 }
 
-hipError_t launch_solve(const SolveParams &p, int NS, hipStream_t s)
+hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
 {
     if (p.n_cells == 0) return hipSuccess;
     if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)p.n_cells), block(kWave);
     const size_t lds = (size_t)p.lds_doubles * sizeof(double);
-    switch (NS) {
-    case 1: hipLaunchKernelGGL(bdf_kernel<1>, grid, block, lds, s, p); break;
-    case 2: hipLaunchKernelGGL(bdf_kernel<2>, grid, block, lds, s, p); break;
-    case 3: hipLaunchKernelGGL(bdf_kernel<3>, grid, block, lds, s, p); break;
-    case 4: hipLaunchKernelGGL(bdf_kernel<4>, grid, block, lds, s, p); break;
-    default: return hipErrorInvalidValue;
+#define MCC_LAUNCH(ns, m)                                                  \
+    if (NS == ns && M == m) {                                              \
+        hipLaunchKernelGGL((bdf_kernel<ns, m>), grid, block, lds, s, p); \
+        return hipGetLastError();                                          \
     }
-    return hipGetLastError();
+    MCC_SOLVE_VARIANTS(MCC_LAUNCH)
+#undef MCC_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 }  // namespace mcc

@@ -50,11 +50,19 @@ struct HostTables {
     std::vector<int32_t> fj_chunks;   // row boundaries of the work chunks
     int n_fchunks = 0, n_jchunks = 0; // f chunks first, then J chunks
 
-    // Solver, in the fill-reducing (permuted) order p = 0..N-1.
+    // Solver.  Positions p = 0..N-1 are the elimination (fill-reducing)
+    // order; every position lives at a virtual index v = slot * 64 + lane of
+    // the per-lane register vectors and of the LDS state vector.
     std::vector<int32_t> perm;        // perm[p] = species at position p
     std::vector<int32_t> iperm;       // iperm[species] = p
-    std::vector<int32_t> rx_reac;     // [4 * R]: permuted reactant ids (N = one), pad
-    std::vector<int32_t> part;        // [4 * P]: j, o1, o2, pad (other slots, N = one)
+    std::vector<int32_t> vspecies;    // [NV]: species at virtual index v, or -1
+    std::vector<int32_t> vpos;        // [N]: virtual index of position p
+    int NV = 0;                       // NS * 64
+    int M = 0, F = 0;                 // dense tail size and front size (F = N - M)
+    int tail_base = 0;                // LU offset of the column-major tail block
+    std::vector<int32_t> slot_cols;   // [NS]: columns (lanes) in use per slot
+    std::vector<int32_t> rx_reac;     // [4 * R]: virtual reactant ids (NV = one), pad
+    std::vector<int32_t> part;        // [4 * P]: j, o1, o2, pad (other slots, NV = one)
     // Op streams, laid out [block][lane][kBlk] so that a lane prefetches one
     // block (kBlk consecutive ops) with wide loads.
     // f gather: one stream per species slot (fg_blocks[s] blocks from block fg_base[s]).
@@ -67,10 +75,9 @@ struct HostTables {
     // dst | l | u | d and flags in bits 56..; barrier flag ends a level.
     std::vector<uint64_t> lu_ops;
     int lu_blocks = 0, lu_steps = 0;
-    // Triangular solves: [slot][lane][NP] LU offsets (NP = N rounded up to 8).
+    // Triangular solves: [slot][lane][NV] LU offsets per virtual column.
     std::vector<uint16_t> fwd_map, bwd_map;
-    int NP = 0;
-    int64_t lu_lower = 0;
+    int64_t lu_lower = 0, lu_upper = 0;  // strictly lower / upper nonzeros of the sparse factors
     int64_t lu_updates = 0;           // multiply-adds per factorisation
     mcc_op_counts counts{};           // algorithmic work per cell
 };
@@ -105,15 +112,15 @@ struct FJParams {
 
 struct SolveParams {
     // mechanism tables (device)
-    const int32_t *perm, *rx_reac, *part;
+    const int32_t *vspecies, *rx_reac, *part;
     const Op16 *fg_ops, *nm_ops;
     const uint64_t *lu_ops;
     const uint16_t *fwd_map, *bwd_map;
-    int32_t fg_blocks[kMaxSlots], fg_base[kMaxSlots];
-    int32_t nm_blocks, lu_blocks, NP;
+    int32_t fg_blocks[kMaxSlots], fg_base[kMaxSlots], slot_cols[kMaxSlots];
+    int32_t nm_blocks, lu_blocks, NV, tail_base;
     int32_t N, R, P, lu_nnz;
     // LDS layout (offsets in doubles)
-    int32_t off_y, off_k, off_r, off_p, off_lu, lds_doubles;
+    int32_t off_y, off_k, off_r, off_p, off_lu, off_tm, lds_doubles;
     // batch
     const double *k;
     double *y;
@@ -127,7 +134,7 @@ struct SolveParams {
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_rates(const RatesParams &p, hipStream_t s);
 hipError_t launch_fj(const FJParams &p, hipStream_t s);
-hipError_t launch_solve(const SolveParams &p, int NS, hipStream_t s);
+hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).
 hipError_t prepare_solve_kernels(int max_lds_bytes);
 

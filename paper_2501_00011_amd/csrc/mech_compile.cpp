@@ -16,6 +16,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <cstdlib>
 #include <numeric>
 #include <sstream>
 
@@ -262,7 +263,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     t->n_jchunks = (int)t->fj_chunks.size() - t->n_fchunks;
     t->fj_chunks.push_back(N + t->nnz);
 
-    // ---- fill-reducing order and symbolic LU (permuted order) -------------
+    // ---- fill-reducing order and symbolic LU (elimination positions) -------
     t->perm = markowitz_order(pat);
     t->iperm.assign(N, 0);
     for (int p = 0; p < N; ++p) t->iperm[t->perm[p]] = p;
@@ -275,11 +276,96 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
             if (lp[i][k])
                 for (int j = k + 1; j < N; ++j)
                     if (lp[k][j]) lp[i][j] = 1;
+    // algorithmic LU work, from the sparse symbolic factorisation
+    t->lu_updates = 0;
+    t->lu_lower = 0;
+    t->lu_upper = 0;
+    for (int k = 0; k < N; ++k) {
+        int64_t r = 0, c = 0;
+        for (int i = k + 1; i < N; ++i) r += lp[i][k];
+        for (int j = k + 1; j < N; ++j) c += lp[k][j];
+        t->lu_updates += r * c;
+        t->lu_lower += r;
+        t->lu_upper += c;
+    }
+
+    // ---- dense tail --------------------------------------------------------
+    // After the ordering the trailing block of the factors is nearly dense.
+    // Its last M pivots are factorised in registers (lane = row) and the
+    // first F = N - M pivots by the level-scheduled sparse op streams.  M is
+    // chosen from {0, 32, 48, 64} by a cost model (cycles of one wavefront:
+    // ~1000 per sparse block, ~8 per dense (pivot, column) pair) with the LDS
+    // the tail adds priced in; MCC_DENSE_TAIL overrides the choice.
+    auto tail_density = [&](int m) {
+        double nzc = 0;
+        for (int i = N - m; i < N; ++i)
+            for (int j = N - m; j < N; ++j) nzc += lp[i][j];
+        return m > 0 ? nzc / ((double)m * m) : 1.0;
+    };
+    auto front_cost = [&](int F) {
+        std::vector<int> lev(F, 1);
+        int maxl = 0;
+        int64_t ops = 0;
+        for (int k = 0; k < F; ++k) {
+            for (int q = 0; q < k; ++q)
+                if (lp[k][q] || lp[q][k]) lev[k] = std::max(lev[k], lev[q] + 1);
+            maxl = std::max(maxl, lev[k]);
+            int64_t r = 0, c = 0;
+            for (int i = k + 1; i < N; ++i) r += lp[i][k];
+            for (int j = k + 1; j < N; ++j) c += lp[k][j];
+            ops += r * c + r + 1;
+        }
+        return 1000.0 * std::max<double>(maxl + (F > 0 ? 2 : 0), (double)ops / (kWave * kBlk) * 1.5);
+    };
+    int M = 0;
+    {
+        double best = front_cost(N);
+        for (int m : {32, 48, 64}) {
+            if (m > N) continue;
+            const double extra_lds = (1.0 - tail_density(m)) * m * m * 8.0;  // bytes
+            const double cost = front_cost(N - m) + 8.0 * m * (m - 1) / 2 + 4.0 * extra_lds;
+            if (cost < best) {
+                best = cost;
+                M = m;
+            }
+        }
+        if (const char *env = std::getenv("MCC_DENSE_TAIL")) {
+            const int m = std::atoi(env);
+            if ((m == 0 || m == 32 || m == 48 || m == 64) && m <= N) M = m;
+        }
+    }
+    const int F = N - M;
+    t->M = M;
+    t->F = F;
+    for (int i = F; i < N; ++i)
+        for (int j = F; j < N; ++j) lp[i][j] = 1;  // the tail is stored dense
+
+    // ---- virtual (slot, lane) index of every position ----------------------
+    // With a dense tail, slot 0 lane r holds tail row r and the front
+    // positions fill slots 1..; otherwise position p is slot p/64, lane p%64.
+    t->NS = M > 0 ? 1 + (F + kWave - 1) / kWave : (N + kWave - 1) / kWave;
+    if (t->NS > kMaxSlots) {
+        *err = "too many species for the solver's register slots";
+        return MCC_ERR_MECH;
+    }
+    t->NV = t->NS * kWave;
+    std::vector<int> vpos(N);  // position -> virtual index
+    for (int p = 0; p < N; ++p) vpos[p] = M > 0 ? (p >= F ? p - F : kWave + p) : p;
+    t->vspecies.assign(t->NV, -1);
+    for (int p = 0; p < N; ++p) t->vspecies[vpos[p]] = t->perm[p];
+    t->vpos.assign(vpos.begin(), vpos.end());
+    auto vid = [&](int species) { return vpos[t->iperm[species]]; };
+    const int ONE = t->NV;  // yv[NV] holds the constant 1
+
+    // ---- LU storage: front entries row by row, then the tail column-major --
     std::vector<std::vector<int>> lpos(N, std::vector<int>(N, -1));
     int nlu = 0;
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j)
-            if (lp[i][j]) lpos[i][j] = nlu++;
+            if (lp[i][j] && !(i >= F && j >= F)) lpos[i][j] = nlu++;
+    t->tail_base = nlu;
+    for (int j = F; j < N; ++j)
+        for (int i = F; i < N; ++i) lpos[i][j] = nlu++;
     t->lu_nnz = nlu;
     if (nlu + 2 >= (1 << kOffBits)) {
         *err = "LU fill exceeds the 14-bit offset range of the solver tables";
@@ -288,18 +374,18 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     const int ZERO = nlu;       // LDS cell holding 0.0
     const int TRASH = nlu + 1;  // LDS cell written by idle lanes
 
-    // ---- solver: reactions and partials in permuted ids -------------------
-    t->rx_reac.assign(4 * (size_t)R, N);
+    // ---- solver: reactions and partials in virtual ids --------------------
+    t->rx_reac.assign(4 * (size_t)R, ONE);
     for (int j = 0; j < R; ++j) {
         const int b = d->reac_ptr[j], e = d->reac_ptr[j + 1];
-        for (int q = b; q < e; ++q) t->rx_reac[4 * j + (q - b)] = t->iperm[d->reac_idx[q]];
+        for (int q = b; q < e; ++q) t->rx_reac[4 * j + (q - b)] = vid(d->reac_idx[q]);
         t->rx_reac[4 * j + 3] = 0;
     }
     t->part.assign(4 * parts.size(), 0);
     for (size_t q = 0; q < parts.size(); ++q) {
         t->part[4 * q + 0] = parts[q].j;
-        t->part[4 * q + 1] = parts[q].o1 < N ? t->iperm[parts[q].o1] : N;
-        t->part[4 * q + 2] = parts[q].o2 < N ? t->iperm[parts[q].o2] : N;
+        t->part[4 * q + 1] = parts[q].o1 < N ? vid(parts[q].o1) : ONE;
+        t->part[4 * q + 2] = parts[q].o2 < N ? vid(parts[q].o2) : ONE;
     }
     const int P = (int)parts.size();
     if (P + 1 >= (1 << kOffBits)) {
@@ -308,20 +394,17 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     }
 
     // ---- solver: f gather, one chain per (slot, lane) ----------------------
-    std::vector<std::vector<std::pair<int, double>>> fcon(N);
+    std::vector<std::vector<std::pair<int, double>>> fcon(t->NV);
     for (int j = 0; j < R; ++j)
         for (const auto &kv : net_stoich(d, j))
-            if (kv.second != 0.0) fcon[t->iperm[kv.first]].push_back({j, kv.second});
+            if (kv.second != 0.0) fcon[vid(kv.first)].push_back({j, kv.second});
     t->fg_ops.clear();
     t->fg_blocks.assign(t->NS, 0);
     t->fg_base.assign(t->NS, 0);
     for (int s = 0; s < t->NS; ++s) {
         std::vector<std::vector<Op16>> lanes(kWave);
-        for (int lane = 0; lane < kWave; ++lane) {
-            const int p = s * kWave + lane;
-            if (p < N)
-                for (const auto &c : fcon[p]) lanes[lane].push_back(make_op16(c.second, (uint32_t)c.first));
-        }
+        for (int lane = 0; lane < kWave; ++lane)
+            for (const auto &c : fcon[s * kWave + lane]) lanes[lane].push_back(make_op16(c.second, (uint32_t)c.first));
         t->fg_base[s] = (int32_t)(t->fg_ops.size() / (kWave * kBlk));
         t->fg_blocks[s] = emit_blocks(lanes, make_op16(0.0, (uint32_t)R), &t->fg_ops);
     }
@@ -353,27 +436,27 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         t->nm_blocks = emit_blocks(lanes, make_op16(0.0, (uint32_t)P | ((uint32_t)TRASH << kOffBits)), &t->nm_ops);
     }
 
-    // ---- solver: level-scheduled right-looking LU -------------------------
+    // ---- solver: level-scheduled right-looking LU of the front pivots ------
     // Pivot k depends on every earlier pivot that updates its row or column
     // (L(k,k') or U(k',k) structurally nonzero).  Pivots of one level only
     // write entries no other pivot of that level reads, so a level is one
     // step between barriers.  Entries written by several pivots of a level
     // are summed by one lane (a chain).  1/U_kk replaces U_kk in storage as
     // soon as U_kk is final (flag on its last update, or in step 0 if nothing
-    // updates it); column k is scaled by it one level after pivot k.
-    std::vector<int> level(N, 1);
+    // updates it); column k is scaled by it one level after pivot k.  Updates
+    // into the tail block form its Schur complement.
+    std::vector<int> level(F, 1);
     int maxlev = 0;
-    for (int k = 0; k < N; ++k) {
+    for (int k = 0; k < F; ++k) {
         for (int q = 0; q < k; ++q)
             if (lp[k][q] || lp[q][k]) level[k] = std::max(level[k], level[q] + 1);
         maxlev = std::max(maxlev, level[k]);
     }
-    std::vector<int> diag_last(N, 0);  // level of the last update of (k,k)
-    for (int q = 0; q < N; ++q)
-        for (int k = q + 1; k < N; ++k)
+    std::vector<int> diag_last(F, 0);  // level of the last update of (k,k)
+    for (int q = 0; q < F; ++q)
+        for (int k = q + 1; k < F; ++k)
             if (lp[k][q] && lp[q][k]) diag_last[k] = std::max(diag_last[k], level[q]);
     t->lu_ops.clear();
-    t->lu_updates = 0;
     t->lu_steps = 0;
     const uint64_t NOP = lu_op(TRASH, ZERO, ZERO, ZERO, kFirst | kLast);
     auto emit_step = [&](std::vector<std::vector<uint64_t>> &chains) {
@@ -389,16 +472,16 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         emit_blocks(lanes, NOP, &t->lu_ops);
         t->lu_steps++;
     };
-    {
+    if (F > 0) {
         std::vector<std::vector<uint64_t>> chains;
-        for (int k = 0; k < N; ++k)
+        for (int k = 0; k < F; ++k)
             if (diag_last[k] == 0) chains.push_back({lu_op(lpos[k][k], ZERO, ZERO, ZERO, kFirst | kLast | kRecip)});
         emit_step(chains);
     }
-    for (int L = 1; L <= maxlev + 1; ++L) {
+    for (int L = 1; L <= maxlev + 1 && F > 0; ++L) {
         std::map<int, std::vector<uint64_t>> by_dst;
         std::vector<std::vector<uint64_t>> chains;
-        for (int k = 0; k < N; ++k) {
+        for (int k = 0; k < F; ++k) {
             if (level[k] == L - 1)  // scale column k of a pivot finished one level ago
                 for (int i = k + 1; i < N; ++i)
                     if (lp[i][k]) chains.push_back({lu_op(lpos[i][k], ZERO, ZERO, lpos[k][k], kFirst | kLast | kScale)});
@@ -408,7 +491,6 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
                 for (int j = k + 1; j < N; ++j) {
                     if (!lp[k][j]) continue;
                     by_dst[lpos[i][j]].push_back(lu_op(lpos[i][j], lpos[i][k], lpos[k][j], lpos[k][k], 0));
-                    t->lu_updates++;
                 }
             }
         }
@@ -416,9 +498,9 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
             auto &c = kv.second;
             c.front() |= (uint64_t)kFirst << 56;
             c.back() |= (uint64_t)kLast << 56;
-            int dst = kv.first;
-            // diagonal entry whose last update happens at this level
-            for (int k = 0; k < N; ++k)
+            const int dst = kv.first;
+            // front diagonal entry whose last update happens at this level
+            for (int k = 0; k < F; ++k)
                 if (lpos[k][k] == dst && diag_last[k] == L) c.back() |= (uint64_t)kRecip << 56;
             chains.push_back(c);
         }
@@ -427,25 +509,21 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     t->lu_blocks = (int)(t->lu_ops.size() / (kWave * kBlk));
 
     // ---- solver: column maps for the triangular solves ---------------------
-    // [slot][lane][NP]: offset of L(p,k) (p > k) for the forward sweep; of
-    // U(p,k) (p < k) or of the stored 1/U_kk (p == k) for the backward sweep.
-    t->NP = (N + 7) / 8 * 8;
-    const size_t map_n = (size_t)t->NS * kWave * t->NP;
+    // [slot][lane][v]: for the column at virtual index v, the offset of L(p,k)
+    // (p after k) for the forward sweep, of U(p,k) (p before k) or of the
+    // stored 1/U_kk (p == k) for the backward sweep; else the zero cell.
+    const size_t map_n = (size_t)t->NS * kWave * t->NV;
     t->fwd_map.assign(map_n, (uint16_t)ZERO);
     t->bwd_map.assign(map_n, (uint16_t)ZERO);
-    for (int s = 0; s < t->NS; ++s)
-        for (int lane = 0; lane < kWave; ++lane) {
-            const int p = s * kWave + lane;
-            if (p >= N) continue;
-            for (int k = 0; k < N; ++k) {
-                const size_t at = ((size_t)s * kWave + lane) * t->NP + k;
-                if (p > k && lp[p][k]) t->fwd_map[at] = (uint16_t)lpos[p][k];
-                if (p <= k && lp[p][k]) t->bwd_map[at] = (uint16_t)lpos[p][k];
-            }
+    for (int pr = 0; pr < N; ++pr)
+        for (int k = 0; k < N; ++k) {
+            const size_t at = (size_t)vpos[pr] * t->NV + vpos[k];
+            if (pr > k && lp[pr][k]) t->fwd_map[at] = (uint16_t)lpos[pr][k];
+            if (pr <= k && lp[pr][k]) t->bwd_map[at] = (uint16_t)lpos[pr][k];
         }
-    t->lu_lower = 0;
-    for (int p = 0; p < N; ++p)
-        for (int q = 0; q < p; ++q) t->lu_lower += lp[p][q];
+    // per-slot column counts (virtual columns in use)
+    t->slot_cols.assign(t->NS, 0);
+    for (int p = 0; p < N; ++p) t->slot_cols[vpos[p] / kWave] = std::max(t->slot_cols[vpos[p] / kWave], vpos[p] % kWave + 1);
 
     // ---- algorithmic work per cell -----------------------------------------
     {
@@ -458,12 +536,8 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         }
         for (int r = 0; r < N; ++r) n_fterms += t->out_ptr[r + 1] - t->out_ptr[r];
         n_jterms = (int64_t)t->out_ptr[N + t->nnz] - t->out_ptr[N];
-        for (int p = 0; p < N; ++p)
-            for (int q = 0; q < N; ++q)
-                if (lp[p][q]) {
-                    if (p > q) n_lower++;
-                    if (p < q) n_upper++;
-                }
+        n_lower = t->lu_lower;
+        n_upper = t->lu_upper;
         mcc_op_counts &oc = t->counts;
         oc.deriv_flops = prod_mults + 2 * n_fterms;
         oc.newton_matrix_flops = part_mults + 2 * n_jterms + t->nnz + N;

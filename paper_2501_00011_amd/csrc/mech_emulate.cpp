@@ -19,12 +19,13 @@ namespace mcc {
 int emulate_cell(const HostTables &t, const double *k, const double *y_species, double c,
                  const double *b_species, double *f_species, double *x_species)
 {
-    const int N = t.N, R = t.R, P = t.n_partials, NS = t.NS;
+    const int N = t.N, R = t.R, P = t.n_partials, NS = t.NS, NV = t.NV, M = t.M;
     const int ZERO = t.lu_nnz, TRASH = t.lu_nnz + 1;
     int bad = 0;
-    std::vector<double> yv(N + 1), rv(R + 1, 0.0), pv(P + 1, 0.0), lu(t.lu_nnz + 2, 0.0);
-    for (int p = 0; p < N; ++p) yv[p] = y_species[t.perm[p]];
-    yv[N] = 1.0;
+    std::vector<double> yv(NV + 1, 0.0), rv(R + 1, 0.0), pv(P + 1, 0.0), lu(t.lu_nnz + 2, 0.0);
+    for (int v = 0; v < NV; ++v)
+        if (t.vspecies[v] >= 0) yv[v] = y_species[t.vspecies[v]];
+    yv[NV] = 1.0;
     auto chk = [&](long v, long n) {
         if (v < 0 || v >= n) bad++;
         return v < 0 || v >= n ? 0 : v;
@@ -32,9 +33,9 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
 
     // deriv: rates then the per-slot gathers
     for (int j = 0; j < R; ++j) {
-        double r = k[j] * yv[chk(t.rx_reac[4 * j], N + 1)];
-        r *= yv[chk(t.rx_reac[4 * j + 1], N + 1)];
-        r *= yv[chk(t.rx_reac[4 * j + 2], N + 1)];
+        double r = k[j] * yv[chk(t.rx_reac[4 * j], NV + 1)];
+        r *= yv[chk(t.rx_reac[4 * j + 1], NV + 1)];
+        r *= yv[chk(t.rx_reac[4 * j + 2], NV + 1)];
         rv[j] = r;
     }
     for (int s = 0; s < NS; ++s)
@@ -45,14 +46,14 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
                     const Op16 &o = t.fg_ops[(((size_t)(t.fg_base[s] + bk)) * kWave + lane) * kBlk + i];
                     acc += o.coef * rv[chk(o.meta, R + 1)];
                 }
-            const int p = s * kWave + lane;
-            if (p < N) f_species[t.perm[p]] = acc;
+            const int v = s * kWave + lane;
+            if (t.vspecies[v] >= 0) f_species[t.vspecies[v]] = acc;
         }
 
     // Newton matrix
     for (int q = 0; q < P; ++q) {
-        double d = k[chk(t.part[4 * q], R)] * yv[chk(t.part[4 * q + 1], N + 1)];
-        d *= yv[chk(t.part[4 * q + 2], N + 1)];
+        double d = k[chk(t.part[4 * q], R)] * yv[chk(t.part[4 * q + 1], NV + 1)];
+        d *= yv[chk(t.part[4 * q + 2], NV + 1)];
         pv[q] = d;
     }
     std::vector<int> written(t.lu_nnz + 2, 0);
@@ -128,27 +129,59 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
     }
     if (!step_writes.empty()) bad++;  // the last level must end with a barrier
 
-    // triangular solves on b (positions)
-    std::vector<double> bp(N);
-    for (int p = 0; p < N; ++p) bp[p] = b_species[t.perm[p]];
-    auto map_at = [&](const std::vector<uint16_t> &m, int p, int kk) {
-        const int s = p / kWave, lane = p % kWave;
-        return (int)chk(m[((size_t)s * kWave + lane) * t.NP + kk], t.lu_nnz + 2);
-    };
-    for (int kk = 0; kk < N; ++kk) {
-        const double xk = bp[kk];
-        for (int p = 0; p < N; ++p) bp[p] -= lu[map_at(t.fwd_map, p, kk)] * xk;  // p <= kk: zero cell
+    // dense tail: row r of the Schur complement, pivot rows broadcast
+    if (M > 0) {
+        std::vector<std::vector<double>> a(M, std::vector<double>(M));
+        for (int r = 0; r < M; ++r)
+            for (int c = 0; c < M; ++c) a[r][c] = lu[t.tail_base + c * M + r];
+        for (int kk = 0; kk < M; ++kk) {
+            const double inv = 1.0 / a[kk][kk];
+            for (int r = kk + 1; r < M; ++r) {
+                const double l = a[r][kk] * inv;
+                a[r][kk] = l;
+                for (int c = kk + 1; c < M; ++c) a[r][c] -= l * a[kk][c];
+            }
+            a[kk][kk] = inv;
+        }
+        for (int r = 0; r < M; ++r)
+            for (int c = 0; c < M; ++c) lu[t.tail_base + c * M + r] = a[r][c];
     }
-    for (int kk = N - 1; kk >= 0; --kk) {
-        const double xk = bp[kk] * lu[map_at(t.bwd_map, kk, kk)];
-        for (int p = 0; p < N; ++p) {
-            if (p == kk)
-                bp[p] = xk;
-            else
-                bp[p] -= lu[map_at(t.bwd_map, p, kk)] * xk;
+
+    // triangular sweeps in elimination order over virtual columns; a column
+    // of slot ks updates only the slots the kernel updates (ord >= / <=)
+    auto ord = [&](int s) { return M > 0 ? (s == 0 ? NS - 1 : s - 1) : s; };
+    std::vector<double> bv(NV, 0.0);
+    for (int v = 0; v < NV; ++v)
+        if (t.vspecies[v] >= 0) bv[v] = b_species[t.vspecies[v]];
+    auto map_at = [&](const std::vector<uint16_t> &m, int u, int v) {
+        return (int)chk(m[(size_t)u * NV + v], t.lu_nnz + 2);
+    };
+    for (int pk = 0; pk < N; ++pk) {
+        const int v = t.vpos[pk], ks = v / kWave;
+        const double xk = bv[v];
+        for (int u = 0; u < NV; ++u) {
+            const int o = map_at(t.fwd_map, u, v);
+            if (ord(u / kWave) >= ord(ks))
+                bv[u] -= lu[o] * xk;
+            else if (o != ZERO)
+                bad++;  // an entry the kernel would skip
         }
     }
-    for (int p = 0; p < N; ++p) x_species[t.perm[p]] = bp[p];
+    for (int pk = N - 1; pk >= 0; --pk) {
+        const int v = t.vpos[pk], ks = v / kWave;
+        const double xk = bv[v] * lu[map_at(t.bwd_map, v, v)];
+        for (int u = 0; u < NV; ++u) {
+            const int o = map_at(t.bwd_map, u, v);
+            if (u == v)
+                bv[u] = xk;
+            else if (ord(u / kWave) <= ord(ks))
+                bv[u] -= lu[o] * xk;
+            else if (o != ZERO)
+                bad++;
+        }
+    }
+    for (int v = 0; v < NV; ++v)
+        if (t.vspecies[v] >= 0) x_species[t.vspecies[v]] = bv[v];
     return bad;
 }
 

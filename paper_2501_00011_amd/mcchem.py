@@ -171,7 +171,7 @@ class Mechanism:
         _check(library().mcc_debug_schedule_info(self._h, ctypes.addressof(buf)))
         v = list(buf)
         return {"lu_blocks": v[0], "lu_levels": v[1], "nm_blocks": v[2], "fg_blocks": v[3:7],
-                "lu_updates": v[7]}
+                "dense_tail": v[7]}
 
     def jac_pattern(self):
         rp = np.zeros(self.n_species + 1, dtype=np.int32)
