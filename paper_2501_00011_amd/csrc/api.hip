@@ -1,5 +1,6 @@
 // C ABI of libmcchem (declared in include/mcc.h): handles, argument checks,
 // table upload and kernel launches.  All arithmetic happens in the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -14,8 +15,10 @@ struct mcc_mech {
     int device = 0;
     void *dev_buf = nullptr;  // every device table, sub-allocated
     // device views
-    const int32_t *rxn_type = nullptr, *out_ptr = nullptr, *term_idx = nullptr, *fj_chunks = nullptr;
-    const double *A = nullptr, *theta = nullptr, *term_coef = nullptr;
+    const int32_t *rxn_type = nullptr;
+    const FjTerm *fj_terms = nullptr;
+    const FjChunk *fj_chunks = nullptr;
+    const double *A = nullptr, *theta = nullptr;
     const int32_t *vspecies = nullptr, *rx_reac = nullptr, *part = nullptr;
     const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
     const uint64_t *lu_ops = nullptr;
@@ -28,6 +31,7 @@ struct mcc_cells {
     mcc_mech *mech = nullptr;
     int64_t n_cells = 0, ld = 0;
     double *k = nullptr;
+    double *ones = nullptr;  // [ld] of 1.0: the factor of a missing reactant
     bool bound = false;
 };
 
@@ -131,8 +135,8 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->off_y = 0;
     m->off_k = t.NV + 1;
     m->off_r = m->off_k + t.R;
-    m->off_p = m->off_r + t.R + 1;
-    m->off_lu = m->off_p + t.n_partials + 1;
+    m->off_p = m->off_r;  // rates (f) and rate partials (Newton matrix) are never live together
+    m->off_lu = m->off_r + std::max(t.R, t.n_partials) + 1;
     m->off_tm = m->off_lu + t.lu_nnz + 2;
     m->lds_doubles = m->off_tm + (kMaxOrder + 1) * (kMaxOrder + 1);
     if (device == -1) {  // host-only: validated and compiled, nothing uploaded
@@ -175,8 +179,7 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
 
     Packer pk;
     const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
-    const size_t o_optr = pk.add(t.out_ptr), o_tidx = pk.add(t.term_idx), o_tcoef = pk.add(t.term_coef);
-    const size_t o_chunks = pk.add(t.fj_chunks);
+    const size_t o_terms = pk.add(t.fj_terms), o_chunks = pk.add(t.fj_chunks);
     const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
     const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
@@ -193,10 +196,8 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->rxn_type = (const int32_t *)(b + o_rxn);
     m->A = (const double *)(b + o_A);
     m->theta = (const double *)(b + o_th);
-    m->out_ptr = (const int32_t *)(b + o_optr);
-    m->term_idx = (const int32_t *)(b + o_tidx);
-    m->term_coef = (const double *)(b + o_tcoef);
-    m->fj_chunks = (const int32_t *)(b + o_chunks);
+    m->fj_terms = (const FjTerm *)(b + o_terms);
+    m->fj_chunks = (const FjChunk *)(b + o_chunks);
     m->vspecies = (const int32_t *)(b + o_perm);
     m->rx_reac = (const int32_t *)(b + o_rxr);
     m->part = (const int32_t *)(b + o_part);
@@ -294,6 +295,19 @@ mcc_status mcc_cells_create(const mcc_mech *mech, int64_t n_cells, int64_t ld, m
             return hip_error(e, "hipMalloc (rate constants)");
         }
     }
+    if (ld > 0) {
+        hipError_t e = hipMalloc(&c->ones, (size_t)ld * sizeof(double));
+        if (e == hipSuccess) {
+            std::vector<double> h((size_t)ld, 1.0);
+            e = hipMemcpy(c->ones, h.data(), (size_t)ld * sizeof(double), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            if (c->k) (void)hipFree(c->k);
+            if (c->ones) (void)hipFree(c->ones);
+            delete c;
+            return hip_error(e, "ones row");
+        }
+    }
     c->mech->live_batches++;
     *out = c;
     return ok();
@@ -337,10 +351,9 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
     const HostTables &t = c->mech->t;
     DeviceGuard g(c->mech->device);
     FJParams p{};
-    p.out_ptr = c->mech->out_ptr;
-    p.term_idx = c->mech->term_idx;
-    p.term_coef = c->mech->term_coef;
+    p.terms = c->mech->fj_terms;
     p.chunks = c->mech->fj_chunks;
+    p.ones = c->ones;
     p.y = y;
     p.k = c->k;
     p.f = f;
@@ -473,10 +486,11 @@ mcc_status mcc_cells_destroy(mcc_cells *c)
     if (!c) return ok();
     DeviceGuard g(c->mech->device);
     hipError_t e = hipDeviceSynchronize();
-    if (c->k) {
-        hipError_t e2 = hipFree(c->k);
-        if (e == hipSuccess) e = e2;
-    }
+    for (double *buf : {c->k, c->ones})
+        if (buf) {
+            hipError_t e2 = hipFree(buf);
+            if (e == hipSuccess) e = e2;
+        }
     c->mech->live_batches--;
     delete c;
     if (e != hipSuccess) return hip_error(e, "mcc_cells_destroy");

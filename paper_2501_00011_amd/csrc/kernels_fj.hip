@@ -32,44 +32,54 @@ hipError_t launch_rates(const RatesParams &p, hipStream_t s)
 }
 
 // Sum-of-monomials evaluation.  A block of 256 lanes covers 256 consecutive
-// cells and one chunk of output rows; rows 0..N-1 go to f, the rest to the
-// Jacobian.  Blocks of one cell tile are spread over chunks such that all the
-// chunks of a tile land on the same XCD (workgroups are dispatched to the 8
-// XCDs round-robin), so y and k of a tile are fetched from HBM once into that
+// cells and one chunk of whole output rows; rows 0..N-1 go to f, the rest to
+// the Jacobian.  The chunk's terms are taken 8 at a time: their indices come
+// through the scalar unit and all their k and y loads (a missing factor reads
+// a row of ones) are issued before any is consumed, so a wavefront keeps up
+// to 32 loads in flight instead of walking a dependent chain per term.
+// Blocks of one cell tile are spread over chunks such that all the chunks of
+// a tile land on the same XCD (workgroups are dispatched to the 8 XCDs
+// round-robin), so y and k of a tile are fetched from HBM once into that
 // XCD's L2 and re-read from there.
 __global__ __launch_bounds__(256) void fj_kernel(FJParams p)
 {
-    const int b = blockIdx.x;
-    const int xcd = b & 7;
-    const int q = b >> 3;
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7;
+    const int q = bid >> 3;
     const int chunk = q % p.n_chunks;
     const int tile = (q / p.n_chunks) * 8 + xcd;
     if (tile >= p.n_tiles) return;
     const int64_t c = (int64_t)tile * 256 + threadIdx.x;
     const bool live = c < p.n_cells;
     const int64_t cc = live ? c : 0;
-    const int N = p.N;
-    const int ch = p.chunk_begin + chunk;
-    const int r0 = p.chunks[ch], r1 = p.chunks[ch + 1];
-    for (int r = r0; r < r1; ++r) {
-        double acc = 0.0;
-        const int t1 = p.out_ptr[r + 1];
-        for (int t = p.out_ptr[r]; t < t1; ++t) {
-            const int j = p.term_idx[4 * t + 0];
-            const int a = p.term_idx[4 * t + 1];
-            const int bb = p.term_idx[4 * t + 2];
-            const int e = p.term_idx[4 * t + 3];
-            double v = p.term_coef[t] * p.k[(int64_t)j * p.ld + cc];
-            if (a < N) v *= p.y[(int64_t)a * p.ld + cc];
-            if (bb < N) v *= p.y[(int64_t)bb * p.ld + cc];
-            if (e < N) v *= p.y[(int64_t)e * p.ld + cc];
-            acc += v;
+    const FjChunk ch = p.chunks[p.chunk_begin + chunk];
+    const FjTerm *tm = p.terms + ch.term_begin;
+    const double *ones = p.ones + cc;
+    int row = ch.row_begin;
+    double acc = 0.0;
+    for (int g = 0; g < ch.term_count; g += kFjGroup) {
+        double v[kFjGroup];
+#pragma unroll
+        for (int i = 0; i < kFjGroup; ++i) {
+            const FjTerm t = tm[g + i];
+            const double *ya = t.a >= 0 ? p.y + (int64_t)t.a * p.ld + cc : ones;
+            const double *yb = t.b >= 0 ? p.y + (int64_t)t.b * p.ld + cc : ones;
+            const double *yc = t.c >= 0 ? p.y + (int64_t)t.c * p.ld + cc : ones;
+            v[i] = t.coef * p.k[(int64_t)t.j * p.ld + cc] * *ya * *yb * *yc;
         }
-        if (live) {
-            if (r < N)
-                p.f[(int64_t)r * p.ld + c] = acc;
-            else
-                p.jac[(int64_t)(r - N) * p.ld + c] = acc;
+#pragma unroll
+        for (int i = 0; i < kFjGroup; ++i) {
+            acc += v[i];
+            if (tm[g + i].end) {
+                if (live) {
+                    if (row < p.N)
+                        p.f[(int64_t)row * p.ld + c] = acc;
+                    else
+                        p.jac[(int64_t)(row - p.N) * p.ld + c] = acc;
+                }
+                acc = 0.0;
+                row++;
+            }
         }
     }
 }

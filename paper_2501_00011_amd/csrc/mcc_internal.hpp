@@ -21,6 +21,22 @@ constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
 // op flags (bits 56.. of an LU op; bits 28.. of a 16-byte op's meta word)
 constexpr uint32_t kFirst = 1, kLast = 2, kRecip = 4, kScale = 8, kBarrier = 16, kDiag = 4;
 
+// One monomial coef * k_j * y_a * y_b * y_c of the streaming f/J kernel
+// (-1 = the row of ones); `end` closes an output row.  32 bytes, read with
+// scalar loads.
+struct alignas(32) FjTerm {
+    int32_t j, a, b, c;
+    int32_t end, pad;
+    double coef;
+};
+// A chunk of whole output rows: terms [term_begin, term_begin + term_count)
+// (a multiple of kFjGroup), the first row being row_begin.
+struct FjChunk {
+    int32_t term_begin, term_count, row_begin, pad;
+};
+constexpr int kFjGroup = 8;        // terms whose loads are issued together
+constexpr int kFjChunkTerms = 64;  // target terms per chunk
+
 // A 16-byte op of the gather streams: coefficient and packed indices/flags.
 struct alignas(16) Op16 {
     double coef;
@@ -43,12 +59,11 @@ struct HostTables {
 
     // Streaming f/J evaluation, species order.  Output rows 0..N-1 are f_i,
     // rows N..N+nnz-1 the Jacobian nonzeros in CSR order.  Each output is a
-    // sum of monomials coef * k_j * y_a * y_b * y_c (index N = the constant 1).
-    std::vector<int32_t> out_ptr;     // [N + nnz + 1]
-    std::vector<int32_t> term_idx;    // [4 * n_terms]: j, a, b, c
-    std::vector<double> term_coef;    // [n_terms]
-    std::vector<int32_t> fj_chunks;   // row boundaries of the work chunks
-    int n_fchunks = 0, n_jchunks = 0; // f chunks first, then J chunks
+    // sum of monomials coef * k_j * y_a * y_b * y_c.
+    std::vector<int32_t> out_ptr;     // [N + nnz + 1] term counts (algorithmic)
+    std::vector<FjTerm> fj_terms;     // flattened, chunk-padded term stream
+    std::vector<FjChunk> fj_chunks;   // f chunks first, then J chunks
+    int n_fchunks = 0, n_jchunks = 0;
 
     // Solver.  Positions p = 0..N-1 are the elimination (fill-reducing)
     // order; every position lives at a virtual index v = slot * 64 + lane of
@@ -102,9 +117,9 @@ struct RatesParams {
 };
 
 struct FJParams {
-    const int32_t *out_ptr, *term_idx, *chunks;
-    const double *term_coef;
-    const double *y, *k;
+    const FjTerm *terms;
+    const FjChunk *chunks;
+    const double *y, *k, *ones;
     double *f, *jac;
     int64_t n_cells, ld;
     int32_t N, chunk_begin, n_chunks, n_tiles;

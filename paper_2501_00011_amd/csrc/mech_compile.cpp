@@ -228,40 +228,59 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         for (const auto &kv : nu)
             if (kv.second != 0.0) out_terms[N + jpos[kv.first][p.s]].push_back({mono, kv.second});
     }
+    // Flattened term stream: every output row gets at least one term (a zero
+    // term for a row with none) and its last term carries the end-of-row
+    // flag.  Missing factors (and monomials of lower degree) point at -1, the
+    // row of ones.  Chunks hold whole rows, about kFjChunkTerms terms, padded
+    // with zero terms to a multiple of kFjGroup so the kernel always fetches
+    // full groups.
     t->out_ptr.assign(1, 0);
-    t->term_idx.clear();
-    t->term_coef.clear();
-    for (const auto &ot : out_terms) {
-        for (const auto &tm : ot) {
-            t->term_idx.insert(t->term_idx.end(), tm.first.begin(), tm.first.end());
-            t->term_coef.push_back(tm.second);
+    std::vector<FjTerm> flat;
+    std::vector<int> row_first(N + t->nnz + 1, 0);
+    for (int r = 0; r < N + t->nnz; ++r) {
+        row_first[r] = (int)flat.size();
+        auto ot = out_terms[r];
+        if (ot.empty()) ot.push_back({{0, N, N, N}, 0.0});
+        for (size_t q = 0; q < ot.size(); ++q) {
+            FjTerm tm{};
+            tm.j = ot[q].first[0];
+            tm.a = ot[q].first[1] < N ? ot[q].first[1] : -1;
+            tm.b = ot[q].first[2] < N ? ot[q].first[2] : -1;
+            tm.c = ot[q].first[3] < N ? ot[q].first[3] : -1;
+            tm.end = q + 1 == ot.size();
+            tm.coef = ot[q].second;
+            flat.push_back(tm);
         }
-        t->out_ptr.push_back((int32_t)t->term_coef.size());
+        t->out_ptr.push_back((int32_t)out_terms[r].size() + t->out_ptr.back());
     }
-    // Chunks of consecutive output rows with about `target` terms each (every
-    // row is at least one unit of work: it is written even with no terms).
-    auto make_chunks = [&](int r0, int r1, int target) {
-        int count = 0;
-        int begin = r0;
-        t->fj_chunks.push_back(r0);
-        for (int r = r0; r < r1; ++r) {
-            count += std::max(1, t->out_ptr[r + 1] - t->out_ptr[r]);
-            if (count >= target && r + 1 < r1) {
-                t->fj_chunks.push_back(r + 1);
-                count = 0;
-                begin = r + 1;
-            }
-        }
-        (void)begin;
-        return 0;
-    };
+    row_first[N + t->nnz] = (int)flat.size();
+    t->fj_terms.clear();
     t->fj_chunks.clear();
-    const int target = 64;
-    make_chunks(0, N, target);
+    auto make_chunks = [&](int r0, int r1) {
+        int r = r0;
+        while (r < r1) {
+            int r_end = r;
+            while (r_end < r1 && (row_first[r_end + 1] - row_first[r] <= kFjChunkTerms || r_end == r)) r_end++;
+            FjChunk ch{};
+            ch.term_begin = (int32_t)t->fj_terms.size();
+            ch.row_begin = r;
+            for (int q = row_first[r]; q < row_first[r_end]; ++q) t->fj_terms.push_back(flat[q]);
+            while ((t->fj_terms.size() - ch.term_begin) % kFjGroup) {
+                FjTerm pad{};
+                pad.j = 0;
+                pad.a = pad.b = pad.c = -1;
+                pad.coef = 0.0;
+                t->fj_terms.push_back(pad);
+            }
+            ch.term_count = (int32_t)(t->fj_terms.size() - ch.term_begin);
+            t->fj_chunks.push_back(ch);
+            r = r_end;
+        }
+    };
+    make_chunks(0, N);
     t->n_fchunks = (int)t->fj_chunks.size();
-    make_chunks(N, N + t->nnz, target);
+    make_chunks(N, N + t->nnz);
     t->n_jchunks = (int)t->fj_chunks.size() - t->n_fchunks;
-    t->fj_chunks.push_back(N + t->nnz);
 
     // ---- fill-reducing order and symbolic LU (elimination positions) -------
     t->perm = markowitz_order(pat);
