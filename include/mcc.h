@@ -177,6 +177,13 @@ mcc_status mcc_mech_jac_pattern(const mcc_mech *mech, int32_t *row_ptr, int32_t 
 mcc_status mcc_debug_emulate_cell(const mcc_mech *mech, const double *k, const double *y, double c,
                                   const double *b, double *f, double *x, int32_t *violations);
 
+/* Testing aid (host only): f and the sparse J of one cell from the tables of
+ * the streaming f/J kernel, run on the host in the kernel's order; k
+ * [n_reactions], y [n_species] in, f [n_species], jac [nnz] out (host
+ * arrays); *violations counts table errors (0 for sound tables). */
+mcc_status mcc_debug_emulate_fj(const mcc_mech *mech, const double *k, const double *y, double *f, double *jac,
+                                int32_t *violations);
+
 /* Testing aid: sizes of the solver schedule, written to out[0..7]: LU
  * blocks, LU levels, Newton-matrix blocks, f-gather blocks of slots 0..3,
  * and the size of the dense tail factorised in registers. */

@@ -16,8 +16,11 @@ struct mcc_mech {
     void *dev_buf = nullptr;  // every device table, sub-allocated
     // device views
     const int32_t *rxn_type = nullptr;
+    const FjMono *fj_monos = nullptr;
+    const FjOut *fj_outs = nullptr;
     const FjTerm *fj_terms = nullptr;
     const FjChunk *fj_chunks = nullptr;
+    const int32_t *fj_items = nullptr;
     const double *A = nullptr, *theta = nullptr;
     const int32_t *vspecies = nullptr, *rx_reac = nullptr, *part = nullptr;
     const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
@@ -179,7 +182,8 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
 
     Packer pk;
     const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
-    const size_t o_terms = pk.add(t.fj_terms), o_chunks = pk.add(t.fj_chunks);
+    const size_t o_monos = pk.add(t.fj_monos), o_outs = pk.add(t.fj_outs), o_terms = pk.add(t.fj_terms);
+    const size_t o_chunks = pk.add(t.fj_chunks), o_items = pk.add(t.fj_items);
     const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
     const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
@@ -196,8 +200,11 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->rxn_type = (const int32_t *)(b + o_rxn);
     m->A = (const double *)(b + o_A);
     m->theta = (const double *)(b + o_th);
+    m->fj_monos = (const FjMono *)(b + o_monos);
+    m->fj_outs = (const FjOut *)(b + o_outs);
     m->fj_terms = (const FjTerm *)(b + o_terms);
     m->fj_chunks = (const FjChunk *)(b + o_chunks);
+    m->fj_items = (const int32_t *)(b + o_items);
     m->vspecies = (const int32_t *)(b + o_perm);
     m->rx_reac = (const int32_t *)(b + o_rxr);
     m->part = (const int32_t *)(b + o_part);
@@ -235,6 +242,15 @@ mcc_status mcc_debug_emulate_cell(const mcc_mech *m, const double *k, const doub
     if (!m || (!k && m->t.R > 0) || !y || !b || !f || !x || !violations)
         return set_error(MCC_ERR_INVALID_ARG, "null argument");
     *violations = emulate_cell(m->t, k, y, c, b, f, x);
+    return ok();
+}
+
+mcc_status mcc_debug_emulate_fj(const mcc_mech *m, const double *k, const double *y, double *f, double *jac,
+                                int32_t *violations)
+{
+    if (!m || (!k && m->t.R > 0) || !y || !f || !jac || !violations)
+        return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    *violations = emulate_fj(m->t, k, y, f, jac);
     return ok();
 }
 
@@ -351,8 +367,11 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
     const HostTables &t = c->mech->t;
     DeviceGuard g(c->mech->device);
     FJParams p{};
+    p.monos = c->mech->fj_monos;
+    p.outs = c->mech->fj_outs;
     p.terms = c->mech->fj_terms;
     p.chunks = c->mech->fj_chunks;
+    p.items = c->mech->fj_items;
     p.ones = c->ones;
     p.y = y;
     p.k = c->k;
@@ -361,16 +380,16 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
     p.n_cells = c->n_cells;
     p.ld = c->ld;
     p.N = t.N;
-    p.n_tiles = (int)((c->n_cells + 255) / 256);
+    p.n_tiles = (int)((c->n_cells + 63) / 64);
     if (f && jac) {
-        p.chunk_begin = 0;
-        p.n_chunks = t.n_fchunks + t.n_jchunks;
+        p.item_begin = 0;
+        p.n_items = t.n_fitems + t.n_jitems;
     } else if (f) {
-        p.chunk_begin = 0;
-        p.n_chunks = t.n_fchunks;
+        p.item_begin = 0;
+        p.n_items = t.n_fitems;
     } else {
-        p.chunk_begin = t.n_fchunks;
-        p.n_chunks = t.n_jchunks;
+        p.item_begin = t.n_fitems;
+        p.n_items = t.n_jitems;
     }
     hipError_t e = launch_fj(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "f/J kernel launch");

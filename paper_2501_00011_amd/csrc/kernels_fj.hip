@@ -31,54 +31,62 @@ hipError_t launch_rates(const RatesParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
-// Sum-of-monomials evaluation.  A block of 256 lanes covers 256 consecutive
-// cells and one chunk of whole output rows; rows 0..N-1 go to f, the rest to
-// the Jacobian.  The chunk's terms are taken 8 at a time: their indices come
-// through the scalar unit and all their k and y loads (a missing factor reads
-// a row of ones) are issued before any is consumed, so a wavefront keeps up
-// to 32 loads in flight instead of walking a dependent chain per term.
-// Blocks of one cell tile are spread over chunks such that all the chunks of
-// a tile land on the same XCD (workgroups are dispatched to the 8 XCDs
-// round-robin), so y and k of a tile are fetched from HBM once into that
-// XCD's L2 and re-read from there.
-__global__ __launch_bounds__(256) void fj_kernel(FJParams p)
+// f and J by chunks.  A block is one wavefront of 64 consecutive cells (lane =
+// cell) and one work item (a run of chunks).  For each chunk the wavefront
+// first computes the chunk's monomials k_j * y_a * y_b * y_c -- the reaction
+// rates of a few f rows, or the rate partials of one Jacobian column --
+// eight at a time so that their loads are in flight together (a missing
+// factor reads a row of ones), into a per-lane LDS scratchpad; then every
+// output row of the chunk is sum coef * monomial, read back from the
+// scratchpad, and written once (no atomics: each output has one owner).
+// Table entries come through the scalar unit.  The work items of one cell
+// tile are mapped to one XCD (workgroups go to the 8 XCDs round-robin), so
+// that XCD's L2 serves the tile's repeated y and k reads.
+__global__ __launch_bounds__(64) void fj_kernel(FJParams p)
 {
+    __shared__ double scratch[kFjQmax * 64];
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int q = bid >> 3;
-    const int chunk = q % p.n_chunks;
-    const int tile = (q / p.n_chunks) * 8 + xcd;
+    const int item = q % p.n_items;
+    const int tile = (q / p.n_items) * 8 + xcd;
     if (tile >= p.n_tiles) return;
-    const int64_t c = (int64_t)tile * 256 + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t c = (int64_t)tile * 64 + lane;
     const bool live = c < p.n_cells;
     const int64_t cc = live ? c : 0;
-    const FjChunk ch = p.chunks[p.chunk_begin + chunk];
-    const FjTerm *tm = p.terms + ch.term_begin;
     const double *ones = p.ones + cc;
-    int row = ch.row_begin;
-    double acc = 0.0;
-    for (int g = 0; g < ch.term_count; g += kFjGroup) {
-        double v[kFjGroup];
+    double *mine = scratch + lane;
+    const int it = p.item_begin + item;
+    for (int ci = p.items[it]; ci < p.items[it + 1]; ++ci) {
+        const FjChunk ch = p.chunks[ci];
+        const FjMono *mo = p.monos + ch.mono_begin;
+        for (int q0 = 0; q0 < ch.n_mono; q0 += kFjGroup) {
+            double v[kFjGroup];
 #pragma unroll
-        for (int i = 0; i < kFjGroup; ++i) {
-            const FjTerm t = tm[g + i];
-            const double *ya = t.a >= 0 ? p.y + (int64_t)t.a * p.ld + cc : ones;
-            const double *yb = t.b >= 0 ? p.y + (int64_t)t.b * p.ld + cc : ones;
-            const double *yc = t.c >= 0 ? p.y + (int64_t)t.c * p.ld + cc : ones;
-            v[i] = t.coef * p.k[(int64_t)t.j * p.ld + cc] * *ya * *yb * *yc;
+            for (int i = 0; i < kFjGroup; ++i) {
+                const FjMono m = mo[min(q0 + i, ch.n_mono - 1)];
+                const double *ya = m.a >= 0 ? p.y + (int64_t)m.a * p.ld + cc : ones;
+                const double *yb = m.b >= 0 ? p.y + (int64_t)m.b * p.ld + cc : ones;
+                const double *yc = m.c >= 0 ? p.y + (int64_t)m.c * p.ld + cc : ones;
+                v[i] = p.k[(int64_t)m.j * p.ld + cc] * *ya * *yb * *yc;
+            }
+#pragma unroll
+            for (int i = 0; i < kFjGroup; ++i)
+                if (q0 + i < ch.n_mono) mine[(q0 + i) * 64] = v[i];
         }
-#pragma unroll
-        for (int i = 0; i < kFjGroup; ++i) {
-            acc += v[i];
-            if (tm[g + i].end) {
-                if (live) {
-                    if (row < p.N)
-                        p.f[(int64_t)row * p.ld + c] = acc;
-                    else
-                        p.jac[(int64_t)(row - p.N) * p.ld + c] = acc;
-                }
-                acc = 0.0;
-                row++;
+        const FjOut *ou = p.outs + ch.out_begin;
+        for (int o = 0; o < ch.n_out; ++o) {
+            const FjOut out = ou[o];
+            double acc = 0.0;
+            for (int t = out.t_begin; t < out.t_begin + out.t_count; ++t) {
+                const FjTerm tm = p.terms[t];
+                acc += tm.coef * mine[tm.slot * 64];
+            }
+            if (live) {
+                double *dst = out.row < p.N ? p.f + (int64_t)out.row * p.ld + c
+                                            : p.jac + (int64_t)(out.row - p.N) * p.ld + c;
+                *dst = out.accum ? *dst + acc : acc;
             }
         }
     }
@@ -86,11 +94,11 @@ __global__ __launch_bounds__(256) void fj_kernel(FJParams p)
 
 hipError_t launch_fj(const FJParams &p, hipStream_t s)
 {
-    if (p.n_cells == 0 || p.n_chunks == 0) return hipSuccess;
+    if (p.n_cells == 0 || p.n_items == 0) return hipSuccess;
     const int groups = (p.n_tiles + 7) / 8;
-    const int64_t blocks = (int64_t)groups * 8 * p.n_chunks;
+    const int64_t blocks = (int64_t)groups * 8 * p.n_items;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fj_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(fj_kernel, dim3((unsigned)blocks), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 

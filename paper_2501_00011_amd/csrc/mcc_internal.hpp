@@ -21,21 +21,27 @@ constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
 // op flags (bits 56.. of an LU op; bits 28.. of a 16-byte op's meta word)
 constexpr uint32_t kFirst = 1, kLast = 2, kRecip = 4, kScale = 8, kBarrier = 16, kDiag = 4;
 
-// One monomial coef * k_j * y_a * y_b * y_c of the streaming f/J kernel
-// (-1 = the row of ones); `end` closes an output row.  32 bytes, read with
-// scalar loads.
-struct alignas(32) FjTerm {
+// Streaming f/J kernel tables.  A chunk computes its monomials
+// k_j * y_a * y_b * y_c (-1 = the constant 1) into a per-lane LDS scratchpad,
+// then each of its outputs as sum coef * monomial[slot].  Outputs flagged
+// `accum` add to what an earlier chunk of the same block wrote.
+struct FjMono {
     int32_t j, a, b, c;
-    int32_t end, pad;
+};
+struct FjOut {
+    int32_t row, t_begin, t_count, accum;  // row < N: f_row, else J nonzero row - N
+};
+struct alignas(16) FjTerm {
     double coef;
+    int32_t slot, pad;
 };
-// A chunk of whole output rows: terms [term_begin, term_begin + term_count)
-// (a multiple of kFjGroup), the first row being row_begin.
 struct FjChunk {
-    int32_t term_begin, term_count, row_begin, pad;
+    int32_t mono_begin, n_mono, out_begin, n_out;
 };
-constexpr int kFjGroup = 8;        // terms whose loads are issued together
-constexpr int kFjChunkTerms = 64;  // target terms per chunk
+// A work item is a run of consecutive chunks processed by one block in
+// order (the later parts of a split unit accumulate into its outputs).
+constexpr int kFjQmax = 32;   // monomials per chunk (LDS: 32 x 64 lanes x 8 B)
+constexpr int kFjGroup = 8;   // monomials whose loads are issued together
 
 // A 16-byte op of the gather streams: coefficient and packed indices/flags.
 struct alignas(16) Op16 {
@@ -58,12 +64,14 @@ struct HostTables {
     std::vector<double> A, theta;
 
     // Streaming f/J evaluation, species order.  Output rows 0..N-1 are f_i,
-    // rows N..N+nnz-1 the Jacobian nonzeros in CSR order.  Each output is a
-    // sum of monomials coef * k_j * y_a * y_b * y_c.
-    std::vector<int32_t> out_ptr;     // [N + nnz + 1] term counts (algorithmic)
-    std::vector<FjTerm> fj_terms;     // flattened, chunk-padded term stream
-    std::vector<FjChunk> fj_chunks;   // f chunks first, then J chunks
-    int n_fchunks = 0, n_jchunks = 0;
+    // rows N..N+nnz-1 the Jacobian nonzeros in CSR order.
+    std::vector<int32_t> out_ptr;     // [N + nnz + 1] algorithmic term counts
+    std::vector<FjMono> fj_monos;
+    std::vector<FjOut> fj_outs;
+    std::vector<FjTerm> fj_terms;
+    std::vector<FjChunk> fj_chunks;
+    std::vector<int32_t> fj_items;    // first chunk of every work item + end
+    int n_fitems = 0, n_jitems = 0;   // f items first, then J items
 
     // Solver.  Positions p = 0..N-1 are the elimination (fill-reducing)
     // order; every position lives at a virtual index v = slot * 64 + lane of
@@ -103,6 +111,8 @@ mcc_status compile_mechanism(const mcc_mech_desc *desc, HostTables *t, std::stri
 // Host emulation of the solver's table-driven phases (testing aid).
 int emulate_cell(const HostTables &t, const double *k, const double *y_species, double c,
                  const double *b_species, double *f_species, double *x_species);
+// Host emulation of the streaming f/J tables for one cell (testing aid).
+int emulate_fj(const HostTables &t, const double *k, const double *y_species, double *f, double *jac);
 
 // ---------------------------------------------------------------------------
 // Device parameter blocks (passed by value as kernel arguments).
@@ -117,12 +127,15 @@ struct RatesParams {
 };
 
 struct FJParams {
+    const FjMono *monos;
+    const FjOut *outs;
     const FjTerm *terms;
     const FjChunk *chunks;
+    const int32_t *items;
     const double *y, *k, *ones;
     double *f, *jac;
     int64_t n_cells, ld;
-    int32_t N, chunk_begin, n_chunks, n_tiles;
+    int32_t N, item_begin, n_items, n_tiles;
 };
 
 struct SolveParams {

@@ -210,77 +210,121 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     }
     t->n_partials = (int)parts.size();
 
-    // ---- streaming terms (species order) ----------------------------------
-    // f_i: one term per (reaction, participant i) with the full rate monomial.
-    // J_is: one term per (partial of slot l with species s, participant i).
-    std::vector<std::vector<std::pair<std::array<int32_t, 4>, double>>> out_terms(N + t->nnz);
-    for (int j = 0; j < R; ++j) {
-        const auto nu = net_stoich(d, j);
-        const int b = d->reac_ptr[j], e = d->reac_ptr[j + 1];
-        std::array<int32_t, 4> mono = {j, N, N, N};
-        for (int q = b; q < e; ++q) mono[1 + (q - b)] = d->reac_idx[q];
-        for (const auto &kv : nu)
-            if (kv.second != 0.0) out_terms[kv.first].push_back({mono, kv.second});
-    }
-    for (const Partial &p : parts) {
-        const auto nu = net_stoich(d, p.j);
-        std::array<int32_t, 4> mono = {p.j, p.o1, p.o2, N};
-        for (const auto &kv : nu)
-            if (kv.second != 0.0) out_terms[N + jpos[kv.first][p.s]].push_back({mono, kv.second});
-    }
-    // Flattened term stream: every output row gets at least one term (a zero
-    // term for a row with none) and its last term carries the end-of-row
-    // flag.  Missing factors (and monomials of lower degree) point at -1, the
-    // row of ones.  Chunks hold whole rows, about kFjChunkTerms terms, padded
-    // with zero terms to a multiple of kFjGroup so the kernel always fetches
-    // full groups.
+    // ---- streaming f/J tables (species order) ------------------------------
+    // Units: an f row i (monomials = the rates of the reactions that change
+    // i) and a J column s (monomials = the partials d r_j / d y_s through each
+    // reactant slot holding s; outputs = every J entry of column s).  Units
+    // are packed into chunks of at most kFjQmax monomials; a unit with more
+    // is split, its later parts accumulating into the same outputs.
+    struct Unit {
+        std::vector<std::array<int32_t, 4>> monos;            // j, a, b, c (-1 = one)
+        std::vector<std::pair<int, std::vector<std::pair<int, double>>>> outs;  // row, (slot, coef)
+    };
+    std::vector<Unit> units;
     t->out_ptr.assign(1, 0);
-    std::vector<FjTerm> flat;
-    std::vector<int> row_first(N + t->nnz + 1, 0);
-    for (int r = 0; r < N + t->nnz; ++r) {
-        row_first[r] = (int)flat.size();
-        auto ot = out_terms[r];
-        if (ot.empty()) ot.push_back({{0, N, N, N}, 0.0});
-        for (size_t q = 0; q < ot.size(); ++q) {
-            FjTerm tm{};
-            tm.j = ot[q].first[0];
-            tm.a = ot[q].first[1] < N ? ot[q].first[1] : -1;
-            tm.b = ot[q].first[2] < N ? ot[q].first[2] : -1;
-            tm.c = ot[q].first[3] < N ? ot[q].first[3] : -1;
-            tm.end = q + 1 == ot.size();
-            tm.coef = ot[q].second;
-            flat.push_back(tm);
+    std::vector<std::vector<std::pair<int, double>>> frow(N);  // species -> (reaction, nu)
+    for (int j = 0; j < R; ++j)
+        for (const auto &kv : net_stoich(d, j))
+            if (kv.second != 0.0) frow[kv.first].push_back({j, kv.second});
+    auto rate_mono = [&](int j) {
+        std::array<int32_t, 4> m = {j, -1, -1, -1};
+        for (int q = d->reac_ptr[j]; q < d->reac_ptr[j + 1]; ++q) m[1 + (q - d->reac_ptr[j])] = d->reac_idx[q];
+        return m;
+    };
+    for (int i = 0; i < N; ++i) {
+        Unit u;
+        std::vector<std::pair<int, double>> terms;
+        for (const auto &rc : frow[i]) {
+            terms.push_back({(int)u.monos.size(), rc.second});
+            u.monos.push_back(rate_mono(rc.first));
         }
-        t->out_ptr.push_back((int32_t)out_terms[r].size() + t->out_ptr.back());
+        u.outs.push_back({i, terms});
+        units.push_back(u);
+        t->out_ptr.push_back(t->out_ptr.back() + (int32_t)frow[i].size());
     }
-    row_first[N + t->nnz] = (int)flat.size();
+    const int n_funits = (int)units.size();
+    std::vector<int32_t> jterms_of_row(t->nnz, 0);
+    for (int s = 0; s < N; ++s) {
+        Unit u;
+        std::map<int, std::vector<std::pair<int, double>>> by_row;  // J row index -> terms
+        for (int i = 0; i < N; ++i)
+            if (jpos[i][s] >= 0) by_row[jpos[i][s]];
+        for (const Partial &pt : parts) {
+            if (pt.s != s) continue;
+            const int slot = (int)u.monos.size();
+            u.monos.push_back({pt.j, pt.o1 < N ? pt.o1 : -1, pt.o2 < N ? pt.o2 : -1, -1});
+            for (const auto &kv : net_stoich(d, pt.j))
+                if (kv.second != 0.0) {
+                    by_row[jpos[kv.first][s]].push_back({slot, kv.second});
+                    jterms_of_row[jpos[kv.first][s]]++;
+                }
+        }
+        for (auto &kv : by_row) u.outs.push_back({N + kv.first, kv.second});
+        units.push_back(u);
+    }
+    for (int e = 0; e < t->nnz; ++e) t->out_ptr.push_back(t->out_ptr.back() + jterms_of_row[e]);
+
+    t->fj_monos.clear();
+    t->fj_outs.clear();
     t->fj_terms.clear();
     t->fj_chunks.clear();
-    auto make_chunks = [&](int r0, int r1) {
-        int r = r0;
-        while (r < r1) {
-            int r_end = r;
-            while (r_end < r1 && (row_first[r_end + 1] - row_first[r] <= kFjChunkTerms || r_end == r)) r_end++;
-            FjChunk ch{};
-            ch.term_begin = (int32_t)t->fj_terms.size();
-            ch.row_begin = r;
-            for (int q = row_first[r]; q < row_first[r_end]; ++q) t->fj_terms.push_back(flat[q]);
-            while ((t->fj_terms.size() - ch.term_begin) % kFjGroup) {
-                FjTerm pad{};
-                pad.j = 0;
-                pad.a = pad.b = pad.c = -1;
-                pad.coef = 0.0;
-                t->fj_terms.push_back(pad);
-            }
-            ch.term_count = (int32_t)(t->fj_terms.size() - ch.term_begin);
-            t->fj_chunks.push_back(ch);
-            r = r_end;
+    t->fj_items.clear();
+    FjChunk cur{0, 0, 0, 0};
+    bool cur_cont = false;  // the open chunk continues the previous work item
+    auto close_chunk = [&]() {
+        if (cur.n_mono > 0 || cur.n_out > 0) {
+            if (!cur_cont) t->fj_items.push_back((int32_t)t->fj_chunks.size());
+            t->fj_chunks.push_back(cur);
+        }
+        cur = FjChunk{(int32_t)t->fj_monos.size(), 0, (int32_t)t->fj_outs.size(), 0};
+        cur_cont = false;
+    };
+    auto add_part = [&](const Unit &u, int m0, int m1, bool accum) {
+        // monomials [m0, m1) of unit u, with the terms that use them
+        if (cur.n_mono + (m1 - m0) > kFjQmax) close_chunk();
+        const int base = cur.n_mono;
+        for (int q = m0; q < m1; ++q) {
+            FjMono mo{u.monos[q][0], u.monos[q][1], u.monos[q][2], u.monos[q][3]};
+            t->fj_monos.push_back(mo);
+        }
+        cur.n_mono += m1 - m0;
+        for (const auto &o : u.outs) {
+            FjOut fo{o.first, (int32_t)t->fj_terms.size(), 0, accum ? 1 : 0};
+            for (const auto &tm : o.second)
+                if (tm.first >= m0 && tm.first < m1) {
+                    FjTerm ft{};
+                    ft.coef = tm.second;
+                    ft.slot = base + (tm.first - m0);
+                    t->fj_terms.push_back(ft);
+                }
+            fo.t_count = (int32_t)t->fj_terms.size() - fo.t_begin;
+            if (accum && fo.t_count == 0) continue;  // nothing to add
+            t->fj_outs.push_back(fo);
+            cur.n_out++;
         }
     };
-    make_chunks(0, N);
-    t->n_fchunks = (int)t->fj_chunks.size();
-    make_chunks(N, N + t->nnz);
-    t->n_jchunks = (int)t->fj_chunks.size() - t->n_fchunks;
+    auto add_unit = [&](const Unit &u) {
+        const int n = (int)u.monos.size();
+        if (n == 0) {
+            add_part(u, 0, 0, false);
+            return;
+        }
+        for (int m0 = 0; m0 < n; m0 += kFjQmax) {
+            const int m1 = std::min(n, m0 + kFjQmax);
+            if (m0 > 0) {  // later parts: a fresh chunk of the same work item
+                close_chunk();
+                cur_cont = true;
+            }
+            add_part(u, m0, m1, m0 > 0);
+        }
+    };
+    for (int q = 0; q < n_funits; ++q) add_unit(units[q]);
+    close_chunk();
+    t->n_fitems = (int)t->fj_items.size();
+    for (size_t q = n_funits; q < units.size(); ++q) add_unit(units[q]);
+    close_chunk();
+    t->n_jitems = (int)t->fj_items.size() - t->n_fitems;
+    t->fj_items.push_back((int32_t)t->fj_chunks.size());
 
     // ---- fill-reducing order and symbolic LU (elimination positions) -------
     t->perm = markowitz_order(pat);

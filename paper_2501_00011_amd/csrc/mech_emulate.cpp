@@ -185,4 +185,61 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
     return bad;
 }
 
+// Host emulation of the streaming f/J tables for one cell: every work item in
+// order, chunk by chunk, monomials into a scratchpad of kFjQmax entries, then
+// the outputs.  Counts violations: slots or indices out of range, an output
+// row written twice, accumulated before it was written, or never written.
+int emulate_fj(const HostTables &t, const double *k, const double *y_species, double *f, double *jac)
+{
+    const int N = t.N, R = t.R;
+    int bad = 0;
+    std::vector<int> written(N + t.nnz, 0);
+    std::vector<double> out(N + t.nnz, 0.0);
+    if (t.fj_items.empty() || (int)t.fj_items.size() != t.n_fitems + t.n_jitems + 1) return 1;
+    for (int it = 0; it + 1 < (int)t.fj_items.size(); ++it) {
+        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
+            const FjChunk &ch = t.fj_chunks[ci];
+            if (ch.n_mono > kFjQmax) bad++;
+            double scratch[kFjQmax] = {0};
+            for (int q = 0; q < ch.n_mono && q < kFjQmax; ++q) {
+                const FjMono &m = t.fj_monos[ch.mono_begin + q];
+                if (m.j < 0 || m.j >= R) { bad++; continue; }
+                double v = k[m.j];
+                for (int f3 : {m.a, m.b, m.c}) {
+                    if (f3 >= N || f3 < -1) { bad++; continue; }
+                    if (f3 >= 0) v *= y_species[f3];
+                }
+                scratch[q] = v;
+            }
+            for (int o = 0; o < ch.n_out; ++o) {
+                const FjOut &fo = t.fj_outs[ch.out_begin + o];
+                if (fo.row < 0 || fo.row >= N + t.nnz) { bad++; continue; }
+                double acc = 0.0;
+                for (int q = fo.t_begin; q < fo.t_begin + fo.t_count; ++q) {
+                    const FjTerm &tm = t.fj_terms[q];
+                    if (tm.slot < 0 || tm.slot >= ch.n_mono) { bad++; continue; }
+                    acc += tm.coef * scratch[tm.slot];
+                }
+                if (fo.accum) {
+                    if (written[fo.row] != 1) bad++;
+                    out[fo.row] += acc;
+                } else {
+                    if (written[fo.row]) bad++;
+                    written[fo.row] = 1;
+                    out[fo.row] = acc;
+                }
+            }
+        }
+        if (it + 1 == t.n_fitems) {  // f items cover exactly the f rows
+            for (int r = 0; r < N; ++r)
+                if (!written[r]) bad++;
+        }
+    }
+    for (int r = 0; r < N + t.nnz; ++r)
+        if (!written[r]) bad++;
+    for (int r = 0; r < N; ++r) f[r] = out[r];
+    for (int e = 0; e < t.nnz; ++e) jac[e] = out[N + e];
+    return bad;
+}
+
 }  // namespace mcc

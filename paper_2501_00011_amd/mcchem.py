@@ -69,6 +69,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_mech_op_counts": ([vp, vp], ctypes.c_int),
         "mcc_debug_emulate_cell": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_debug_schedule_info": ([vp, vp], ctypes.c_int),
+        "mcc_debug_emulate_fj": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_mech_destroy": ([vp], ctypes.c_int),
         "mcc_cells_create": ([vp, i64, i64, vp], ctypes.c_int),
         "mcc_cells_bind": ([vp, vp, vp, vp, vp], ctypes.c_int),
@@ -164,6 +165,18 @@ class Mechanism:
         _check(library().mcc_debug_emulate_cell(self._h, k.ctypes.data, y.ctypes.data, float(c), b.ctypes.data,
                                                 f.ctypes.data, x.ctypes.data, ctypes.byref(v)))
         return f, x, v.value
+
+    def emulate_fj(self, k, y):
+        """Host emulation of the f/J kernel's tables for one cell (testing
+        aid): returns (f, J nonzeros in CSR order, violations)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        f = np.zeros(self.n_species)
+        J = np.zeros(max(self.nnz, 1))
+        v = ctypes.c_int32()
+        _check(library().mcc_debug_emulate_fj(self._h, k.ctypes.data, y.ctypes.data, f.ctypes.data,
+                                              J.ctypes.data, ctypes.byref(v)))
+        return f, J[:self.nnz], v.value
 
     def schedule_info(self) -> dict:
         """Sizes of the solver schedule (testing aid)."""

@@ -292,3 +292,18 @@ def test_errors_before_bind_and_bad_args(dev):
         h.close()  # a batch is still alive
     cells.close()
     h.close()
+
+
+def test_fj_split_unit_accumulates(dev, oracle_mod):
+    """One species changed by 59 reactions: its f row and J rows span two
+    chunks of the f/J kernel, the second adding to what the first wrote."""
+    n = 60
+    rx = [([i], [(0, 1.0)], 1e-3 * (i + 1), 0.0, 0) for i in range(1, n)]
+    rx.append(([0, 1], [(2, 0.5), (3, 0.5)], 1e-2, 0.0, 0))
+    m = synth.mechanism_from_lists(n, rx)
+    cells = synth.Cells(T=np.full(130, 280.0), P=np.full(130, 1000.0), jscale=np.ones(130),
+                        y0=np.random.default_rng(3).uniform(0.5, 2.0, size=(n, 130)))
+    b = Batch(dev, m, cells, oracle_mod=oracle_mod)
+    f, J = b.cells.deriv_jac(b.y_dev())
+    torch.cuda.synchronize()
+    _check_fj(b, f.cpu().numpy(), J.cpu().numpy(), cells.y0)

@@ -48,3 +48,37 @@ def test_emulator_handles_tiny_mechanisms():
         f, x, viol = h.emulate_cell(np.array([r[2] for r in rx]), y, 0.1, np.ones(n))
         assert viol == 0
         assert np.all(np.isfinite(x))
+
+
+@pytest.mark.parametrize("mech_fn", [synth.mech_small_thermal, synth.mech_small, synth.mech_medium,
+                                     synth.mech_large])
+def test_emulated_fj_tables_match_oracle(oracle_mod, mech_fn):
+    m = mech_fn()
+    h = mcchem.Mechanism(m, device=-1)
+    o = oracle_mod.Oracle(m)
+    cells = synth.make_cells(m, 3, seed=37)
+    k = o.rate_constants(cells.T, cells.jscale)
+    f_ref, fs = o.deriv(k, cells.y0)
+    J_ref, Js = o.jac(k, cells.y0)
+    rp, ci = h.jac_pattern()
+    rows = np.repeat(np.arange(m.n_species), np.diff(rp))
+    for cell in range(3):
+        f, J, viol = h.emulate_fj(k[:, cell], cells.y0[:, cell])
+        assert viol == 0
+        assert np.all(np.abs(f - f_ref[:, cell]) <= 1e-12 * fs[:, cell])
+        assert np.all(np.abs(J - J_ref[cell][rows, ci]) <= 1e-12 * Js[cell][rows, ci])
+
+
+def test_fj_tables_split_wide_units():
+    """A species changed by more reactions than one chunk holds is split into
+    parts that accumulate into the same output."""
+    n = 60
+    rx = [([i], [(0, 1.0)], 1e-3 * (i + 1), 0.0, 0) for i in range(1, n)]
+    m = synth.mechanism_from_lists(n, rx)
+    h = mcchem.Mechanism(m, device=-1)
+    k = np.array([r[2] for r in rx])
+    y = np.linspace(1.0, 2.0, n)
+    f, J, viol = h.emulate_fj(k, y)
+    assert viol == 0
+    assert f[0] == pytest.approx(float(np.sum(k * y[1:])), rel=1e-14)
+    np.testing.assert_allclose(f[1:], -k * y[1:], rtol=1e-15)
