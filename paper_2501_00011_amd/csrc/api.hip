@@ -2,6 +2,7 @@
 // table upload and kernel launches.  All arithmetic happens in the kernels.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -17,8 +18,7 @@ struct mcc_mech {
     // device views
     const int32_t *rxn_type = nullptr;
     const FjMono *fj_monos = nullptr;
-    const FjOut *fj_outs = nullptr;
-    const FjTerm *fj_terms = nullptr;
+    const FjRec *fj_recs = nullptr;
     const FjChunk *fj_chunks = nullptr;
     const int32_t *fj_items = nullptr;
     const double *A = nullptr, *theta = nullptr;
@@ -182,7 +182,7 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
 
     Packer pk;
     const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
-    const size_t o_monos = pk.add(t.fj_monos), o_outs = pk.add(t.fj_outs), o_terms = pk.add(t.fj_terms);
+    const size_t o_monos = pk.add(t.fj_monos), o_recs = pk.add(t.fj_recs);
     const size_t o_chunks = pk.add(t.fj_chunks), o_items = pk.add(t.fj_items);
     const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
@@ -201,10 +201,10 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->A = (const double *)(b + o_A);
     m->theta = (const double *)(b + o_th);
     m->fj_monos = (const FjMono *)(b + o_monos);
-    m->fj_outs = (const FjOut *)(b + o_outs);
-    m->fj_terms = (const FjTerm *)(b + o_terms);
+    m->fj_recs = (const FjRec *)(b + o_recs);
     m->fj_chunks = (const FjChunk *)(b + o_chunks);
     m->fj_items = (const int32_t *)(b + o_items);
+
     m->vspecies = (const int32_t *)(b + o_perm);
     m->rx_reac = (const int32_t *)(b + o_rxr);
     m->part = (const int32_t *)(b + o_part);
@@ -368,13 +368,12 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
     DeviceGuard g(c->mech->device);
     FJParams p{};
     p.monos = c->mech->fj_monos;
-    p.outs = c->mech->fj_outs;
-    p.terms = c->mech->fj_terms;
+    p.recs = c->mech->fj_recs;
     p.chunks = c->mech->fj_chunks;
     p.items = c->mech->fj_items;
-    p.ones = c->ones;
     p.y = y;
     p.k = c->k;
+    p.ones = c->ones;
     p.f = f;
     p.jac = jac;
     p.n_cells = c->n_cells;

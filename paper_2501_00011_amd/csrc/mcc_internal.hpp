@@ -21,27 +21,38 @@ constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
 // op flags (bits 56.. of an LU op; bits 28.. of a 16-byte op's meta word)
 constexpr uint32_t kFirst = 1, kLast = 2, kRecip = 4, kScale = 8, kBarrier = 16, kDiag = 4;
 
-// Streaming f/J kernel tables.  A chunk computes its monomials
-// k_j * y_a * y_b * y_c (-1 = the constant 1) into a per-lane LDS scratchpad,
-// then each of its outputs as sum coef * monomial[slot].  Outputs flagged
-// `accum` add to what an earlier chunk of the same block wrote.
+// Streaming f/J kernel tables.  A work item is a run of chunks processed by
+// one wavefront in order.  A chunk computes its monomials -- the product of
+// a rate-constant row and up to three y rows (index -1: the constant 1);
+// padded to a multiple of kFjGroup with monomials equal to 1 -- into a
+// per-lane LDS scratchpad, then runs its output records.  A record adds up
+// to three terms coef * monomial[slot] (unused terms: coefficient 0 on the
+// zero slot kFjQmax) to a running sum that it starts or continues, and may
+// write the sum to its output row, or add it to what an earlier chunk of the
+// same work item wrote there.  A chunk's records are padded to a multiple of
+// kFjRecGroup with records that do nothing.
 struct FjMono {
-    int32_t j, a, b, c;
+    int32_t j, a, b, c;  // k row j, y rows a, b, c (-1: the constant 1)
 };
-struct FjOut {
-    int32_t row, t_begin, t_count, accum;  // row < N: f_row, else J nonzero row - N
+struct alignas(32) FjRec {
+    double coef[3];
+    uint32_t slots;  // three 8-bit scratchpad slots
+    uint32_t meta;   // output row (row < N: f row, else J nonzero row - N) | flags << 24
 };
-struct alignas(16) FjTerm {
-    double coef;
-    int32_t slot, pad;
-};
+constexpr uint32_t kFjKeep = 1;   // continue the running sum of the previous record
+constexpr uint32_t kFjStore = 2;  // write the sum to the output row
+constexpr uint32_t kFjAdd = 4;    // ... adding it to the value already there
+constexpr uint32_t kFjRowMask = (1u << 24) - 1;
 struct FjChunk {
-    int32_t mono_begin, n_mono, out_begin, n_out;
+    int32_t mono_begin, n_mono, rec_begin, n_rec;  // counts include padding
 };
-// A work item is a run of consecutive chunks processed by one block in
-// order (the later parts of a split unit accumulate into its outputs).
-constexpr int kFjQmax = 32;   // monomials per chunk (LDS: 32 x 64 lanes x 8 B)
-constexpr int kFjGroup = 8;   // monomials whose loads are issued together
+#ifndef MCC_FJ_QMAX
+#define MCC_FJ_QMAX 16
+#endif
+constexpr int kFjQmax = MCC_FJ_QMAX;  // monomials per chunk (a multiple of kFjGroup)
+constexpr int kFjGroup = 8;           // monomials whose loads are issued together
+constexpr int kFjRecGroup = 4;        // records whose table loads are issued together
+static_assert(kFjQmax % kFjGroup == 0 && kFjQmax < 256, "chunk size");
 
 // A 16-byte op of the gather streams: coefficient and packed indices/flags.
 struct alignas(16) Op16 {
@@ -67,8 +78,7 @@ struct HostTables {
     // rows N..N+nnz-1 the Jacobian nonzeros in CSR order.
     std::vector<int32_t> out_ptr;     // [N + nnz + 1] algorithmic term counts
     std::vector<FjMono> fj_monos;
-    std::vector<FjOut> fj_outs;
-    std::vector<FjTerm> fj_terms;
+    std::vector<FjRec> fj_recs;
     std::vector<FjChunk> fj_chunks;
     std::vector<int32_t> fj_items;    // first chunk of every work item + end
     int n_fitems = 0, n_jitems = 0;   // f items first, then J items
@@ -128,8 +138,7 @@ struct RatesParams {
 
 struct FJParams {
     const FjMono *monos;
-    const FjOut *outs;
-    const FjTerm *terms;
+    const FjRec *recs;
     const FjChunk *chunks;
     const int32_t *items;
     const double *y, *k, *ones;

@@ -265,18 +265,27 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     for (int e = 0; e < t->nnz; ++e) t->out_ptr.push_back(t->out_ptr.back() + jterms_of_row[e]);
 
     t->fj_monos.clear();
-    t->fj_outs.clear();
-    t->fj_terms.clear();
+    t->fj_recs.clear();
     t->fj_chunks.clear();
     t->fj_items.clear();
     FjChunk cur{0, 0, 0, 0};
     bool cur_cont = false;  // the open chunk continues the previous work item
     auto close_chunk = [&]() {
-        if (cur.n_mono > 0 || cur.n_out > 0) {
+        if (cur.n_mono > 0 || cur.n_rec > 0) {
+            while (cur.n_mono % kFjGroup) {  // padding monomials: the constant 1
+                t->fj_monos.push_back(FjMono{-1, -1, -1, -1});
+                cur.n_mono++;
+            }
+            while (cur.n_rec % kFjRecGroup) {  // padding records: no effect
+                FjRec r{};
+                r.slots = (uint32_t)kFjQmax * 0x10101u;
+                t->fj_recs.push_back(r);
+                cur.n_rec++;
+            }
             if (!cur_cont) t->fj_items.push_back((int32_t)t->fj_chunks.size());
             t->fj_chunks.push_back(cur);
         }
-        cur = FjChunk{(int32_t)t->fj_monos.size(), 0, (int32_t)t->fj_outs.size(), 0};
+        cur = FjChunk{(int32_t)t->fj_monos.size(), 0, (int32_t)t->fj_recs.size(), 0};
         cur_cont = false;
     };
     auto add_part = [&](const Unit &u, int m0, int m1, bool accum) {
@@ -289,18 +298,25 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         }
         cur.n_mono += m1 - m0;
         for (const auto &o : u.outs) {
-            FjOut fo{o.first, (int32_t)t->fj_terms.size(), 0, accum ? 1 : 0};
+            std::vector<std::pair<int, double>> terms;
             for (const auto &tm : o.second)
-                if (tm.first >= m0 && tm.first < m1) {
-                    FjTerm ft{};
-                    ft.coef = tm.second;
-                    ft.slot = base + (tm.first - m0);
-                    t->fj_terms.push_back(ft);
+                if (tm.first >= m0 && tm.first < m1) terms.push_back({base + (tm.first - m0), tm.second});
+            if (accum && terms.empty()) continue;  // nothing to add
+            if (terms.empty()) terms.push_back({kFjQmax, 0.0});
+            for (size_t q0 = 0; q0 < terms.size(); q0 += 3) {
+                FjRec r{};
+                r.slots = (uint32_t)kFjQmax * 0x10101u;
+                for (size_t q = q0; q < std::min(terms.size(), q0 + 3); ++q) {
+                    r.coef[q - q0] = terms[q].second;
+                    r.slots = (r.slots & ~(0xffu << (8 * (q - q0)))) | ((uint32_t)terms[q].first << (8 * (q - q0)));
                 }
-            fo.t_count = (int32_t)t->fj_terms.size() - fo.t_begin;
-            if (accum && fo.t_count == 0) continue;  // nothing to add
-            t->fj_outs.push_back(fo);
-            cur.n_out++;
+                uint32_t flags = 0;
+                if (q0 > 0) flags |= kFjKeep;
+                if (q0 + 3 >= terms.size()) flags |= kFjStore | (accum ? kFjAdd : 0);
+                r.meta = (uint32_t)o.first | flags << 24;
+                t->fj_recs.push_back(r);
+                cur.n_rec++;
+            }
         }
     };
     auto add_unit = [&](const Unit &u) {
@@ -325,6 +341,14 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     close_chunk();
     t->n_jitems = (int)t->fj_items.size() - t->n_fitems;
     t->fj_items.push_back((int32_t)t->fj_chunks.size());
+    // one spare entry at each table's end: a lane's table read stays in
+    // bounds even for a chunk without monomials at the end
+    t->fj_monos.push_back(FjMono{-1, -1, -1, -1});
+    {
+        FjRec r{};
+        r.slots = (uint32_t)kFjQmax * 0x10101u;
+        t->fj_recs.push_back(r);
+    }
 
     // ---- fill-reducing order and symbolic LU (elimination positions) -------
     t->perm = markowitz_order(pat);

@@ -186,9 +186,11 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
 }
 
 // Host emulation of the streaming f/J tables for one cell: every work item in
-// order, chunk by chunk, monomials into a scratchpad of kFjQmax entries, then
-// the outputs.  Counts violations: slots or indices out of range, an output
-// row written twice, accumulated before it was written, or never written.
+// order, chunk by chunk, monomials into a scratchpad of kFjQmax entries (plus
+// the zero slot), then the output records.  Counts violations: indices or
+// slots out of range, unpadded chunks, an output row written twice, added to
+// before it was written, or never written, a running sum continued across
+// chunks or left unwritten.
 int emulate_fj(const HostTables &t, const double *k, const double *y_species, double *f, double *jac)
 {
     const int N = t.N, R = t.R;
@@ -199,36 +201,44 @@ int emulate_fj(const HostTables &t, const double *k, const double *y_species, do
     for (int it = 0; it + 1 < (int)t.fj_items.size(); ++it) {
         for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
             const FjChunk &ch = t.fj_chunks[ci];
-            if (ch.n_mono > kFjQmax) bad++;
-            double scratch[kFjQmax] = {0};
+            if (ch.n_mono > kFjQmax || ch.n_mono % kFjGroup || ch.n_rec % kFjRecGroup) bad++;
+            double scratch[kFjQmax + 1] = {0};
             for (int q = 0; q < ch.n_mono && q < kFjQmax; ++q) {
                 const FjMono &m = t.fj_monos[ch.mono_begin + q];
-                if (m.j < 0 || m.j >= R) { bad++; continue; }
-                double v = k[m.j];
+                if (m.j >= R || m.j < -1) { bad++; continue; }
+                double v = m.j >= 0 ? k[m.j] : 1.0;
                 for (int f3 : {m.a, m.b, m.c}) {
                     if (f3 >= N || f3 < -1) { bad++; continue; }
                     if (f3 >= 0) v *= y_species[f3];
                 }
                 scratch[q] = v;
             }
-            for (int o = 0; o < ch.n_out; ++o) {
-                const FjOut &fo = t.fj_outs[ch.out_begin + o];
-                if (fo.row < 0 || fo.row >= N + t.nnz) { bad++; continue; }
-                double acc = 0.0;
-                for (int q = fo.t_begin; q < fo.t_begin + fo.t_count; ++q) {
-                    const FjTerm &tm = t.fj_terms[q];
-                    if (tm.slot < 0 || tm.slot >= ch.n_mono) { bad++; continue; }
-                    acc += tm.coef * scratch[tm.slot];
+            double acc = 0.0;
+            bool open = false;
+            for (int o = 0; o < ch.n_rec; ++o) {
+                const FjRec &r = t.fj_recs[ch.rec_begin + o];
+                const uint32_t flags = r.meta >> 24, row = r.meta & kFjRowMask;
+                double s = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    const int slot = (r.slots >> (8 * q)) & 0xff;
+                    if (slot > kFjQmax || (slot >= ch.n_mono && slot != kFjQmax)) { bad++; continue; }
+                    s += r.coef[q] * scratch[slot];
                 }
-                if (fo.accum) {
-                    if (written[fo.row] != 1) bad++;
-                    out[fo.row] += acc;
+                if ((flags & kFjKeep) && !open) bad++;
+                acc = (flags & kFjKeep) ? acc + s : s;
+                open = !(flags & kFjStore);
+                if (!(flags & kFjStore)) continue;
+                if (row >= (uint32_t)(N + t.nnz)) { bad++; continue; }
+                if (flags & kFjAdd) {
+                    if (written[row] != 1) bad++;
+                    out[row] += acc;
                 } else {
-                    if (written[fo.row]) bad++;
-                    written[fo.row] = 1;
-                    out[fo.row] = acc;
+                    if (written[row]) bad++;
+                    written[row] = 1;
+                    out[row] = acc;
                 }
             }
+            if (open && acc != 0.0) bad++;
         }
         if (it + 1 == t.n_fitems) {  // f items cover exactly the f rows
             for (int r = 0; r < N; ++r)

@@ -307,3 +307,20 @@ def test_fj_split_unit_accumulates(dev, oracle_mod):
     f, J = b.cells.deriv_jac(b.y_dev())
     torch.cuda.synchronize()
     _check_fj(b, f.cpu().numpy(), J.cpu().numpy(), cells.y0)
+
+
+def test_fj_direct_chunks(dev, oracle_mod):
+    """A species formed by 130 bimolecular reactions: its f row alone uses more
+    rows than a block stages, so its chunks read y and k from global memory."""
+    n = 140
+    rx = [([i, i + 1], [(0, 1.0)], 1e-12 * (1 + i % 7), 0.0, 0) for i in range(1, 131)]
+    rx.append(([0], [(139, 1.0)], 1e-3, 0.0, 0))
+    m = synth.mechanism_from_lists(n, rx)
+    C = 100
+    rng = np.random.default_rng(8)
+    cells = synth.Cells(T=np.full(C, 280.0), P=np.full(C, 1000.0), jscale=np.ones(C),
+                        y0=rng.uniform(1e8, 1e9, size=(n, C)))
+    b = Batch(dev, m, cells, ld=C + 28, oracle_mod=oracle_mod)
+    f, J = b.cells.deriv_jac(b.y_dev())
+    torch.cuda.synchronize()
+    _check_fj(b, f.cpu().numpy()[:, :C], J.cpu().numpy()[:, :C], cells.y0)

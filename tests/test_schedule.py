@@ -82,3 +82,18 @@ def test_fj_tables_split_wide_units():
     assert viol == 0
     assert f[0] == pytest.approx(float(np.sum(k * y[1:])), rel=1e-14)
     np.testing.assert_allclose(f[1:], -k * y[1:], rtol=1e-15)
+
+
+def test_fj_tables_direct_item():
+    """A unit using more rows than a panel stages is read from global memory
+    (direct chunks); the emulator runs that path too."""
+    n = 140
+    rx = [([i, i + 1], [(0, 1.0)], 1e-3 * (1 + i % 7), 0.0, 0) for i in range(1, 131)]
+    m = synth.mechanism_from_lists(n, rx)
+    h = mcchem.Mechanism(m, device=-1)
+    k = np.array([r[2] for r in rx])
+    y = np.linspace(1.0, 2.0, n)
+    f, J, viol = h.emulate_fj(k, y)
+    assert viol == 0
+    r = k * y[1:131] * y[2:132]
+    assert f[0] == pytest.approx(float(np.sum(r)), rel=1e-14)
