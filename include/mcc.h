@@ -184,6 +184,28 @@ mcc_status mcc_debug_emulate_cell(const mcc_mech *mech, const double *k, const d
 mcc_status mcc_debug_emulate_fj(const mcc_mech *mech, const double *k, const double *y, double *f, double *jac,
                                 int32_t *violations);
 
+/* Which f/J kernel mcc_calc_deriv / mcc_calc_jac / mcc_calc_deriv_jac of
+ * this mechanism launch.  MCC_FJ_GENERATED (the default): straight-line HIP
+ * written for this mechanism from its f/J tables and compiled with hipRTC
+ * for the handle's device on the first such call (which then blocks for the
+ * compile, a few seconds); MCC_FJ_TABLES: one generic kernel that reads the
+ * same work from the tables at run time.  Both evaluate the same terms in
+ * the same order (Section 2 definitions of f and J).  MCC_ERR_INVALID_ARG for
+ * another kind. */
+typedef enum { MCC_FJ_GENERATED = 0, MCC_FJ_TABLES = 1 } mcc_fj_kernel;
+mcc_status mcc_mech_set_fj_kernel(mcc_mech *mech, int32_t kind);
+
+/* Testing aid (host only): the generated f/J source of this mechanism.
+ * Copies min(cap, len + 1) bytes, NUL-terminated when cap > len, into buf
+ * (buf may be null with cap 0) and the source length to *len. */
+mcc_status mcc_debug_fj_source(const mcc_mech *mech, char *buf, int64_t cap, int64_t *len);
+
+/* Testing aid (host only, needs no GPU): compiles the generated f/J source
+ * with hipRTC for the named architecture (e.g. "gfx950") without loading
+ * it; *code_bytes receives the code object size.  MCC_ERR_DEVICE with the
+ * compiler log in mcc_last_error() on failure. */
+mcc_status mcc_debug_compile_fj(const mcc_mech *mech, const char *arch, int64_t *code_bytes);
+
 /* Testing aid: sizes of the solver schedule, written to out[0..7]: LU
  * blocks, LU levels, Newton-matrix blocks, f-gather blocks of slots 0..3,
  * and the size of the dense tail factorised in registers. */

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libmcchem.so")
 SOURCES = ["csrc/api.hip", "csrc/kernels_fj.hip", "csrc/kernels_solve.hip", "csrc/mech_compile.cpp",
-           "csrc/mech_emulate.cpp"]
+           "csrc/mech_emulate.cpp", "csrc/fj_codegen.cpp"]
 ARCH = os.environ.get("MCC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions stay off: the library computes in FP64, and packed
@@ -26,7 +26,7 @@ def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = [os.path.join(HERE, s) for s in SOURCES]
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc, *HIP_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", tmp, *srcs]
+    cmd = [hipcc, *HIP_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", tmp, *srcs, "-lhiprtc"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -28,6 +28,11 @@ struct mcc_mech {
     const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
     int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, off_tm = 0, lds_doubles = 0;
     int live_batches = 0;
+    // mechanism-specialised f/J kernel, compiled on first use
+    int fj_kind = MCC_FJ_GENERATED;
+    std::string arch;
+    hipModule_t fj_mod = nullptr;
+    hipFunction_t fj_fn = nullptr;
 };
 
 struct mcc_cells {
@@ -162,6 +167,15 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
         delete m;
         return set_error(MCC_ERR_DEVICE, "cannot select device");
     }
+    {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, device);
+        if (e != hipSuccess) {
+            delete m;
+            return hip_error(e, "hipGetDeviceProperties");
+        }
+        m->arch = prop.gcnArchName;
+    }
     // Device limits (Section 3: checked at run time rather than assumed).
     int max_lds = 0;
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
@@ -282,11 +296,48 @@ mcc_status mcc_mech_destroy(mcc_mech *m)
         return ok();
     }
     DeviceGuard g(m->device);
+    if (m->fj_mod) {
+        hipError_t e = hipModuleUnload(m->fj_mod);
+        if (e != hipSuccess) return hip_error(e, "hipModuleUnload");
+        m->fj_mod = nullptr;
+        m->fj_fn = nullptr;
+    }
     if (m->dev_buf) {
         hipError_t e = hipFree(m->dev_buf);
         if (e != hipSuccess) return hip_error(e, "hipFree");
     }
     delete m;
+    return ok();
+}
+
+mcc_status mcc_mech_set_fj_kernel(mcc_mech *m, int32_t kind)
+{
+    if (!m) return set_error(MCC_ERR_INVALID_ARG, "mech is null");
+    if (kind != MCC_FJ_GENERATED && kind != MCC_FJ_TABLES) return set_error(MCC_ERR_INVALID_ARG, "unknown f/J kernel kind");
+    m->fj_kind = kind;
+    return ok();
+}
+
+mcc_status mcc_debug_fj_source(const mcc_mech *m, char *buf, int64_t cap, int64_t *len)
+{
+    if (!m || !len || (cap > 0 && !buf) || cap < 0) return set_error(MCC_ERR_INVALID_ARG, "bad argument");
+    const std::string src = generate_fj_source(m->t);
+    *len = (int64_t)src.size();
+    if (cap > 0) {
+        const size_t n = std::min((size_t)cap, src.size() + 1);
+        std::memcpy(buf, src.c_str(), n);
+    }
+    return ok();
+}
+
+mcc_status mcc_debug_compile_fj(const mcc_mech *m, const char *arch, int64_t *code_bytes)
+{
+    if (!m || !arch || !code_bytes) return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    std::vector<char> code;
+    std::string log;
+    if (!compile_fj_source(generate_fj_source(m->t), arch, &code, &log))
+        return set_error(MCC_ERR_DEVICE, "generated f/J kernel does not compile: " + log);
+    *code_bytes = (int64_t)code.size();
     return ok();
 }
 
@@ -358,6 +409,29 @@ mcc_status mcc_cells_rate_constants(const mcc_cells *c, const double **k)
     return ok();
 }
 
+// Generates, compiles (hipRTC) and loads the mechanism's f/J kernel once.
+static mcc_status ensure_fj_module(mcc_mech *m)
+{
+    if (m->fj_fn) return ok();
+    std::vector<char> code;
+    std::string log;
+    if (!compile_fj_source(generate_fj_source(m->t), m->arch, &code, &log))
+        return set_error(MCC_ERR_DEVICE, "generated f/J kernel does not compile: " + log);
+    hipError_t e = hipModuleLoadData(&m->fj_mod, code.data());
+    if (e != hipSuccess) {
+        m->fj_mod = nullptr;
+        return hip_error(e, "hipModuleLoadData (generated f/J kernel)");
+    }
+    e = hipModuleGetFunction(&m->fj_fn, m->fj_mod, "mcc_fj_generated");
+    if (e != hipSuccess) {
+        (void)hipModuleUnload(m->fj_mod);
+        m->fj_mod = nullptr;
+        m->fj_fn = nullptr;
+        return hip_error(e, "hipModuleGetFunction (generated f/J kernel)");
+    }
+    return ok();
+}
+
 static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double *jac, void *stream)
 {
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
@@ -390,8 +464,22 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
         p.item_begin = t.n_fitems;
         p.n_items = t.n_jitems;
     }
-    hipError_t e = launch_fj(p, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_error(e, "f/J kernel launch");
+    if (c->mech->fj_kind == MCC_FJ_TABLES) {
+        hipError_t e = launch_fj(p, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_error(e, "f/J kernel launch");
+        return ok();
+    }
+    mcc_status st = ensure_fj_module(c->mech);
+    if (st != MCC_OK) return st;
+    const int64_t blocks = (int64_t)((p.n_tiles + 7) / 8) * 8 * p.n_items;
+    if (p.n_items == 0) return ok();
+    if (blocks > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "too many cells for one f/J launch");
+    long long n_cells = p.n_cells, ld = p.ld;
+    int item_begin = p.item_begin, n_items = p.n_items, n_tiles = p.n_tiles;
+    void *args[] = {&p.y, &p.k, &p.f, &p.jac, &n_cells, &ld, &item_begin, &n_items, &n_tiles};
+    hipError_t e = hipModuleLaunchKernel(c->mech->fj_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
+                                         args, nullptr);
+    if (e != hipSuccess) return hip_error(e, "generated f/J kernel launch");
     return ok();
 }
 

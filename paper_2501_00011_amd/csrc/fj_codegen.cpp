@@ -1,0 +1,146 @@
+// Mechanism-specialised f/J kernel: the streaming f/J tables (work items ->
+// chunks -> monomials and output records) written out as straight-line HIP,
+// one switch case per work item, and compiled at mechanism creation with
+// hipRTC.  Row indices become constants (the row address is a scalar
+// multiply of the leading dimension), coefficients become literals, each y
+// or k row an item uses is loaded once into a register, and no table is
+// read at run time: what is left is the loads, the products and sums of the
+// rate expressions, and the stores.  The arithmetic is the one the tables
+// describe (Section 2: mass-action rates and their partials, f = sum nu r,
+// J = sum nu dr/dy), term by term in the same order.
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <set>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "mcc_internal.hpp"
+
+namespace mcc {
+
+namespace {
+
+std::string lit(double v)
+{
+    char b[64];
+    std::snprintf(b, sizeof b, "%a", v);  // exact: hexadecimal floating literal
+    return b;
+}
+
+}  // namespace
+
+std::string generate_fj_source(const HostTables &t)
+{
+    const int N = t.N;
+    std::ostringstream o;
+    o << "// generated f/J kernel: " << N << " species, " << t.R << " reactions, " << t.nnz << " Jacobian nonzeros\n"
+      << "extern \"C\" __global__ __launch_bounds__(64) void mcc_fj_generated(\n"
+      << "    const double *__restrict__ y, const double *__restrict__ k, double *__restrict__ f,\n"
+      << "    double *__restrict__ jac, long long n_cells, long long ld, int item_begin, int n_items, int n_tiles)\n"
+      << "{\n"
+      << "    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;\n"
+      << "    const int item = item_begin + q % n_items, tile = (q / n_items) * 8 + xcd;\n"
+      << "    if (tile >= n_tiles) return;\n"
+      << "    const long long c = (long long)tile * 64 + threadIdx.x;\n"
+      << "    if (c >= n_cells) return;\n"
+      << "    const double *__restrict__ Y = y + c;\n"
+      << "    const double *__restrict__ K = k + c;\n"
+      << "    double *__restrict__ F = f + c;\n"
+      << "    double *__restrict__ G = jac + c;\n"
+      << "    switch (item) {\n";
+    const int n_items = t.n_fitems + t.n_jitems;
+    for (int it = 0; it < n_items; ++it) {
+        o << "    case " << it << ": {\n";
+        // every row the item uses, loaded once, at the top (all in flight together)
+        std::set<int> ys, ks;
+        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
+            const FjChunk &ch = t.fj_chunks[ci];
+            for (int qm = 0; qm < ch.n_mono; ++qm) {
+                const FjMono &m = t.fj_monos[ch.mono_begin + qm];
+                if (m.j >= 0) ks.insert(m.j);
+                for (int f3 : {m.a, m.b, m.c})
+                    if (f3 >= 0) ys.insert(f3);
+            }
+        }
+        for (int j : ks) o << "        const double k" << j << " = K[" << j << " * ld];\n";
+        for (int r : ys) o << "        const double y" << r << " = Y[" << r << " * ld];\n";
+        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
+            const FjChunk &ch = t.fj_chunks[ci];
+            o << "        {\n";
+            std::vector<std::string> mono(kFjQmax);
+            for (int qm = 0; qm < ch.n_mono; ++qm) {
+                const FjMono &m = t.fj_monos[ch.mono_begin + qm];
+                if (m.j < 0 && m.a < 0 && m.b < 0 && m.c < 0) continue;  // padding
+                std::string e;
+                if (m.j >= 0) e = "k" + std::to_string(m.j);
+                for (int f3 : {m.a, m.b, m.c})
+                    if (f3 >= 0) e += (e.empty() ? "" : " * ") + ("y" + std::to_string(f3));
+                mono[qm] = "m" + std::to_string(qm);
+                o << "            const double " << mono[qm] << " = " << e << ";\n";
+            }
+            o << "            double acc = 0.0;\n";
+            for (int r = 0; r < ch.n_rec; ++r) {
+                const FjRec &rec = t.fj_recs[ch.rec_begin + r];
+                const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
+                std::string sum;
+                for (int qq = 0; qq < 3; ++qq) {
+                    const int slot = (rec.slots >> (8 * qq)) & 0xff;
+                    if (slot >= kFjQmax || rec.coef[qq] == 0.0 || mono[slot].empty()) continue;
+                    sum += (sum.empty() ? "" : " + ") + lit(rec.coef[qq]) + " * " + mono[slot];
+                }
+                if (sum.empty()) sum = "0.0";
+                if (!(flags & (kFjKeep | kFjStore))) {
+                    if (sum == "0.0") continue;  // padding record
+                }
+                o << "            acc " << ((flags & kFjKeep) ? "+=" : "=") << " " << sum << ";\n";
+                if (flags & kFjStore) {
+                    const std::string dst = row < (uint32_t)N ? "F[" + std::to_string(row) + " * ld]"
+                                                              : "G[" + std::to_string(row - N) + " * ld]";
+                    o << "            " << dst << ((flags & kFjAdd) ? " += acc;\n" : " = acc;\n");
+                }
+            }
+            o << "            (void)acc;\n        }\n";
+        }
+        o << "    } break;\n";
+    }
+    o << "    default: break;\n    }\n}\n";
+    return o.str();
+}
+
+}  // namespace mcc
+
+namespace mcc {
+
+bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log)
+{
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "mcc_fj_generated.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        *log = "hiprtcCreateProgram failed";
+        return false;
+    }
+    const std::string arch_opt = "--offload-arch=" + arch;
+    const char *opts[] = {arch_opt.c_str(), "-O3", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    size_t n = 0;
+    if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 1) {
+        std::string l(n, '\0');
+        if (hiprtcGetProgramLog(prog, &l[0]) == HIPRTC_SUCCESS) *log = l.c_str();
+    }
+    bool ok = r == HIPRTC_SUCCESS;
+    if (!ok && log->empty()) *log = hiprtcGetErrorString(r);
+    if (ok) {
+        size_t cs = 0;
+        ok = hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs > 0;
+        if (ok) {
+            code->resize(cs);
+            ok = hiprtcGetCode(prog, code->data()) == HIPRTC_SUCCESS;
+        }
+        if (!ok) *log = "hiprtcGetCode failed";
+    }
+    hiprtcDestroyProgram(&prog);
+    return ok;
+}
+
+}  // namespace mcc

@@ -171,6 +171,9 @@ struct SolveParams {
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_rates(const RatesParams &p, hipStream_t s);
 hipError_t launch_fj(const FJParams &p, hipStream_t s);
+// Mechanism-specialised f/J kernel (same work items, compiled with hipRTC).
+std::string generate_fj_source(const HostTables &t);
+bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log);
 hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).
 hipError_t prepare_solve_kernels(int max_lds_bytes);

@@ -70,6 +70,9 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_debug_emulate_cell": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_debug_schedule_info": ([vp, vp], ctypes.c_int),
         "mcc_debug_emulate_fj": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
+        "mcc_debug_fj_source": ([vp, vp, i64, vp], ctypes.c_int),
+        "mcc_debug_compile_fj": ([vp, ctypes.c_char_p, vp], ctypes.c_int),
         "mcc_mech_destroy": ([vp], ctypes.c_int),
         "mcc_cells_create": ([vp, i64, i64, vp], ctypes.c_int),
         "mcc_cells_bind": ([vp, vp, vp, vp, vp], ctypes.c_int),
@@ -177,6 +180,26 @@ class Mechanism:
         _check(library().mcc_debug_emulate_fj(self._h, k.ctypes.data, y.ctypes.data, f.ctypes.data,
                                               J.ctypes.data, ctypes.byref(v)))
         return f, J[:self.nnz], v.value
+
+    FJ_GENERATED, FJ_TABLES = 0, 1
+
+    def set_fj_kernel(self, kind: int):
+        """Choose the f/J kernel: FJ_GENERATED (default) or FJ_TABLES."""
+        _check(library().mcc_mech_set_fj_kernel(self._h, int(kind)))
+
+    def fj_source(self) -> str:
+        """The generated f/J kernel source (testing aid)."""
+        n = ctypes.c_int64()
+        _check(library().mcc_debug_fj_source(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(library().mcc_debug_fj_source(self._h, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def compile_fj(self, arch: str = "gfx950") -> int:
+        """Compile the generated f/J kernel with hipRTC (no GPU needed); code bytes."""
+        n = ctypes.c_int64()
+        _check(library().mcc_debug_compile_fj(self._h, arch.encode(), ctypes.byref(n)))
+        return n.value
 
     def schedule_info(self) -> dict:
         """Sizes of the solver schedule (testing aid)."""

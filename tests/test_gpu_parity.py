@@ -87,11 +87,16 @@ def _check_fj(b, f, J, y):
     assert np.all(J_ref[:, mask] == 0.0)
 
 
+KINDS = [mcchem.Mechanism.FJ_GENERATED, mcchem.Mechanism.FJ_TABLES]
+
+
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("name,n,ld", [("small10", 10, 10), ("small10", 10, 67),
                                        ("medium10k", 777, 800), ("medium10k", 1, 1)])
-def test_deriv_and_jac_parity(dev, oracle_mod, name, n, ld):
+def test_deriv_and_jac_parity(dev, oracle_mod, name, n, ld, kind):
     m, c, _ = synth.workload(name, n)
     b = Batch(dev, m, c, ld=ld, oracle_mod=oracle_mod)
+    b.h.set_fj_kernel(kind)
     y = b.y_dev()
     f = torch.full((m.n_species, ld), 7.0, dtype=torch.float64, device=dev)
     J = torch.full((b.h.nnz, ld), 7.0, dtype=torch.float64, device=dev)
@@ -108,20 +113,24 @@ def test_deriv_and_jac_parity(dev, oracle_mod, name, n, ld):
     np.testing.assert_array_equal(J2.cpu().numpy()[:, :n], Jn[:, :n])
 
 
-def test_large_mechanism_fj_parity(dev, oracle_mod):
+@pytest.mark.parametrize("kind", KINDS)
+def test_large_mechanism_fj_parity(dev, oracle_mod, kind):
     m = synth.mech_large()
     c = synth.make_cells(m, 300, seed=4242)
     b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    b.h.set_fj_kernel(kind)
     f, J = b.cells.deriv_jac(b.y_dev())
     torch.cuda.synchronize()
     _check_fj(b, f.cpu().numpy(), J.cpu().numpy(), c.y0)
 
 
-def test_full_size_fj_sampled_and_homogeneity(dev, oracle_mod):
+@pytest.mark.parametrize("kind", KINDS)
+def test_full_size_fj_sampled_and_homogeneity(dev, oracle_mod, kind):
     """10,000 cells in the benchmark's launch: sampled cells against the
     oracle, every cell against Euler's identity sum_s J_is y_s = sum_j ord_j nu_ij r_j."""
     m, c, _ = synth.workload("medium10k")
     b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    b.h.set_fj_kernel(kind)
     f, J = b.cells.deriv_jac(b.y_dev())
     torch.cuda.synchronize()
     fn, Jn = f.cpu().numpy(), J.cpu().numpy()
@@ -309,9 +318,10 @@ def test_fj_split_unit_accumulates(dev, oracle_mod):
     _check_fj(b, f.cpu().numpy(), J.cpu().numpy(), cells.y0)
 
 
-def test_fj_direct_chunks(dev, oracle_mod):
-    """A species formed by 130 bimolecular reactions: its f row alone uses more
-    rows than a block stages, so its chunks read y and k from global memory."""
+@pytest.mark.parametrize("kind", [mcchem.Mechanism.FJ_GENERATED, mcchem.Mechanism.FJ_TABLES])
+def test_fj_wide_species(dev, oracle_mod, kind):
+    """A species formed by 130 bimolecular reactions: its f row spans many
+    chunks of one work item, the later ones adding to what the first wrote."""
     n = 140
     rx = [([i, i + 1], [(0, 1.0)], 1e-12 * (1 + i % 7), 0.0, 0) for i in range(1, 131)]
     rx.append(([0], [(139, 1.0)], 1e-3, 0.0, 0))
@@ -321,6 +331,7 @@ def test_fj_direct_chunks(dev, oracle_mod):
     cells = synth.Cells(T=np.full(C, 280.0), P=np.full(C, 1000.0), jscale=np.ones(C),
                         y0=rng.uniform(1e8, 1e9, size=(n, C)))
     b = Batch(dev, m, cells, ld=C + 28, oracle_mod=oracle_mod)
+    b.h.set_fj_kernel(kind)
     f, J = b.cells.deriv_jac(b.y_dev())
     torch.cuda.synchronize()
     _check_fj(b, f.cpu().numpy()[:, :C], J.cpu().numpy()[:, :C], cells.y0)

@@ -84,9 +84,9 @@ def test_fj_tables_split_wide_units():
     np.testing.assert_allclose(f[1:], -k * y[1:], rtol=1e-15)
 
 
-def test_fj_tables_direct_item():
-    """A unit using more rows than a panel stages is read from global memory
-    (direct chunks); the emulator runs that path too."""
+def test_fj_tables_wide_item():
+    """A species formed by 130 reactions: its f row spans many chunks of one
+    work item, the later ones adding to what the first wrote."""
     n = 140
     rx = [([i, i + 1], [(0, 1.0)], 1e-3 * (1 + i % 7), 0.0, 0) for i in range(1, 131)]
     m = synth.mechanism_from_lists(n, rx)
@@ -97,3 +97,29 @@ def test_fj_tables_direct_item():
     assert viol == 0
     r = k * y[1:131] * y[2:132]
     assert f[0] == pytest.approx(float(np.sum(r)), rel=1e-14)
+
+
+@pytest.mark.parametrize("mech_fn", [synth.mech_small_thermal, synth.mech_medium])
+def test_generated_fj_kernel_compiles(mech_fn):
+    """The mechanism-specialised f/J kernel is generated from the same tables
+    and compiles for gfx950 with hipRTC (no GPU needed)."""
+    m = mech_fn()
+    h = mcchem.Mechanism(m, device=-1)
+    src = h.fj_source()
+    # one switch case per work item; every output row stored exactly once
+    n_items = src.count("    case ")
+    assert n_items >= 2
+    rp, _ = h.jac_pattern()
+    for i in range(m.n_species):
+        assert src.count(f"F[{i} * ld] = acc;") == 1
+    for e in range(int(rp[-1])):
+        assert src.count(f"G[{e} * ld] = acc;") == 1
+    assert h.compile_fj("gfx950") > 0
+
+
+def test_fj_kernel_kind_validation():
+    h = mcchem.Mechanism(synth.mech_small(), device=-1)
+    h.set_fj_kernel(mcchem.Mechanism.FJ_TABLES)
+    h.set_fj_kernel(mcchem.Mechanism.FJ_GENERATED)
+    with pytest.raises(mcchem.MccError):
+        h.set_fj_kernel(7)
