@@ -30,8 +30,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 SOLVE_SOURCES = ["paper_2501_00011_amd/csrc/kernels_solve.hip", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
                  "paper_2501_00011_amd/csrc/mech_compile.cpp"]
-FJ_SOURCES = ["paper_2501_00011_amd/csrc/kernels_fj.hip", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
+FJ_SOURCES = ["paper_2501_00011_amd/csrc/fj_codegen.cpp", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
               "paper_2501_00011_amd/csrc/mech_compile.cpp"]
+FJ_KERNEL = "mcc_fj_generated"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_medium10k.txt")
 
 
@@ -58,10 +59,23 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium10k")
     ap.add_argument("--cells", type=int, default=None, help="override the number of cells")
-    ap.add_argument("--fj-reps", type=int, default=50, help="extra timed f+J launches for its roofline")
+    ap.add_argument("--fj-reps", type=int, default=100, help="extra timed f+J launches for its roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three device-to-device copies of 1 GiB (the reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
 
 
 def cpu_baseline(m, c, dt, target_s):
@@ -95,6 +109,9 @@ def cpu_baseline(m, c, dt, target_s):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the cells of this workload are independent and this "
               "build measures one GPU's share; use --gpus 1.", file=sys.stderr)
@@ -153,12 +170,13 @@ def main():
     solve_s = float(np.mean(solve_ms)) / 1e3
     achieved_tf = flops / solve_s / 1e12
 
-    # f+J roofline: back-to-back fused launches on the same stream
-    fj_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    for _ in range(3):
+    # f+J roofline: back-to-back fused launches between two events on the
+    # launch stream; the average launch time
+    for _ in range(10):
         cells.deriv_jac(y0, f, J, stream=stream)
+    fj_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     fj_ev[0].record(stream)
-    for _ in range(args.fj_reps):
+    for _ in range(max(args.fj_reps, 1)):
         cells.deriv_jac(y0, f, J, stream=stream)
     fj_ev[1].record(stream)
     torch.cuda.synchronize()
@@ -187,9 +205,10 @@ def main():
                      "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,
                      "traffic": measured_traffic("bdf_kernel", SOLVE_SOURCES) if C == 10000 else None,
                      "launch_ms": solve_s * 1e3, "flops_per_launch": flops},
-        "fj_roofline": {"kernel": "fj_kernel (calc_deriv_jac)", "bound": "hbm", "achieved": fj_gbs,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
-                        "traffic": measured_traffic("fj_kernel", FJ_SOURCES) if C == 10000 else None, "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
+        "fj_roofline": {"kernel": FJ_KERNEL + " (calc_deriv_jac, generated for this mechanism)", "bound": "hbm",
+                        "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
+                        "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
+                        "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
         "solver": {"failed_cells": int((st != 0).sum()),
                    "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),
                    "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),
