@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--fj-reps", type=int, default=100, help="extra timed f+J launches for its roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--steps-per-launch", type=int, default=0,
+                    help="0: each outer step in one launch (default); K > 0: the per-launch form, at most K "
+                         "accepted BDF steps per launch with the solver state in HBM between launches")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -135,7 +138,7 @@ def main():
     J = torch.empty((mech.nnz, C), dtype=torch.float64, device=dev)
     status = torch.empty(C, dtype=torch.int32, device=dev)
     stats = torch.empty((C, mcchem.STATS_DTYPE.itemsize), dtype=torch.uint8, device=dev)
-    opts = mcchem.default_opts()
+    opts = mcchem.default_opts(steps_per_launch=args.steps_per_launch)
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
@@ -199,7 +202,7 @@ def main():
         "config": {"workload": f"{m.n_species} species / {m.n_reactions} reactions, {C} cells, "
                                f"one {dt:g} s BDF step + rate constants + fused f/J per step",
                    "cells": C, "species": m.n_species, "reactions": m.n_reactions, "dt_s": dt,
-                   "rtol": opts.rtol, "atol": opts.atol},
+                   "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch},
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,

@@ -100,10 +100,17 @@ typedef struct {
  *   rejected-step factor = max(fac_min, safety * err^(-1/(k+1)));
  *   Newton-failure factor = fac_newton_fail;
  *   failure once h < h_min_rel * dt (or h vanishes against t);
- *   max_order 1..5, max_newton 1..16, max_steps >= 1 step attempts. */
+ *   max_order 1..5, max_newton 1..16, max_steps >= 1 step attempts.
+ * steps_per_launch selects how the outer step is launched (the results are
+ * identical bit for bit): 0 = the whole outer step of every cell in one
+ * launch (the default); K > 0 = the per-launch form, in which a launch takes
+ * every unfinished cell at most K accepted steps further, the cell's solver
+ * state (backward differences, t, h, order, counters) kept in HBM between
+ * launches, and the host relaunches until no cell is left (it waits for
+ * each launch, so this form cannot be captured into a graph). */
 typedef struct {
     double rtol, atol, eta_newton, safety, fac_min, fac_max, fac_newton_fail, h_min_rel;
-    int32_t max_order, max_newton, max_steps, reserved;
+    int32_t max_order, max_newton, max_steps, steps_per_launch;
 } mcc_solver_opts;
 
 /* Per-cell counters of one mcc_solve_step. */

@@ -41,6 +41,12 @@ struct mcc_cells {
     double *k = nullptr;
     double *ones = nullptr;  // [ld] of 1.0: the factor of a missing reactant
     bool bound = false;
+    // per-launch solver form: state between launches, count of unfinished cells
+    double *state = nullptr;
+    int64_t state_doubles = 0;
+    int32_t *pending = nullptr;
+    int32_t *pending_host = nullptr;  // pinned
+    int32_t call_id = 0;
 };
 
 namespace {
@@ -118,7 +124,7 @@ mcc_status mcc_solver_opts_default(mcc_solver_opts *o)
     o->max_order = 5;
     o->max_newton = 4;
     o->max_steps = 100000;
-    o->reserved = 0;
+    o->steps_per_launch = 0;
     return ok();
 }
 
@@ -516,6 +522,10 @@ static bool opts_valid(const mcc_solver_opts &o, std::string *why)
         *why = "need max_order in 1..5, max_newton in 1..16, max_steps >= 1";
         return false;
     }
+    if (o.steps_per_launch < 0) {
+        *why = "need steps_per_launch >= 0";
+        return false;
+    }
     return true;
 }
 
@@ -573,8 +583,46 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     p.ld = c->ld;
     p.dt = dt;
     p.opts = o;
-    hipError_t e = launch_solve(p, m->t.NS, m->t.M, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_error(e, "solver kernel launch");
+    if (o.steps_per_launch <= 0) {  // the whole outer step in one launch
+        hipError_t e = launch_solve(p, m->t.NS, m->t.M, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_error(e, "solver kernel launch");
+        return ok();
+    }
+    // Per-launch form: state in HBM between launches; relaunch until every
+    // cell has finished.  Every launch takes each unfinished cell at least one
+    // accepted step (or to its end), so max_steps / K + 1 launches suffice.
+    p.state_stride = (int64_t)(kMaxOrder + 3) * m->t.NV + kStateScalars;
+    const int64_t need = p.state_stride * c->n_cells;
+    hipStream_t s = (hipStream_t)stream;
+    if (c->state_doubles < need) {
+        if (c->state) (void)hipFree(c->state);
+        c->state = nullptr;
+        c->state_doubles = 0;
+        hipError_t e = hipMalloc(&c->state, (size_t)need * sizeof(double));
+        if (e != hipSuccess) return hip_error(e, "hipMalloc (solver state)");
+        e = hipMemset(c->state, 0, (size_t)need * sizeof(double));  // no call id matches 0
+        if (e != hipSuccess) return hip_error(e, "hipMemset (solver state)");
+        c->state_doubles = need;
+    }
+    if (!c->pending) {
+        hipError_t e = hipMalloc(&c->pending, sizeof(int32_t));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&c->pending_host, sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) return hip_error(e, "allocating the pending-cell counter");
+    }
+    c->call_id = c->call_id >= 0x3fffffff ? 1 : c->call_id + 1;
+    p.state = c->state;
+    p.pending = c->pending;
+    p.call_id = c->call_id;
+    const int64_t max_launches = (int64_t)o.max_steps / o.steps_per_launch + 2;
+    for (int64_t launch = 0;; ++launch) {
+        if (launch >= max_launches) return set_error(MCC_ERR_DEVICE, "per-launch solver did not finish");
+        hipError_t e = launch_fill_i32(c->pending, 0, s);
+        if (e == hipSuccess) e = launch_solve(p, m->t.NS, m->t.M, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->pending_host, c->pending, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_error(e, "per-launch solver");
+        if (*c->pending_host == 0) break;
+    }
     return ok();
 }
 
@@ -592,11 +640,15 @@ mcc_status mcc_cells_destroy(mcc_cells *c)
     if (!c) return ok();
     DeviceGuard g(c->mech->device);
     hipError_t e = hipDeviceSynchronize();
-    for (double *buf : {c->k, c->ones})
+    for (void *buf : {(void *)c->k, (void *)c->ones, (void *)c->state, (void *)c->pending})
         if (buf) {
             hipError_t e2 = hipFree(buf);
             if (e == hipSuccess) e = e2;
         }
+    if (c->pending_host) {
+        hipError_t e2 = hipHostFree(c->pending_host);
+        if (e == hipSuccess) e = e2;
+    }
     c->mech->live_batches--;
     delete c;
     if (e != hipSuccess) return hip_error(e, "mcc_cells_destroy");

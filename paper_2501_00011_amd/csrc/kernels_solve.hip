@@ -467,6 +467,15 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
     extern __shared__ double smem[];
     const int64_t cell = blockIdx.x;
     if (cell >= p.n_cells) return;
+    // per-launch form: where this cell's state lives between launches
+    const int K = p.opts.steps_per_launch;
+    double *st_d = K > 0 ? p.state + cell * p.state_stride : nullptr;
+    double *st_s = K > 0 ? st_d + (kMaxOrder + 3) * NS * kWave : nullptr;
+    bool resumed = false;
+    if (K > 0 && st_s[0] == (double)p.call_id) {
+        if (st_s[1] == 2.0) return;  // finished in an earlier launch of this outer step
+        resumed = true;
+    }
     Cell<NS, M> C(p, smem);
     const int lane = C.lane, N = p.N;
     const mcc_solver_opts &o = p.opts;
@@ -484,54 +493,77 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         sp[s] = C.valid(s) ? p.vspecies[s * kWave + lane] : 0;
-        const double y0 = C.valid(s) ? p.y[(int64_t)sp[s] * p.ld + cell] : 0.0;
+        const double y0 = C.valid(s) && !resumed ? p.y[(int64_t)sp[s] * p.ld + cell] : 0.0;
 #pragma unroll
-        for (int j = 0; j < kMaxOrder + 3; ++j) D[j][s] = 0.0;
-        D[0][s] = y0;
+        for (int j = 0; j < kMaxOrder + 3; ++j) D[j][s] = resumed ? st_d[(j * NS + s) * kWave + lane] : 0.0;
+        if (!resumed) D[0][s] = y0;
     }
     // counters (uniform)
     int steps = 0, rejects = 0, newton_fails = 0, newton_iters = 0, f_evals = 0, jac_evals = 0, lu_count = 0;
     int status = MCC_CELL_OK;
-    double h = 0.0;
-    int order = 1;
-
-    // ---- starting step size -------------------------------------------------
-    C.deriv(D[0], f);
-    f_evals++;
-    bool bad = C.any_nonfinite(D[0]) || C.any_nonfinite(f);
-    if (bad) {
-        status = MCC_CELL_NONFINITE;
-        order = 0;
+    double h = 0.0, t = 0.0;
+    int order = 1, n_equal = 0, attempts = 0;
+    bool bad = false;
+    if (resumed) {
+        t = st_s[2];
+        h = st_s[3];
+        order = (int)st_s[4];
+        n_equal = (int)st_s[5];
+        attempts = (int)st_s[6];
+        steps = (int)st_s[7];
+        rejects = (int)st_s[8];
+        newton_fails = (int)st_s[9];
+        newton_iters = (int)st_s[10];
+        f_evals = (int)st_s[11];
+        jac_evals = (int)st_s[12];
+        lu_count = (int)st_s[13];
+        status = (int)st_s[14];
     } else {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
-        const double d0 = C.wrms(D[0], w), d1 = C.wrms(f, w);
-        const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) ypred[s] = D[0][s] + h0 * f[s];
-        C.deriv(ypred, tmp);
+        // ---- starting step size -------------------------------------------------
+        C.deriv(D[0], f);
         f_evals++;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) tmp[s] -= f[s];
-        const double d2 = C.wrms(tmp, w) / h0;
-        const double dm = d1 > d2 ? d1 : d2;
-        const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
-        h = fmin(100.0 * h0, fmin(h1, dt));
-        if (!(h > 0.0) || !isfinite(h)) {
+        bad = C.any_nonfinite(D[0]) || C.any_nonfinite(f);
+        if (bad) {
             status = MCC_CELL_NONFINITE;
             order = 0;
-            h = 0.0;
-            bad = true;
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
+            const double d0 = C.wrms(D[0], w), d1 = C.wrms(f, w);
+            const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) ypred[s] = D[0][s] + h0 * f[s];
+            C.deriv(ypred, tmp);
+            f_evals++;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) tmp[s] -= f[s];
+            const double d2 = C.wrms(tmp, w) / h0;
+            const double dm = d1 > d2 ? d1 : d2;
+            const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
+            h = fmin(100.0 * h0, fmin(h1, dt));
+            if (!(h > 0.0) || !isfinite(h)) {
+                status = MCC_CELL_NONFINITE;
+                order = 0;
+                h = 0.0;
+                bad = true;
+            }
+        }
+
+        if (!bad) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) D[1][s] = h * f[s];
         }
     }
 
+    bool suspended = false;
     if (!bad) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) D[1][s] = h * f[s];
-        int n_equal = 0, attempts = 0;
-        double t = 0.0;
+        int steps_here = 0;
         bool done = false;
         while (!done && t < dt) {
+            if (K > 0 && steps_here >= K) {  // per-launch form: the rest in a later launch
+                suspended = true;
+                break;
+            }
             bool accepted = false, landing = false;
             double err_norm = 0.0;
             while (!accepted) {
@@ -630,6 +662,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
             if (done) break;
             t = landing ? dt : t + h;
             steps++;
+            steps_here++;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -685,6 +718,32 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
         }
     }
 
+    if (suspended) {
+#pragma unroll
+        for (int j = 0; j < kMaxOrder + 3; ++j)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) st_d[(j * NS + s) * kWave + lane] = D[j][s];
+        if (lane == 0) {
+            st_s[0] = (double)p.call_id;
+            st_s[1] = 1.0;
+            st_s[2] = t;
+            st_s[3] = h;
+            st_s[4] = order;
+            st_s[5] = n_equal;
+            st_s[6] = attempts;
+            st_s[7] = steps;
+            st_s[8] = rejects;
+            st_s[9] = newton_fails;
+            st_s[10] = newton_iters;
+            st_s[11] = f_evals;
+            st_s[12] = jac_evals;
+            st_s[13] = lu_count;
+            st_s[14] = status;
+            atomicAdd(p.pending, 1);
+        }
+        return;
+    }
+
     double ymin = 0.0;
     if (status != MCC_CELL_NONFINITE) {
         double lm = INFINITY;
@@ -716,7 +775,16 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
             st.y_min = ymin;
             p.stats[cell] = st;
         }
+        if (K > 0) {  // finished: later launches of this outer step skip the cell
+            st_s[0] = (double)p.call_id;
+            st_s[1] = 2.0;
+        }
     }
+}
+
+__global__ void fill_i32_kernel(int32_t *q, int32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = v;
 }
 
 }  // namespace
@@ -735,6 +803,12 @@ hipError_t prepare_solve_kernels(int max_lds_bytes)
     MCC_SOLVE_VARIANTS(MCC_SET_LDS)
 #undef MCC_SET_LDS
     return e;
+}
+
+hipError_t launch_fill_i32(int32_t *q, int32_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, q, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)

@@ -166,7 +166,15 @@ struct SolveParams {
     int64_t n_cells, ld;
     double dt;
     mcc_solver_opts opts;
+    // per-launch form (opts.steps_per_launch > 0): solver state per cell kept
+    // in HBM between launches, [n_cells][state_stride] doubles: the backward
+    // differences [kMaxOrder + 3][NV], then the scalars of kStateScalars
+    double *state;
+    int32_t *pending;  // cells this launch left unfinished (one atomic add per cell)
+    int64_t state_stride;
+    int32_t call_id;   // the outer step this launch belongs to
 };
+constexpr int kStateScalars = 16;
 
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_rates(const RatesParams &p, hipStream_t s);
@@ -177,5 +185,6 @@ bool compile_fj_source(const std::string &src, const std::string &arch, std::vec
 hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).
 hipError_t prepare_solve_kernels(int max_lds_bytes);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);  // *p = v by a kernel (graph-safe)
 
 }  // namespace mcc

@@ -32,7 +32,7 @@ class SolverOpts(ctypes.Structure):
                 ("safety", ctypes.c_double), ("fac_min", ctypes.c_double), ("fac_max", ctypes.c_double),
                 ("fac_newton_fail", ctypes.c_double), ("h_min_rel", ctypes.c_double),
                 ("max_order", ctypes.c_int32), ("max_newton", ctypes.c_int32),
-                ("max_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32)]
 
 
 class _MechDesc(ctypes.Structure):

@@ -297,6 +297,8 @@ def test_errors_before_bind_and_bad_args(dev):
         cells.step(y, -1.0)
     with pytest.raises(mcchem.MccError, match="status 1"):
         cells.step(y, dt, mcchem.default_opts(max_order=6))
+    with pytest.raises(mcchem.MccError, match="status 1"):
+        cells.step(y, dt, mcchem.default_opts(steps_per_launch=-1))
     with pytest.raises(mcchem.MccError, match="status 5"):
         h.close()  # a batch is still alive
     cells.close()
@@ -335,3 +337,39 @@ def test_fj_wide_species(dev, oracle_mod, kind):
     f, J = b.cells.deriv_jac(b.y_dev())
     torch.cuda.synchronize()
     _check_fj(b, f.cpu().numpy()[:, :C], J.cpu().numpy()[:, :C], cells.y0)
+
+
+def _step_all(b, dt, **kw):
+    y = b.y_dev()
+    st, stats = b.cells.step(y, dt, mcchem.default_opts(**kw))
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy()
+
+
+@pytest.mark.parametrize("K", [1, 7])
+def test_per_launch_form_is_bit_identical(dev, K):
+    """The per-launch form (state in HBM between launches, at most K accepted
+    steps per launch) computes exactly what the one-launch form computes."""
+    m, c, dt = synth.workload("medium10k", 200)
+    b = Batch(dev, m, c, ld=203)
+    y0, s0, t0 = _step_all(b, dt)
+    y1, s1, t1 = _step_all(b, dt, steps_per_launch=K)
+    assert np.all(s0 == 0)
+    np.testing.assert_array_equal(s1, s0)
+    np.testing.assert_array_equal(y1, y0)
+    np.testing.assert_array_equal(t1, t0)
+    # a second outer step on the same handle starts every cell afresh
+    y2, s2, t2 = _step_all(b, dt, steps_per_launch=K)
+    np.testing.assert_array_equal(y2, y0)
+    np.testing.assert_array_equal(t2, t0)
+
+
+def test_per_launch_form_status_codes(dev):
+    m, c, dt = synth.workload("small10")
+    b = Batch(dev, m, c)
+    for kw in ({"max_steps": 1}, {"max_steps": 40}, {"max_newton": 1, "h_min_rel": 1e-12}):
+        y0, s0, t0 = _step_all(b, dt, **kw)
+        y1, s1, t1 = _step_all(b, dt, steps_per_launch=3, **kw)
+        np.testing.assert_array_equal(s1, s0)
+        np.testing.assert_array_equal(y1, y0)
+        np.testing.assert_array_equal(t1, t0)
