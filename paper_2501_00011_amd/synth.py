@@ -283,3 +283,22 @@ def workload(name: str, n_cells: int | None = None):
         c = make_cells(m, n_cells or 10000, seed=1005)
         return m, c, 60.0
     raise KeyError(name)
+
+
+def mixed_workload(n_cells: int = 100000):
+    """The mixed batch: 20/30, 72/156 and 150/350 mechanisms with 30% / 50% /
+    20% of n_cells, randomly interleaved (seed 1004), 60 s steps.
+
+    Returns (groups, owner, dt): groups is a list of (mechanism, cells) with
+    the cells of each mechanism in their interleaved order, and owner[g] the
+    global indices of group g's cells in the interleaved batch."""
+    mechs = [mech_small(), mech_medium(), mech_large()]
+    counts = split_counts(n_cells, [30, 50, 20])
+    rng = np.random.default_rng(1004)
+    label = rng.permutation(np.repeat(np.arange(3), counts))
+    groups, owner = [], []
+    for g, m in enumerate(mechs):
+        idx = np.flatnonzero(label == g)
+        groups.append((m, make_cells(m, len(idx), seed=1004 + 10 * (g + 1))))
+        owner.append(idx)
+    return groups, owner, 60.0
