@@ -266,6 +266,22 @@ def main():
     fj_s = fj_ev[0].elapsed_time(fj_ev[1]) / 1e3 / max(args.fj_reps, 1)
     fj_gbs = oc["fj_bytes"] * C / fj_s / 1e9
 
+    # reverse mode: J^T v and d(v.f)/d ln k in one launch, back to back
+    v = torch.ones_like(y0)
+    gy = torch.empty_like(y0)
+    glnk = torch.empty((m.n_reactions, C), dtype=torch.float64, device=dev)
+    for _ in range(10):
+        cells.vjp(y0, v, gy, glnk, stream=stream)
+    vj_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    vj_ev[0].record(stream)
+    for _ in range(max(args.fj_reps, 1)):
+        cells.vjp(y0, v, gy, glnk, stream=stream)
+    vj_ev[1].record(stream)
+    torch.cuda.synchronize()
+    vj_s = vj_ev[0].elapsed_time(vj_ev[1]) / 1e3 / max(args.fj_reps, 1)
+    vj_bytes = 8 * (3 * m.n_species + 2 * m.n_reactions)  # read y, v, k; write gy, glnk
+    vj_gbs = vj_bytes * C / vj_s / 1e9
+
     result = {
         "metric": "cell-timesteps/s (FP64, 1e-6 rel vs oracle); f+J evals/s as % HBM peak",
         "value": C * args.steps / wall,
@@ -292,6 +308,9 @@ def main():
                         "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
                         "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
                         "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
+        "vjp_roofline": {"kernel": "mcc_vjp_generated (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
+                         "achieved": vj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vj_gbs / HBM_PEAK_GBS,
+                         "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes},
         "solver": {"failed_cells": int((st != 0).sum()),
                    "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),
                    "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),

@@ -251,6 +251,21 @@ mcc_status mcc_calc_jac(const mcc_cells *cells, const double *y, double *jac, vo
 mcc_status mcc_calc_deriv_jac(const mcc_cells *cells, const double *y, double *f, double *jac,
                               void *stream);
 
+/* Vector-Jacobian products of f at y for every cell, for reverse-mode
+ * differentiation (Section 2 definitions of f and J):
+ *   gy_s   = sum_i v_i d f_i / d y_s            (gy = J^T v),
+ *   glnk_j = sum_i v_i d f_i / d ln k_j = r_j sum_i nu_ij v_i
+ * (f is linear in each k_j).  y, v, gy device [n_species][ld]; glnk device
+ * [n_reactions][ld]; one of gy and glnk may be NULL.  Uses the generated
+ * kernel of the mechanism (compiled on the first call, as for f/J). */
+mcc_status mcc_calc_vjp(const mcc_cells *cells, const double *y, const double *v, double *gy, double *glnk,
+                        void *stream);
+
+/* Replace the batch's rate constants by caller values (device [n_reactions]
+ * [ld], copied on `stream`), e.g. k = exp(ln k) of a parameter being
+ * differentiated; the batch then counts as bound. */
+mcc_status mcc_cells_set_rate_constants(mcc_cells *cells, const double *k, void *stream);
+
 /* One outer step of length dt > 0 for every cell: each cell integrates
  * y' = f(y) from 0 to dt on its own with the variable-order BDF method and a
  * Newton iteration on a sparse LU of I - (h/gamma_k) J (Section 2: solver

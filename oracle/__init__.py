@@ -83,6 +83,7 @@ class Oracle:
         L.orc_rate_constants.argtypes = [vp, i64, vp, vp, vp]
         L.orc_deriv.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_jac.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.orc_vjp.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.orc_solve.argtypes = [vp, i64, vp, vp, dbl, vp, vp, vp, ctypes.c_int]
         L.orc_solve.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
@@ -128,6 +129,18 @@ class Oracle:
         s = np.empty((C, self.N, self.N))
         self.lib.orc_jac(self._mp(), C, k.ctypes.data, y.ctypes.data, J.ctypes.data, s.ctypes.data)
         return J, s
+
+    def vjp(self, k, y, v):
+        """gy = J^T v [N][C] and glnk = d(v.f)/d ln k [R][C] (f is linear in k)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        C = y.shape[1]
+        gy = np.empty((self.N, C))
+        gk = np.empty((self.R, C))
+        self.lib.orc_vjp(self._mp(), C, k.ctypes.data, y.ctypes.data, v.ctypes.data, gy.ctypes.data,
+                         gk.ctypes.data)
+        return gy, gk
 
     def solve(self, k, y0, dt, opts: Opts | None = None, n_threads: int = 0):
         """One outer BDF step of length dt for every cell.

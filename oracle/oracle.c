@@ -205,6 +205,46 @@ void orc_jac(const orc_mech *m, int64_t n_cells, const double *k, const double *
     free(kc); free(yc);
 }
 
+/* Vector-Jacobian products of f for every cell, from the definitions:
+ * gy_s = sum_i v_i J_is (J from cell_jac) and, with respect to the log rate
+ * constants, glnk_j = sum_i v_i d f_i / d ln k_j = sum_i v_i nu_ij r_j
+ * (f is linear in each k_j, so d f / d ln k_j = nu_j r_j).
+ * k: [R][C]; y, v, gy: [N][C]; glnk: [R][C]; gy or glnk may be NULL. */
+void orc_vjp(const orc_mech *m, int64_t n_cells, const double *k, const double *y, const double *v,
+             double *gy, double *glnk)
+{
+    const int N = m->n_species, R = m->n_reactions;
+    double *kc = malloc(sizeof(double) * R), *yc = malloc(sizeof(double) * N);
+    double *vc = malloc(sizeof(double) * N), *g = malloc(sizeof(double) * (N > R ? N : R));
+    double *J = malloc(sizeof(double) * (size_t)N * N);
+    for (int64_t c = 0; c < n_cells; ++c) {
+        gather_cell(k, R, n_cells, c, kc);
+        gather_cell(y, N, n_cells, c, yc);
+        gather_cell(v, N, n_cells, c, vc);
+        if (gy) {
+            cell_jac(m, kc, yc, J, NULL);
+            for (int s = 0; s < N; ++s) {
+                double acc = 0.0;
+                for (int i = 0; i < N; ++i) acc += vc[i] * J[(size_t)i * N + s];
+                g[s] = acc;
+            }
+            scatter_cell(g, N, n_cells, c, gy);
+        }
+        if (glnk) {
+            for (int j = 0; j < R; ++j) {
+                const double r = reaction_rate(m, j, kc[j], yc);
+                double acc = 0.0;
+                for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p) acc -= vc[m->reac_idx[p]] * r;
+                for (int p = m->prod_ptr[j]; p < m->prod_ptr[j + 1]; ++p)
+                    acc += vc[m->prod_idx[p]] * m->prod_yield[p] * r;
+                g[j] = acc;
+            }
+            scatter_cell(g, R, n_cells, c, glnk);
+        }
+    }
+    free(kc); free(yc); free(vc); free(g); free(J);
+}
+
 /* -------------------------------------------- dense LU with partial pivoting */
 
 /* In-place LU of the n x n row-major matrix a, row interchanges in piv.

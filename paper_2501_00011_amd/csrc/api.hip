@@ -32,7 +32,7 @@ struct mcc_mech {
     int fj_kind = MCC_FJ_GENERATED;
     std::string arch;
     hipModule_t fj_mod = nullptr;
-    hipFunction_t fj_fn = nullptr;
+    hipFunction_t fj_fn = nullptr, vjp_fn = nullptr;
 };
 
 struct mcc_cells {
@@ -307,6 +307,7 @@ mcc_status mcc_mech_destroy(mcc_mech *m)
         if (e != hipSuccess) return hip_error(e, "hipModuleUnload");
         m->fj_mod = nullptr;
         m->fj_fn = nullptr;
+        m->vjp_fn = nullptr;
     }
     if (m->dev_buf) {
         hipError_t e = hipFree(m->dev_buf);
@@ -327,7 +328,7 @@ mcc_status mcc_mech_set_fj_kernel(mcc_mech *m, int32_t kind)
 mcc_status mcc_debug_fj_source(const mcc_mech *m, char *buf, int64_t cap, int64_t *len)
 {
     if (!m || !len || (cap > 0 && !buf) || cap < 0) return set_error(MCC_ERR_INVALID_ARG, "bad argument");
-    const std::string src = generate_fj_source(m->t);
+    const std::string src = generate_fj_source(m->t) + generate_vjp_source(m->t);
     *len = (int64_t)src.size();
     if (cap > 0) {
         const size_t n = std::min((size_t)cap, src.size() + 1);
@@ -341,7 +342,7 @@ mcc_status mcc_debug_compile_fj(const mcc_mech *m, const char *arch, int64_t *co
     if (!m || !arch || !code_bytes) return set_error(MCC_ERR_INVALID_ARG, "null argument");
     std::vector<char> code;
     std::string log;
-    if (!compile_fj_source(generate_fj_source(m->t), arch, &code, &log))
+    if (!compile_fj_source(generate_fj_source(m->t) + generate_vjp_source(m->t), arch, &code, &log))
         return set_error(MCC_ERR_DEVICE, "generated f/J kernel does not compile: " + log);
     *code_bytes = (int64_t)code.size();
     return ok();
@@ -421,7 +422,7 @@ static mcc_status ensure_fj_module(mcc_mech *m)
     if (m->fj_fn) return ok();
     std::vector<char> code;
     std::string log;
-    if (!compile_fj_source(generate_fj_source(m->t), m->arch, &code, &log))
+    if (!compile_fj_source(generate_fj_source(m->t) + generate_vjp_source(m->t), m->arch, &code, &log))
         return set_error(MCC_ERR_DEVICE, "generated f/J kernel does not compile: " + log);
     hipError_t e = hipModuleLoadData(&m->fj_mod, code.data());
     if (e != hipSuccess) {
@@ -429,10 +430,12 @@ static mcc_status ensure_fj_module(mcc_mech *m)
         return hip_error(e, "hipModuleLoadData (generated f/J kernel)");
     }
     e = hipModuleGetFunction(&m->fj_fn, m->fj_mod, "mcc_fj_generated");
+    if (e == hipSuccess) e = hipModuleGetFunction(&m->vjp_fn, m->fj_mod, "mcc_vjp_generated");
     if (e != hipSuccess) {
         (void)hipModuleUnload(m->fj_mod);
         m->fj_mod = nullptr;
         m->fj_fn = nullptr;
+        m->vjp_fn = nullptr;
         return hip_error(e, "hipModuleGetFunction (generated f/J kernel)");
     }
     return ok();
@@ -486,6 +489,48 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
     hipError_t e = hipModuleLaunchKernel(c->mech->fj_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
                                          args, nullptr);
     if (e != hipSuccess) return hip_error(e, "generated f/J kernel launch");
+    return ok();
+}
+
+mcc_status mcc_calc_vjp(const mcc_cells *c, const double *y, const double *v, double *gy, double *glnk,
+                        void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "the batch has no rate constants yet");
+    if (c->n_cells == 0) return ok();
+    if (!y || !v) return set_error(MCC_ERR_INVALID_ARG, "y and v must not be null");
+    if (!gy && !glnk) return set_error(MCC_ERR_INVALID_ARG, "gy and glnk are both null");
+    const HostTables &t = c->mech->t;
+    DeviceGuard g(c->mech->device);
+    mcc_status st = ensure_fj_module(c->mech);
+    if (st != MCC_OK) return st;
+    const int n_ritems = (t.R + kVjpRxnGroup - 1) / kVjpRxnGroup;
+    int item_begin = gy ? 0 : t.n_jitems;
+    int n_items = (gy ? t.n_jitems : 0) + (glnk ? n_ritems : 0);
+    int n_tiles = (int)((c->n_cells + 63) / 64);
+    const int64_t blocks = (int64_t)((n_tiles + 7) / 8) * 8 * n_items;
+    if (n_items == 0) return ok();
+    if (blocks > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "too many cells for one launch");
+    const double *k = c->k;
+    long long n_cells = c->n_cells, ld = c->ld;
+    void *args[] = {&y, &k, &v, &gy, &glnk, &n_cells, &ld, &item_begin, &n_items, &n_tiles};
+    hipError_t e = hipModuleLaunchKernel(c->mech->vjp_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
+                                         args, nullptr);
+    if (e != hipSuccess) return hip_error(e, "generated VJP kernel launch");
+    return ok();
+}
+
+mcc_status mcc_cells_set_rate_constants(mcc_cells *c, const double *k, void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (c->n_cells > 0 && !k) return set_error(MCC_ERR_INVALID_ARG, "k is null");
+    DeviceGuard g(c->mech->device);
+    const size_t bytes = (size_t)c->mech->t.R * (size_t)c->ld * sizeof(double);
+    if (bytes > 0) {
+        hipError_t e = hipMemcpyAsync(c->k, k, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync (rate constants)");
+    }
+    c->bound = true;
     return ok();
 }
 

@@ -10,6 +10,7 @@
 // J = sum nu dr/dy), term by term in the same order.
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <set>
 #include <sstream>
@@ -112,6 +113,128 @@ std::string generate_fj_source(const HostTables &t)
 }  // namespace mcc
 
 namespace mcc {
+
+// Vector-Jacobian products, generated from the same tables.  Work items
+// 0 .. n_jitems-1 are the Jacobian-column items of the f/J kernel: each J
+// entry (i, s) they form is contracted at once with v_i into a register
+// accumulator gy_s (gy = J^T v), stored when the item ends (a column never
+// spans two items).  Items n_jitems .. are groups of kVjpRxnGroup reactions:
+// glnk_j = r_j * sum_i nu_ij v_i, the derivative of v.f with respect to
+// ln k_j (f is linear in each k_j).
+std::string generate_vjp_source(const HostTables &t)
+{
+    const int N = t.N, R = t.R;
+    std::vector<int> entry_row(t.nnz), entry_col(t.nnz);
+    for (int i = 0; i < N; ++i)
+        for (int e = t.row_ptr[i]; e < t.row_ptr[i + 1]; ++e) {
+            entry_row[e] = i;
+            entry_col[e] = t.col_idx[e];
+        }
+    std::ostringstream o;
+    o << "extern \"C\" __global__ __launch_bounds__(64) void mcc_vjp_generated(\n"
+      << "    const double *__restrict__ y, const double *__restrict__ k, const double *__restrict__ v,\n"
+      << "    double *__restrict__ gy, double *__restrict__ glnk, long long n_cells, long long ld, int item_begin,\n"
+      << "    int n_items, int n_tiles)\n"
+      << "{\n"
+      << "    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;\n"
+      << "    const int item = item_begin + q % n_items, tile = (q / n_items) * 8 + xcd;\n"
+      << "    if (tile >= n_tiles) return;\n"
+      << "    const long long c = (long long)tile * 64 + threadIdx.x;\n"
+      << "    if (c >= n_cells) return;\n"
+      << "    const double *__restrict__ Y = y + c;\n"
+      << "    const double *__restrict__ K = k + c;\n"
+      << "    const double *__restrict__ V = v + c;\n"
+      << "    double *__restrict__ GY = gy + c;\n"
+      << "    double *__restrict__ GK = glnk + c;\n"
+      << "    switch (item) {\n";
+    int case_no = 0;
+    for (int it = t.n_fitems; it < t.n_fitems + t.n_jitems; ++it, ++case_no) {
+        o << "    case " << case_no << ": {\n";
+        std::set<int> ys, ks, vs, cols;
+        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
+            const FjChunk &ch = t.fj_chunks[ci];
+            for (int qm = 0; qm < ch.n_mono; ++qm) {
+                const FjMono &m = t.fj_monos[ch.mono_begin + qm];
+                if (m.j >= 0) ks.insert(m.j);
+                for (int f3 : {m.a, m.b, m.c})
+                    if (f3 >= 0) ys.insert(f3);
+            }
+            for (int r = 0; r < ch.n_rec; ++r) {
+                const FjRec &rec = t.fj_recs[ch.rec_begin + r];
+                const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
+                if ((flags & kFjStore) && row >= (uint32_t)N) {
+                    vs.insert(entry_row[row - N]);
+                    cols.insert(entry_col[row - N]);
+                }
+            }
+        }
+        for (int j : ks) o << "        const double k" << j << " = K[" << j << " * ld];\n";
+        for (int r : ys) o << "        const double y" << r << " = Y[" << r << " * ld];\n";
+        for (int r : vs) o << "        const double v" << r << " = V[" << r << " * ld];\n";
+        for (int sc : cols) o << "        double g" << sc << " = 0.0;\n";
+        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
+            const FjChunk &ch = t.fj_chunks[ci];
+            o << "        {\n";
+            std::vector<std::string> mono(kFjQmax);
+            for (int qm = 0; qm < ch.n_mono; ++qm) {
+                const FjMono &m = t.fj_monos[ch.mono_begin + qm];
+                if (m.j < 0 && m.a < 0 && m.b < 0 && m.c < 0) continue;
+                std::string e;
+                if (m.j >= 0) e = "k" + std::to_string(m.j);
+                for (int f3 : {m.a, m.b, m.c})
+                    if (f3 >= 0) e += (e.empty() ? "" : " * ") + ("y" + std::to_string(f3));
+                mono[qm] = "m" + std::to_string(qm);
+                o << "            const double " << mono[qm] << " = " << e << ";\n";
+            }
+            o << "            double acc = 0.0;\n";
+            for (int r = 0; r < ch.n_rec; ++r) {
+                const FjRec &rec = t.fj_recs[ch.rec_begin + r];
+                const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
+                std::string sum;
+                for (int qq = 0; qq < 3; ++qq) {
+                    const int slot = (rec.slots >> (8 * qq)) & 0xff;
+                    if (slot >= kFjQmax || rec.coef[qq] == 0.0 || mono[slot].empty()) continue;
+                    sum += (sum.empty() ? "" : " + ") + lit(rec.coef[qq]) + " * " + mono[slot];
+                }
+                if (sum.empty()) sum = "0.0";
+                if (!(flags & (kFjKeep | kFjStore)) && sum == "0.0") continue;
+                o << "            acc " << ((flags & kFjKeep) ? "+=" : "=") << " " << sum << ";\n";
+                if ((flags & kFjStore) && row >= (uint32_t)N) {
+                    const int e = (int)row - N;
+                    o << "            g" << entry_col[e] << " += v" << entry_row[e] << " * acc;\n";
+                }
+            }
+            o << "            (void)acc;\n        }\n";
+        }
+        for (int sc : cols) o << "        GY[" << sc << " * ld] = g" << sc << ";\n";
+        o << "    } break;\n";
+    }
+    for (int j0 = 0; j0 < R; j0 += kVjpRxnGroup, ++case_no) {
+        const int j1 = std::min(R, j0 + kVjpRxnGroup);
+        o << "    case " << case_no << ": {\n";
+        std::set<int> ys, vs;
+        for (int j = j0; j < j1; ++j) {
+            for (int q = 0; q < 3; ++q)
+                if (t.rx_sp[3 * j + q] >= 0) ys.insert(t.rx_sp[3 * j + q]);
+            for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) vs.insert(t.nu_sp[e]);
+        }
+        for (int r : ys) o << "        const double y" << r << " = Y[" << r << " * ld];\n";
+        for (int r : vs) o << "        const double v" << r << " = V[" << r << " * ld];\n";
+        for (int j = j0; j < j1; ++j) {
+            std::string rate = "K[" + std::to_string(j) + " * ld]";
+            for (int q = 0; q < 3; ++q)
+                if (t.rx_sp[3 * j + q] >= 0) rate += " * y" + std::to_string(t.rx_sp[3 * j + q]);
+            std::string w;
+            for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e)
+                w += (w.empty() ? "" : " + ") + lit(t.nu_coef[e]) + " * v" + std::to_string(t.nu_sp[e]);
+            if (w.empty()) w = "0.0";
+            o << "        GK[" << j << " * ld] = (" << rate << ") * (" << w << ");\n";
+        }
+        o << "    } break;\n";
+    }
+    o << "    default: break;\n    }\n}\n";
+    return o.str();
+}
 
 bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log)
 {

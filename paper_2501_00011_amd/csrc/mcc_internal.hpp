@@ -82,6 +82,11 @@ struct HostTables {
     std::vector<FjChunk> fj_chunks;
     std::vector<int32_t> fj_items;    // first chunk of every work item + end
     int n_fitems = 0, n_jitems = 0;   // f items first, then J items
+    // reactions as written: reactant species per slot (-1: none) and the net
+    // stoichiometry nu_ij (CSR over reactions), for the generated VJP kernel
+    std::vector<int32_t> rx_sp;       // [3 * R]
+    std::vector<int32_t> nu_ptr, nu_sp;
+    std::vector<double> nu_coef;
 
     // Solver.  Positions p = 0..N-1 are the elimination (fill-reducing)
     // order; every position lives at a virtual index v = slot * 64 + lane of
@@ -181,6 +186,8 @@ hipError_t launch_rates(const RatesParams &p, hipStream_t s);
 hipError_t launch_fj(const FJParams &p, hipStream_t s);
 // Mechanism-specialised f/J kernel (same work items, compiled with hipRTC).
 std::string generate_fj_source(const HostTables &t);
+std::string generate_vjp_source(const HostTables &t);  // appended to the f/J source: one module
+constexpr int kVjpRxnGroup = 16;  // reactions per d/d ln k work item
 bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log);
 hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).

@@ -210,6 +210,21 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     }
     t->n_partials = (int)parts.size();
 
+    // ---- reactions as written (for the VJP kernel) -------------------------
+    t->rx_sp.assign(3 * (size_t)R, -1);
+    t->nu_ptr.assign(1, 0);
+    t->nu_sp.clear();
+    t->nu_coef.clear();
+    for (int j = 0; j < R; ++j) {
+        for (int q = d->reac_ptr[j]; q < d->reac_ptr[j + 1]; ++q) t->rx_sp[3 * j + (q - d->reac_ptr[j])] = d->reac_idx[q];
+        for (const auto &kv : net_stoich(d, j))
+            if (kv.second != 0.0) {
+                t->nu_sp.push_back(kv.first);
+                t->nu_coef.push_back(kv.second);
+            }
+        t->nu_ptr.push_back((int32_t)t->nu_sp.size());
+    }
+
     // ---- streaming f/J tables (species order) ------------------------------
     // Units: an f row i (monomials = the rates of the reactions that change
     // i) and a J column s (monomials = the partials d r_j / d y_s through each

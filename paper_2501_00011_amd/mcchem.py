@@ -71,6 +71,8 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_debug_schedule_info": ([vp, vp], ctypes.c_int),
         "mcc_debug_emulate_fj": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
+        "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
         "mcc_debug_fj_source": ([vp, vp, i64, vp], ctypes.c_int),
         "mcc_debug_compile_fj": ([vp, ctypes.c_char_p, vp], ctypes.c_int),
         "mcc_mech_destroy": ([vp], ctypes.c_int),
@@ -294,6 +296,26 @@ class Cells:
                                             _dptr(f, "f", torch.float64, self._yshape()),
                                             _dptr(jac, "jac", torch.float64, shape), _stream_ptr(stream)))
         return f, jac
+
+    def vjp(self, y, v, gy=None, glnk=None, want_gy=True, want_glnk=True, stream=None):
+        """gy = J^T v [N][ld] and glnk = d(v.f)/d ln k [R][ld] at y."""
+        import torch
+        if want_gy and gy is None:
+            gy = torch.empty(self._yshape(), dtype=torch.float64, device=y.device)
+        if want_glnk and glnk is None:
+            glnk = torch.empty((self.mech.n_reactions, self.ld), dtype=torch.float64, device=y.device)
+        _check(library().mcc_calc_vjp(
+            self._h, _dptr(y, "y", torch.float64, self._yshape()), _dptr(v, "v", torch.float64, self._yshape()),
+            _dptr(gy, "gy", torch.float64, self._yshape()) if gy is not None else None,
+            _dptr(glnk, "glnk", torch.float64, (self.mech.n_reactions, self.ld)) if glnk is not None else None,
+            _stream_ptr(stream)))
+        return gy, glnk
+
+    def set_rate_constants(self, k, stream=None):
+        """Use caller rate constants k [R][ld] (device float64) instead of bind()'s."""
+        import torch
+        _check(library().mcc_cells_set_rate_constants(
+            self._h, _dptr(k, "k", torch.float64, (self.mech.n_reactions, self.ld)), _stream_ptr(stream)))
 
     def step(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, want_stats=True,
              stream=None):

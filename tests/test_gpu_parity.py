@@ -419,3 +419,75 @@ def test_mixed_mechanisms_graph_replay(dev, oracle_mod):
         yo, so, _ = b.o.solve(k, b.c.y0[:, sel], dt, orc.default_opts())
         assert np.all(so == 0)
         assert _within(yr.cpu().numpy()[:, sel], yo, 1.0) <= 1.0
+
+
+def _vjp_bounds(m, k, y, v, Js):
+    """Scales of the two products: sum_i |v_i| |J|_is and r_j sum_i |nu_ij v_i|."""
+    by = np.einsum("ic,cis->sc", np.abs(v), Js)
+    bk = np.zeros((m.n_reactions, y.shape[1]))
+    for j in range(m.n_reactions):
+        reac = m.reac_idx[m.reac_ptr[j]:m.reac_ptr[j + 1]]
+        r = k[j] * np.prod(y[reac], axis=0)
+        w = np.zeros(y.shape[1])
+        for s in reac:
+            w += np.abs(v[s])
+        for s, yl in zip(m.prod_idx[m.prod_ptr[j]:m.prod_ptr[j + 1]], m.prod_yield[m.prod_ptr[j]:m.prod_ptr[j + 1]]):
+            w += np.abs(yl * v[s])
+        bk[j] = np.abs(r) * w
+    return by, bk
+
+
+@pytest.mark.parametrize("name,n,ld", [("small10", 10, 13), ("medium10k", 333, 333)])
+def test_vjp_parity(dev, oracle_mod, name, n, ld):
+    m, c, _ = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=ld, oracle_mod=oracle_mod)
+    rng = np.random.default_rng(12)
+    v = rng.normal(size=c.y0.shape)
+    gy, gk = b.cells.vjp(b.y_dev(), _t(_padded(v, ld), dev))
+    gy_only, _ = b.cells.vjp(b.y_dev(), _t(_padded(v, ld), dev), want_glnk=False)
+    torch.cuda.synchronize()
+    gy, gk = gy.cpu().numpy()[:, :n], gk.cpu().numpy()[:, :n]
+    k = b.o.rate_constants(c.T, c.jscale)
+    gy_ref, gk_ref = b.o.vjp(k, c.y0, v)
+    _, Js = b.o.jac(k, c.y0)
+    by, bk = _vjp_bounds(m, k, c.y0, v, Js)
+    assert np.all(np.abs(gy - gy_ref) <= 1e-12 * by)
+    assert np.all(np.abs(gk - gk_ref) <= 1e-12 * bk)
+    np.testing.assert_array_equal(gy_only.cpu().numpy()[:, :n], gy)
+
+
+def test_vjp_large_mechanism(dev, oracle_mod):
+    m = synth.mech_large()
+    c = synth.make_cells(m, 130, seed=4243)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    v = np.random.default_rng(13).normal(size=c.y0.shape)
+    gy, gk = b.cells.vjp(b.y_dev(), _t(v, dev))
+    torch.cuda.synchronize()
+    k = b.o.rate_constants(c.T, c.jscale)
+    gy_ref, gk_ref = b.o.vjp(k, c.y0, v)
+    _, Js = b.o.jac(k, c.y0)
+    by, bk = _vjp_bounds(m, k, c.y0, v, Js)
+    assert np.all(np.abs(gy.cpu().numpy() - gy_ref) <= 1e-12 * by)
+    assert np.all(np.abs(gk.cpu().numpy() - gk_ref) <= 1e-12 * bk)
+
+
+def test_autograd_deriv(dev, oracle_mod):
+    """torch autograd through f(y, ln k): gradients of sum(w * f) equal the
+    oracle's vector-Jacobian products."""
+    from paper_2501_00011_amd import autograd as mag
+    m, c, _ = synth.workload("medium10k", 200)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    k = b.o.rate_constants(c.T, c.jscale)
+    y = _t(c.y0, dev).requires_grad_(True)
+    lnk = _t(np.log(k), dev).requires_grad_(True)
+    w = np.random.default_rng(14).normal(size=c.y0.shape)
+    f = mag.deriv(b.cells, y, lnk)
+    (f * _t(w, dev)).sum().backward()
+    f_ref, fs = b.o.deriv(k, c.y0)
+    gy_ref, gk_ref = b.o.vjp(k, c.y0, w)
+    _, Js = b.o.jac(k, c.y0)
+    by, bk = _vjp_bounds(m, k, c.y0, w, Js)
+    # k = exp(ln k) in torch: one rounding of exp on each side
+    assert np.all(np.abs(f.detach().cpu().numpy() - f_ref) <= 1e-11 * fs)
+    assert np.all(np.abs(y.grad.cpu().numpy() - gy_ref) <= 1e-11 * by)
+    assert np.all(np.abs(lnk.grad.cpu().numpy() - gk_ref) <= 1e-11 * bk)

@@ -181,3 +181,69 @@ def test_scale_matches_contributions(oracle_mod):
     for i in only_lost:
         np.testing.assert_allclose(f[i], -fs[i], rtol=1e-15)
     assert math.isfinite(float(fs.sum()))
+
+
+# ---- vector-Jacobian products (reverse mode) ---------------------------------
+
+def test_vjp_handworked(oracle_mod):
+    """gy = J^T v with the hand-derived J of every golden case; for a single
+    reaction d(v.f)/d ln k = v.f (f is proportional to k)."""
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)
+    for case in gold["cases"]:
+        m = _mech_from_case(case)
+        o = oracle_mod.Oracle(m)
+        N = m.n_species
+        y = np.array(case["y"], dtype=np.float64)[:, None]
+        k = np.array([r["k"] for r in case["reactions"]], dtype=np.float64)[:, None]
+        v = (1.0 + np.arange(N, dtype=np.float64))[:, None] * np.array([1.0, -0.5, 0.25] * N)[:N, None]
+        gy, gk = o.vjp(k, y, v)
+        J = np.array(case["J"], dtype=np.float64)
+        np.testing.assert_allclose(gy[:, 0], J.T @ v[:, 0], rtol=1e-14, atol=1e-14)
+        if len(case["reactions"]) == 1:
+            f = np.array(case["f"], dtype=np.float64)
+            assert gk[0, 0] == pytest.approx(float(v[:, 0] @ f), rel=1e-14)
+
+
+@pytest.mark.parametrize("mech_fn", [synth.mech_small, synth.mech_medium])
+def test_vjp_rate_constants_linear_and_euler(oracle_mod, mech_fn):
+    """f is linear in each k_j: d(v.f)/d ln k_j = v.(f(k + k_j e_j) - f(k));
+    and sum_j d(v.f)/d ln k_j = v.f (f is homogeneous of degree 1 in k)."""
+    m = mech_fn()
+    o = oracle_mod.Oracle(m)
+    c = synth.make_cells(m, 2, seed=77)
+    k = o.rate_constants(c.T, c.jscale)
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=c.y0.shape)
+    gy, gk = o.vjp(k, c.y0, v)
+    f0, fs = o.deriv(k, c.y0)
+    vf = np.sum(v * f0, axis=0)
+    scale = np.sum(np.abs(v) * fs, axis=0)
+    assert np.all(np.abs(gk.sum(axis=0) - vf) <= 1e-12 * scale)
+    for j in rng.choice(m.n_reactions, 12, replace=False):
+        k2 = k.copy()
+        k2[j] *= 2.0
+        f2, _ = o.deriv(k2, c.y0)
+        ref = np.sum(v * (f2 - f0), axis=0)
+        assert np.all(np.abs(gk[j] - ref) <= 1e-12 * scale)
+
+
+@pytest.mark.parametrize("mech_fn", [synth.mech_small, synth.mech_medium])
+def test_vjp_state_central_differences(oracle_mod, mech_fn):
+    """v.(f(y + e u) - f(y - e u)) / 2e = gy.u up to the cubic term of f."""
+    m = mech_fn()
+    o = oracle_mod.Oracle(m)
+    c = synth.make_cells(m, 2, seed=78)
+    k = o.rate_constants(c.T, c.jscale)
+    rng = np.random.default_rng(4)
+    v = rng.normal(size=c.y0.shape)
+    gy, _ = o.vjp(k, c.y0, v)
+    for _ in range(4):
+        u = rng.normal(size=c.y0.shape) * c.y0
+        e = 1e-4
+        fp, _ = o.deriv(k, c.y0 + e * u)
+        fm, fs = o.deriv(k, c.y0 - e * u)
+        fd = np.sum(v * (fp - fm), axis=0) / (2 * e)
+        an = np.sum(gy * u, axis=0)
+        scale = np.sum(np.abs(v) * fs, axis=0)
+        assert np.all(np.abs(fd - an) <= 1e-6 * scale), (fd, an, scale)

@@ -32,6 +32,10 @@ MUTANTS = {
     "lu_back_substitution": ("b[i] = s / a[(size_t)i * n + i];", "b[i] = s;"),
     "difference_update": ("D[(size_t)j * N + i] += D[(size_t)(j + 1) * N + i];",
                           "D[(size_t)j * N + i] -= D[(size_t)(j + 1) * N + i];"),
+    "vjp_not_transposed": ("for (int i = 0; i < N; ++i) acc += vc[i] * J[(size_t)i * N + s];",
+                           "for (int i = 0; i < N; ++i) acc += vc[i] * J[(size_t)s * N + i];"),
+    "vjp_lnk_reactant_sign": ("for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p) acc -= vc[m->reac_idx[p]] * r;",
+                              "for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p) acc += vc[m->reac_idx[p]] * r;"),
     "error_constant": ("err_norm = wrms(N, wk->d, wk->w) / (order + 1);",
                        "err_norm = wrms(N, wk->d, wk->w) / (order + 1) * 1e-3;"),
 }
@@ -163,7 +167,29 @@ def _pin_pieces(lib):
     return bool(st[0] == 0 and s["newton_fails"][0] == 0 and s["newton_iters"][0] == 2 * s["lu_count"][0])
 
 
-PINS = [_pin_handworked, _pin_fd_homogeneity_balance, _pin_pieces, _pin_closed_forms, _pin_radau_small]
+def _pin_vjp(lib):
+    """Reverse-mode products against the hand-derived J and f's linearity in k."""
+    g = json.load(open(GOLDEN))
+    for case in g["cases"]:
+        rx = [(r["reac"], [tuple(p) for p in r["prod"]], r["k"], 0.0, 0) for r in case["reactions"]]
+        m = synth.mechanism_from_lists(case["n_species"], rx)
+        o = oracle_pkg.Oracle(m, lib_path=lib)
+        k = np.array([[r["k"]] for r in case["reactions"]])
+        y = np.array(case["y"])[:, None]
+        v = (1.0 + np.arange(m.n_species, dtype=np.float64))[:, None]
+        gy, gk = o.vjp(k, y, v)
+        if not np.allclose(gy[:, 0], np.array(case["J"]).T @ v[:, 0], rtol=1e-14, atol=1e-14):
+            return False
+        f0 = o.deriv(k, y)[0]
+        for j in range(m.n_reactions):
+            k2 = k.copy()
+            k2[j] *= 2.0
+            if not np.isclose(gk[j, 0], float(v[:, 0] @ (o.deriv(k2, y)[0] - f0)[:, 0]), rtol=1e-13, atol=1e-13):
+                return False
+    return True
+
+
+PINS = [_pin_handworked, _pin_fd_homogeneity_balance, _pin_pieces, _pin_closed_forms, _pin_radau_small, _pin_vjp]
 
 
 def test_unmodified_oracle_passes_every_pin():
