@@ -84,6 +84,8 @@ class Oracle:
         L.orc_deriv.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_jac.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_vjp.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.orc_solve_multicell.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
+        L.orc_solve_multicell.restype = ctypes.c_int
         L.orc_solve.argtypes = [vp, i64, vp, vp, dbl, vp, vp, vp, ctypes.c_int]
         L.orc_solve.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
@@ -157,6 +159,19 @@ class Oracle:
                            ctypes.addressof(opts), status.ctypes.data, stats.ctypes.data,
                            int(n_threads))
         return y, status, stats
+
+    def solve_multicell(self, k, y0, dt, opts: Opts | None = None):
+        """Multi-cells: all cells as one system (shared h and order, norms over
+        all cells).  Returns (y, status, stats) with one status and one stats
+        record for the whole system."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.array(y0, dtype=np.float64, order="C", copy=True)
+        C = y.shape[1]
+        stats = np.zeros(1, dtype=STATS_DTYPE)
+        o = opts or default_opts()
+        s = self.lib.orc_solve_multicell(self._mp(), C, k.ctypes.data, y.ctypes.data, float(dt),
+                                         ctypes.addressof(o), stats.ctypes.data)
+        return y, int(s), stats[0]
 
     def rescale_differences(self, D, order, rho):
         """Backward differences D [order+1][N] re-sampled at spacing rho*h."""

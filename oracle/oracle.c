@@ -616,6 +616,217 @@ int orc_solve(const orc_mech *m, int64_t n_cells, const double *k, double *y, do
     return failed;
 }
 
+/* ----------------------------------------------- Multi-cells (Section 3) */
+
+/* The Multi-cells reading: all C cells form one ODE system of N*C unknowns
+ * (cell c's species i at c*N + i), integrated with the same BDF steps as
+ * cell_solve but with one shared t, h and order, every WRMS norm taken over
+ * all N*C components, and one Newton iteration for the whole system.  Cells
+ * do not interact, so the Jacobian is block-diagonal: the Newton matrix is
+ * factorised block by block (the same elimination that dense LU with partial
+ * pivoting performs on the whole matrix, whose pivot search never leaves a
+ * block).  k: [R][C], y: [N][C] in/out; one status and one stats record for
+ * the whole system. */
+int orc_solve_multicell(const orc_mech *m, int64_t n_cells, const double *k, double *y, double dt,
+                        const orc_opts *o, orc_stats *st)
+{
+    const int N = m->n_species, R = m->n_reactions, C = (int)n_cells;
+    const int NC = N * C;
+    const int maxord = o->max_order < 1 ? 1 : (o->max_order > ORC_MAXORD ? ORC_MAXORD : o->max_order);
+    double *kc = malloc(sizeof(double) * (size_t)R * C);   /* cell-major copies */
+    double *Y = malloc(sizeof(double) * NC);
+    double *D = calloc((size_t)(ORC_MAXORD + 3) * NC, sizeof(double));
+    double *f = malloc(sizeof(double) * NC), *w = malloc(sizeof(double) * NC);
+    double *ypred = malloc(sizeof(double) * NC), *psi = malloc(sizeof(double) * NC);
+    double *d = malloc(sizeof(double) * NC), *ycur = malloc(sizeof(double) * NC);
+    double *rhs = malloc(sizeof(double) * NC), *tmp = malloc(sizeof(double) * NC);
+    double *J = malloc(sizeof(double) * (size_t)N * N * C);
+    int *piv = malloc(sizeof(int) * NC);
+    int status = ORC_OK;
+    memset(st, 0, sizeof(*st));
+    for (int c = 0; c < C; ++c) {
+        gather_cell(k, R, n_cells, c, kc + (size_t)c * R);
+        gather_cell(y, N, n_cells, c, Y + (size_t)c * N);
+    }
+#define SYS_DERIV(yin, fout)                                                          \
+    for (int c = 0; c < C; ++c)                                                       \
+        cell_deriv(m, kc + (size_t)c * R, (yin) + (size_t)c * N, (fout) + (size_t)c * N, NULL);
+
+    SYS_DERIV(Y, f);
+    st->f_evals++;
+    double h = 0.0;
+    int order = 1;
+    if (!all_finite(NC, Y) || !all_finite(NC, f)) {
+        status = ORC_NONFINITE;
+        goto done;
+    }
+    for (int i = 0; i < NC; ++i) w[i] = 1.0 / (o->rtol * fabs(Y[i]) + o->atol);
+    {
+        const double d0 = wrms(NC, Y, w), d1 = wrms(NC, f, w);
+        const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+        for (int i = 0; i < NC; ++i) ycur[i] = Y[i] + h0 * f[i];
+        SYS_DERIV(ycur, tmp);
+        st->f_evals++;
+        for (int i = 0; i < NC; ++i) rhs[i] = tmp[i] - f[i];
+        const double d2 = wrms(NC, rhs, w) / h0;
+        const double dm = d1 > d2 ? d1 : d2;
+        const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
+        h = fmin(100.0 * h0, fmin(h1, dt));
+    }
+    if (!(h > 0.0) || !isfinite(h)) {
+        status = ORC_NONFINITE;
+        h = 0.0;
+        goto done;
+    }
+    for (int i = 0; i < NC; ++i) {
+        D[i] = Y[i];
+        D[(size_t)NC + i] = h * f[i];
+    }
+    {
+        int n_equal = 0, attempts = 0;
+        double t = 0.0;
+        while (t < dt) {
+            int accepted = 0, landing = 0;
+            double err_norm = 0.0;
+            while (!accepted) {
+                if (attempts >= o->max_steps) {
+                    status = ORC_TOO_MUCH_WORK;
+                    goto finish;
+                }
+                attempts++;
+                landing = 0;
+                if (h >= dt - t) {
+                    const double hn = dt - t;
+                    rescale_differences(NC, D, order, hn / h);
+                    h = hn;
+                    n_equal = 0;
+                    landing = 1;
+                }
+                const double gk = bdf_gamma(order);
+                const double cc = h / gk;
+                for (int i = 0; i < NC; ++i) {
+                    double yp = 0.0, ps = 0.0;
+                    for (int j = 0; j <= order; ++j) yp += D[(size_t)j * NC + i];
+                    for (int j = 1; j <= order; ++j) ps += bdf_gamma(j) * D[(size_t)j * NC + i];
+                    ypred[i] = yp;
+                    psi[i] = ps / gk;
+                    w[i] = 1.0 / (o->rtol * fabs(D[i]) + o->atol);
+                    d[i] = 0.0;
+                }
+                /* block-diagonal Newton matrix, one N x N block per cell */
+                int singular = 0;
+                for (int c = 0; c < C; ++c) {
+                    double *Jc = J + (size_t)c * N * N;
+                    cell_jac(m, kc + (size_t)c * R, ypred + (size_t)c * N, Jc, NULL);
+                    for (size_t q = 0; q < (size_t)N * N; ++q) Jc[q] = -cc * Jc[q];
+                    for (int i = 0; i < N; ++i) Jc[(size_t)i * N + i] += 1.0;
+                    singular |= lu_factor(N, Jc, piv + (size_t)c * N);
+                }
+                st->jac_evals++;
+                st->lu_count++;
+                int converged = 0;
+                if (!singular) {
+                    double nrm_old = 0.0;
+                    for (int it = 0; it < o->max_newton; ++it) {
+                        for (int i = 0; i < NC; ++i) ycur[i] = ypred[i] + d[i];
+                        SYS_DERIV(ycur, f);
+                        st->f_evals++;
+                        if (!all_finite(NC, f)) break;
+                        for (int i = 0; i < NC; ++i) rhs[i] = cc * f[i] - psi[i] - d[i];
+                        for (int c = 0; c < C; ++c)
+                            lu_solve(N, J + (size_t)c * N * N, piv + (size_t)c * N, rhs + (size_t)c * N);
+                        st->newton_iters++;
+                        const double nrm = wrms(NC, rhs, w);
+                        if (!isfinite(nrm)) break;
+                        double rho = 0.0;
+                        if (it >= 1) {
+                            rho = nrm / nrm_old;
+                            if (rho >= 1.0) break;
+                        }
+                        for (int i = 0; i < NC; ++i) d[i] += rhs[i];
+                        if (nrm == 0.0 || (it >= 1 && rho / (1.0 - rho) * nrm < o->eta_newton)) {
+                            converged = 1;
+                            break;
+                        }
+                        nrm_old = nrm;
+                    }
+                }
+                if (!converged) {
+                    st->newton_fails++;
+                    rescale_differences(NC, D, order, o->fac_newton_fail);
+                    h *= o->fac_newton_fail;
+                    n_equal = 0;
+                    if (h < o->h_min_rel * dt || t + h == t) {
+                        status = singular ? ORC_SINGULAR : ORC_CONV_FAIL;
+                        goto finish;
+                    }
+                    continue;
+                }
+                err_norm = wrms(NC, d, w) / (order + 1);
+                if (err_norm > 1.0) {
+                    st->rejects++;
+                    double fac = o->safety * pow(err_norm, -1.0 / (order + 1));
+                    if (fac < o->fac_min) fac = o->fac_min;
+                    rescale_differences(NC, D, order, fac);
+                    h *= fac;
+                    n_equal = 0;
+                    if (h < o->h_min_rel * dt || t + h == t) {
+                        status = ORC_ERR_FAIL;
+                        goto finish;
+                    }
+                    continue;
+                }
+                accepted = 1;
+            }
+            t = landing ? dt : t + h;
+            st->steps++;
+            for (int i = 0; i < NC; ++i) {
+                D[(size_t)(order + 2) * NC + i] = d[i] - D[(size_t)(order + 1) * NC + i];
+                D[(size_t)(order + 1) * NC + i] = d[i];
+            }
+            for (int j = order; j >= 0; --j)
+                for (int i = 0; i < NC; ++i) D[(size_t)j * NC + i] += D[(size_t)(j + 1) * NC + i];
+            n_equal++;
+            if (t >= dt) break;
+            if (n_equal < order + 1) continue;
+            const double e_cur = err_norm;
+            const double e_low = order > 1 ? wrms(NC, D + (size_t)order * NC, w) / order : INFINITY;
+            const double e_high = order < maxord ? wrms(NC, D + (size_t)(order + 2) * NC, w) / (order + 2) : INFINITY;
+            const double r_cur = pow(e_cur, -1.0 / (order + 1));
+            const double r_low = order > 1 ? pow(e_low, -1.0 / order) : 0.0;
+            const double r_high = order < maxord ? pow(e_high, -1.0 / (order + 2)) : 0.0;
+            int new_order = order;
+            double best = r_cur;
+            if (r_low > best) { best = r_low; new_order = order - 1; }
+            if (r_high > best) { best = r_high; new_order = order + 1; }
+            double fac = o->safety * best;
+            if (fac > o->fac_max) fac = o->fac_max;
+            order = new_order;
+            rescale_differences(NC, D, order, fac);
+            h *= fac;
+            n_equal = 0;
+        }
+    }
+finish:
+    {
+        double ymin = INFINITY;
+        for (int i = 0; i < NC; ++i) {
+            Y[i] = D[i];
+            if (D[i] < ymin) ymin = D[i];
+        }
+        if (status == ORC_OK) st->y_min = ymin;  /* as cell_solve: only after a normal finish */
+        if (status == ORC_OK && !all_finite(NC, Y)) status = ORC_NONFINITE;
+        for (int c = 0; c < C; ++c) scatter_cell(Y + (size_t)c * N, N, n_cells, c, y);
+    }
+done:
+#undef SYS_DERIV
+    st->order = order;
+    st->h_last = h;
+    free(kc); free(Y); free(D); free(f); free(w); free(ypred); free(psi); free(d); free(ycur);
+    free(rhs); free(tmp); free(J); free(piv);
+    return status;
+}
+
 /* Number of OpenMP threads a parallel region would use. */
 int orc_max_threads(void)
 {
