@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--steps-per-launch", type=int, default=0,
                     help="0: each outer step in one launch (default); K > 0: the per-launch form, at most K "
                          "accepted BDF steps per launch with the solver state in HBM between launches")
+    ap.add_argument("--multicell", action="store_true",
+                    help="the paper's Multi-cells mode: all cells one system with a shared step size "
+                         "(the batch must fit on the device at once)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -227,7 +230,10 @@ def main():
         y.copy_(y0)
         if ev is not None:
             ev[0].record(stream)
-        cells.step(y, dt, opts, status, stats, stream=stream)
+        if args.multicell:
+            cells.step_multicell(y, dt, opts, status, stats, stream=stream)
+        else:
+            cells.step(y, dt, opts, status, stats, stream=stream)
         if ev is not None:
             ev[1].record(stream)
 
@@ -298,7 +304,8 @@ def main():
         "config": {"workload": f"{m.n_species} species / {m.n_reactions} reactions, {C} cells, "
                                f"one {dt:g} s BDF step + rate constants + fused f/J per step",
                    "cells": C, "species": m.n_species, "reactions": m.n_reactions, "dt_s": dt,
-                   "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch},
+                   "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch,
+                   "step_control": "multi-cells (shared)" if args.multicell else "per cell"},
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,

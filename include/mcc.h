@@ -277,6 +277,23 @@ mcc_status mcc_cells_set_rate_constants(mcc_cells *cells, const double *k, void 
 mcc_status mcc_solve_step(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
                           int32_t *cell_status, mcc_cell_stats *stats, void *stream);
 
+/* The paper's Multi-cells mode (Section 3: the data of every cell grouped
+ * into one structure and solved as one system; Section 5: the solver then
+ * needs about as many iterations for all cells as for one): one outer step
+ * of length dt in which all cells form one ODE system of n_species x n_cells
+ * unknowns with one shared step size and order, every WRMS norm taken over
+ * all cells, and one Newton iteration for the whole system (the Jacobian is
+ * block-diagonal, factorised cell by cell).  Arguments as mcc_solve_step;
+ * every cell gets the system's status, and the system's counters in its
+ * stats (y_min is the cell's own).  All cells are resident at once (a
+ * cooperative launch), so n_cells is limited by the device
+ * (MCC_ERR_INVALID_ARG beyond, with the limit in mcc_last_error());
+ * opts->steps_per_launch must be 0.  Implemented for mechanisms whose
+ * solver uses one slot, or two slots with no or a 48-row dense tail (up to
+ * about 110 species). */
+mcc_status mcc_solve_step_multicell(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
+                                    int32_t *cell_status, mcc_cell_stats *stats, void *stream);
+
 /* Wait for all work of this batch's device and report any asynchronous error. */
 mcc_status mcc_sync(mcc_cells *cells);
 

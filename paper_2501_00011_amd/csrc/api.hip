@@ -47,6 +47,8 @@ struct mcc_cells {
     int32_t *pending = nullptr;
     int32_t *pending_host = nullptr;  // pinned
     int32_t call_id = 0;
+    double *mc_slots = nullptr;  // Multi-cells reduction slots [2][mc_cells]
+    int64_t mc_cells = 0;
 };
 
 namespace {
@@ -574,23 +576,10 @@ static bool opts_valid(const mcc_solver_opts &o, std::string *why)
     return true;
 }
 
-mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
-                          mcc_cell_stats *stats, void *stream)
+static SolveParams solve_params(mcc_cells *c, double *y, double dt, const mcc_solver_opts &o, int32_t *cell_status,
+                                mcc_cell_stats *stats)
 {
-    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
-    if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(MCC_ERR_INVALID_ARG, "dt must be finite and > 0");
-    mcc_solver_opts o;
-    if (opts)
-        o = *opts;
-    else
-        mcc_solver_opts_default(&o);
-    std::string why;
-    if (!opts_valid(o, &why)) return set_error(MCC_ERR_INVALID_ARG, why);
-    if (c->n_cells == 0) return ok();
-    if (!y || !cell_status) return set_error(MCC_ERR_INVALID_ARG, "y and cell_status must not be null");
     const mcc_mech *m = c->mech;
-    DeviceGuard g(m->device);
     SolveParams p{};
     p.vspecies = m->vspecies;
     p.rx_reac = m->rx_reac;
@@ -628,6 +617,27 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     p.ld = c->ld;
     p.dt = dt;
     p.opts = o;
+    return p;
+}
+
+mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
+                          mcc_cell_stats *stats, void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(MCC_ERR_INVALID_ARG, "dt must be finite and > 0");
+    mcc_solver_opts o;
+    if (opts)
+        o = *opts;
+    else
+        mcc_solver_opts_default(&o);
+    std::string why;
+    if (!opts_valid(o, &why)) return set_error(MCC_ERR_INVALID_ARG, why);
+    if (c->n_cells == 0) return ok();
+    if (!y || !cell_status) return set_error(MCC_ERR_INVALID_ARG, "y and cell_status must not be null");
+    const mcc_mech *m = c->mech;
+    DeviceGuard g(m->device);
+    SolveParams p = solve_params(c, y, dt, o, cell_status, stats);
     if (o.steps_per_launch <= 0) {  // the whole outer step in one launch
         hipError_t e = launch_solve(p, m->t.NS, m->t.M, (hipStream_t)stream);
         if (e != hipSuccess) return hip_error(e, "solver kernel launch");
@@ -671,6 +681,46 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     return ok();
 }
 
+mcc_status mcc_solve_step_multicell(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts,
+                                    int32_t *cell_status, mcc_cell_stats *stats, void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(MCC_ERR_INVALID_ARG, "dt must be finite and > 0");
+    mcc_solver_opts o;
+    if (opts)
+        o = *opts;
+    else
+        mcc_solver_opts_default(&o);
+    std::string why;
+    if (!opts_valid(o, &why)) return set_error(MCC_ERR_INVALID_ARG, why);
+    if (o.steps_per_launch != 0) return set_error(MCC_ERR_INVALID_ARG, "Multi-cells runs in one launch: steps_per_launch must be 0");
+    if (c->n_cells == 0) return ok();
+    if (!y || !cell_status) return set_error(MCC_ERR_INVALID_ARG, "y and cell_status must not be null");
+    const mcc_mech *m = c->mech;
+    DeviceGuard g(m->device);
+    int64_t cap = 0;
+    hipError_t e = multicell_capacity(m->t.NS, m->t.M, (size_t)m->lds_doubles * sizeof(double), m->device, &cap);
+    if (e != hipSuccess) return hip_error(e, "Multi-cells occupancy");
+    if (cap == 0) return set_error(MCC_ERR_INVALID_ARG, "no Multi-cells solver for this mechanism's size");
+    if (c->n_cells > cap)
+        return set_error(MCC_ERR_INVALID_ARG, "Multi-cells needs every cell resident at once: at most " +
+                                                  std::to_string(cap) + " cells of this mechanism on this device");
+    if (c->mc_cells < c->n_cells) {
+        if (c->mc_slots) (void)hipFree(c->mc_slots);
+        c->mc_slots = nullptr;
+        c->mc_cells = 0;
+        e = hipMalloc(&c->mc_slots, 2 * (size_t)c->n_cells * sizeof(double));
+        if (e != hipSuccess) return hip_error(e, "hipMalloc (Multi-cells reduction slots)");
+        c->mc_cells = c->n_cells;
+    }
+    SolveParams p = solve_params(c, y, dt, o, cell_status, stats);
+    p.mc_slots = c->mc_slots;
+    e = launch_solve_multicell(p, m->t.NS, m->t.M, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "Multi-cells solver launch");
+    return ok();
+}
+
 mcc_status mcc_sync(mcc_cells *c)
 {
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
@@ -685,7 +735,7 @@ mcc_status mcc_cells_destroy(mcc_cells *c)
     if (!c) return ok();
     DeviceGuard g(c->mech->device);
     hipError_t e = hipDeviceSynchronize();
-    for (void *buf : {(void *)c->k, (void *)c->ones, (void *)c->state, (void *)c->pending})
+    for (void *buf : {(void *)c->k, (void *)c->ones, (void *)c->state, (void *)c->pending, (void *)c->mc_slots})
         if (buf) {
             hipError_t e2 = hipFree(buf);
             if (e == hipSuccess) e = e2;

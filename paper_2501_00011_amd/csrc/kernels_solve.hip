@@ -23,6 +23,8 @@
 //               column-major; + a zero cell and a write-only cell), and the
 //               6 x 6 transform of a step-size change.
 //   HBM       : only y in/out, k in, status and stats out.
+#include <hip/hip_cooperative_groups.h>
+
 #include "mcc_internal.hpp"
 
 namespace mcc {
@@ -399,7 +401,8 @@ struct Cell {
         }
     }
 
-    __device__ __forceinline__ double wrms(const double (&v)[NS], const double (&w)[NS]) const
+    // sum over this cell of (v_i w_i)^2, the same on every lane
+    __device__ __forceinline__ double ssq(const double (&v)[NS], const double (&w)[NS]) const
     {
         double acc = 0.0;
 #pragma unroll
@@ -407,7 +410,12 @@ struct Cell {
             const double t = v[s] * w[s];
             acc += t * t;
         }
-        return sqrt(wave_sum(acc) / N);
+        return wave_sum(acc);
+    }
+
+    __device__ __forceinline__ double wrms(const double (&v)[NS], const double (&w)[NS]) const
+    {
+        return sqrt(ssq(v, w) / N);
     }
 
     __device__ __forceinline__ bool any_nonfinite(const double (&v)[NS]) const
@@ -461,7 +469,30 @@ __device__ __forceinline__ void rescale(double (&D)[kMaxOrder + 3][NS], int orde
     }
 }
 
-template <int NS, int M>
+// Multi-cells: sums over all cells of the launch (one workgroup per cell,
+// all co-resident: a cooperative launch).  Every wavefront publishes its
+// value in a slot of its own, waits at the grid barrier, then adds all slots
+// in one fixed order, so every wavefront obtains the same bits and takes the
+// same decisions.  Two slot arrays alternate: the barrier of reduction r + 1
+// separates reading r from writing r + 2.  Slots are read and written with
+// device-scope atomics, coherent across the XCDs' separate L2 caches.
+struct GridSum {
+    double *slots;  // [2][n]
+    int n, r;
+
+    __device__ __forceinline__ double sum(double v)  // v: the same on every lane
+    {
+        double *b = slots + (size_t)(r & 1) * n;
+        if (threadIdx.x == 0) __hip_atomic_store(&b[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cooperative_groups::this_grid().sync();
+        double acc = 0.0;
+        for (int i = (int)threadIdx.x; i < n; i += kWave) acc += __hip_atomic_load(&b[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++r;
+        return wave_sum(acc);
+    }
+};
+
+template <int NS, int M, bool MC>
 __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
 {
     extern __shared__ double smem[];
@@ -478,6 +509,14 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
     }
     Cell<NS, M> C(p, smem);
     const int lane = C.lane, N = p.N;
+    // norms and failure flags: of this cell, or (Multi-cells) of the whole system
+    GridSum grid{p.mc_slots, (int)p.n_cells, 0};
+    const double n_all = MC ? (double)N * (double)p.n_cells : (double)N;
+    auto norm = [&](const double (&v)[NS], const double (&w)[NS]) -> double {
+        const double q = C.ssq(v, w);
+        return sqrt((MC ? grid.sum(q) : q) / n_all);
+    };
+    auto any_cell = [&](bool b) -> bool { return MC ? grid.sum(b ? 1.0 : 0.0) > 0.0 : b; };
     const mcc_solver_opts &o = p.opts;
     const double dt = p.dt;
     const int maxord = o.max_order < 1 ? 1 : (o.max_order > kMaxOrder ? kMaxOrder : o.max_order);
@@ -522,14 +561,14 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
         // ---- starting step size -------------------------------------------------
         C.deriv(D[0], f);
         f_evals++;
-        bad = C.any_nonfinite(D[0]) || C.any_nonfinite(f);
+        bad = any_cell(C.any_nonfinite(D[0]) || C.any_nonfinite(f));
         if (bad) {
             status = MCC_CELL_NONFINITE;
             order = 0;
         } else {
 #pragma unroll
             for (int s = 0; s < NS; ++s) w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
-            const double d0 = C.wrms(D[0], w), d1 = C.wrms(f, w);
+            const double d0 = norm(D[0], w), d1 = norm(f, w);
             const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
 #pragma unroll
             for (int s = 0; s < NS; ++s) ypred[s] = D[0][s] + h0 * f[s];
@@ -537,7 +576,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
             f_evals++;
 #pragma unroll
             for (int s = 0; s < NS; ++s) tmp[s] -= f[s];
-            const double d2 = C.wrms(tmp, w) / h0;
+            const double d2 = norm(tmp, w) / h0;
             const double dm = d1 > d2 ? d1 : d2;
             const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
             h = fmin(100.0 * h0, fmin(h1, dt));
@@ -600,7 +639,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                 C.newton_matrix(ypred, c);
                 jac_evals++;
                 lu_count++;
-                const bool singular = C.factor();
+                const bool singular = any_cell(C.factor());
                 bool converged = false;
                 if (!singular) {
                     double nrm_old = 0.0;
@@ -609,12 +648,12 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                         for (int s = 0; s < NS; ++s) tmp[s] = ypred[s] + d[s];
                         C.deriv(tmp, f);
                         f_evals++;
-                        if (C.any_nonfinite(f)) break;
+                        if (any_cell(C.any_nonfinite(f))) break;
 #pragma unroll
                         for (int s = 0; s < NS; ++s) tmp[s] = c * f[s] - psi[s] - d[s];
                         C.solve(tmp);
                         newton_iters++;
-                        const double nrm = C.wrms(tmp, w);
+                        const double nrm = norm(tmp, w);
                         if (!isfinite(nrm)) break;
                         double rho = 0.0;
                         if (it >= 1) {
@@ -642,7 +681,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                     }
                     continue;
                 }
-                err_norm = C.wrms(d, w) / (order + 1);
+                err_norm = norm(d, w) / (order + 1);
                 if (err_norm > 1.0) {
                     rejects++;
                     double fac = o.safety * step_pow(err_norm, -1.0 / (order + 1));
@@ -689,7 +728,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                         v += j == order ? D[j][s] : 0.0;
                     tmp[s] = v;
                 }
-                e_low = C.wrms(tmp, w) / order;
+                e_low = norm(tmp, w) / order;
             }
             if (order < maxord) {
 #pragma unroll
@@ -700,7 +739,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
                         v += j == order + 2 ? D[j][s] : 0.0;
                     tmp[s] = v;
                 }
-                e_high = C.wrms(tmp, w) / (order + 2);
+                e_high = norm(tmp, w) / (order + 2);
             }
             const double r_cur = step_pow(e_cur, -1.0 / (order + 1));
             const double r_low = order > 1 ? step_pow(e_low, -1.0 / order) : 0.0;
@@ -755,7 +794,7 @@ __global__ __launch_bounds__(64) void bdf_kernel(SolveParams p)
             }
         if (status == MCC_CELL_OK) {
             ymin = wave_min(lm);
-            bool fin = !C.any_nonfinite(D[0]);
+            bool fin = !any_cell(C.any_nonfinite(D[0]));
             if (!fin) status = MCC_CELL_NONFINITE;
         }
     }
@@ -793,15 +832,24 @@ __global__ void fill_i32_kernel(int32_t *q, int32_t v)
     X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 32) X(2, 32) X(3, 32) X(4, 32) \
     X(1, 48) X(2, 48) X(3, 48) X(4, 48) X(1, 64) X(2, 64) X(3, 64) X(4, 64)
 
+// Multi-cells instantiations (small and 72-species class mechanisms).
+#define MCC_MULTICELL_VARIANTS(X) X(1, 0) X(2, 0) X(2, 48)
+
 hipError_t prepare_solve_kernels(int max_lds_bytes)
 {
     hipError_t e = hipSuccess;
 #define MCC_SET_LDS(ns, m)                                                                                    \
     if (e == hipSuccess)                                                                                     \
-        e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+        e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m, false>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                 max_lds_bytes);
     MCC_SOLVE_VARIANTS(MCC_SET_LDS)
 #undef MCC_SET_LDS
+#define MCC_SET_LDS_MC(ns, m)                                                                                \
+    if (e == hipSuccess)                                                                                    \
+        e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                max_lds_bytes);
+    MCC_MULTICELL_VARIANTS(MCC_SET_LDS_MC)
+#undef MCC_SET_LDS_MC
     return e;
 }
 
@@ -817,13 +865,44 @@ hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
     if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)p.n_cells), block(kWave);
     const size_t lds = (size_t)p.lds_doubles * sizeof(double);
-#define MCC_LAUNCH(ns, m)                                                  \
-    if (NS == ns && M == m) {                                              \
-        hipLaunchKernelGGL((bdf_kernel<ns, m>), grid, block, lds, s, p); \
-        return hipGetLastError();                                          \
+#define MCC_LAUNCH(ns, m)                                                         \
+    if (NS == ns && M == m) {                                                     \
+        hipLaunchKernelGGL((bdf_kernel<ns, m, false>), grid, block, lds, s, p); \
+        return hipGetLastError();                                                 \
     }
     MCC_SOLVE_VARIANTS(MCC_LAUNCH)
 #undef MCC_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t multicell_capacity(int NS, int M, size_t lds_bytes, int device, int64_t *max_cells)
+{
+    *max_cells = 0;
+    const void *fn = nullptr;
+#define MCC_FN(ns, m) \
+    if (NS == ns && M == m) fn = (const void *)bdf_kernel<ns, m, true>;
+    MCC_MULTICELL_VARIANTS(MCC_FN)
+#undef MCC_FN
+    if (!fn) return hipSuccess;  // no Multi-cells kernel for this solver shape
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWave, lds_bytes);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) *max_cells = (int64_t)per_cu * n_cu;
+    return e;
+}
+
+hipError_t launch_solve_multicell(const SolveParams &p, int NS, int M, hipStream_t s)
+{
+    if (p.n_cells == 0) return hipSuccess;
+    const dim3 grid((unsigned)p.n_cells), block(kWave);
+    const size_t lds = (size_t)p.lds_doubles * sizeof(double);
+    SolveParams q = p;
+    void *args[] = {(void *)&q};
+#define MCC_LAUNCH_MC(ns, m)                                                                               \
+    if (NS == ns && M == m)                                                                                \
+        return hipLaunchCooperativeKernel((const void *)bdf_kernel<ns, m, true>, grid, block, args, lds, s);
+    MCC_MULTICELL_VARIANTS(MCC_LAUNCH_MC)
+#undef MCC_LAUNCH_MC
     return hipErrorInvalidValue;
 }
 

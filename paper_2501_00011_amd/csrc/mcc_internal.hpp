@@ -178,6 +178,8 @@ struct SolveParams {
     int32_t *pending;  // cells this launch left unfinished (one atomic add per cell)
     int64_t state_stride;
     int32_t call_id;   // the outer step this launch belongs to
+    // Multi-cells (one system over all cells): [2][n_cells] reduction slots
+    double *mc_slots;
 };
 constexpr int kStateScalars = 16;
 
@@ -193,5 +195,8 @@ hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).
 hipError_t prepare_solve_kernels(int max_lds_bytes);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);  // *p = v by a kernel (graph-safe)
+// Multi-cells solver: largest co-resident batch (0: no kernel for this shape), cooperative launch.
+hipError_t multicell_capacity(int NS, int M, size_t lds_bytes, int device, int64_t *max_cells);
+hipError_t launch_solve_multicell(const SolveParams &p, int NS, int M, hipStream_t s);
 
 }  // namespace mcc

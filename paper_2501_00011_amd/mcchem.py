@@ -72,6 +72,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_debug_emulate_fj": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
         "mcc_debug_fj_source": ([vp, vp, i64, vp], ctypes.c_int),
         "mcc_debug_compile_fj": ([vp, ctypes.c_char_p, vp], ctypes.c_int),
@@ -331,6 +332,20 @@ class Cells:
         _check(library().mcc_solve_step(self._h, _dptr(y, "y", torch.float64, self._yshape()), float(dt), op,
                                         _dptr(status, "status", torch.int32, (self.n_cells,)), sp,
                                         _stream_ptr(stream)))
+        return status, stats
+
+    def step_multicell(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, stream=None):
+        """The Multi-cells outer step: all cells as one system (shared h and order)."""
+        import torch
+        if status is None:
+            status = torch.empty(self.n_cells, dtype=torch.int32, device=y.device)
+        if stats is None:
+            stats = torch.empty((self.n_cells, STATS_DTYPE.itemsize), dtype=torch.uint8, device=y.device)
+        op = ctypes.addressof(opts) if opts is not None else None
+        _check(library().mcc_solve_step_multicell(
+            self._h, _dptr(y, "y", torch.float64, self._yshape()), float(dt), op,
+            _dptr(status, "status", torch.int32, (self.n_cells,)),
+            _dptr(stats, "stats", torch.uint8, (self.n_cells, STATS_DTYPE.itemsize)), _stream_ptr(stream)))
         return status, stats
 
     def sync(self):

@@ -265,6 +265,7 @@ def workload(name: str, n_cells: int | None = None):
     medium10k : 72/156 mechanism, 10,000 cells, T 220-310 K, P 100-1013 hPa, one 180 s step
     medium200k: as medium10k with 200,000 cells and photolysis scale log-uniform 1e-3..1
     adjoint10k: as medium10k, 60 s steps (ten of them for the adjoint workload)
+    paper_test: Section 4's 3-species mechanism, 1,000 cells with index offsets, one 60 s step
     """
     if name == "small10":
         m = mech_small_thermal()
@@ -278,6 +279,17 @@ def workload(name: str, n_cells: int | None = None):
         m = mech_medium()
         c = make_cells(m, n_cells or 200000, seed=1003, jscale_log10_range=(-3.0, 0.0))
         return m, c, 180.0
+    if name == "paper_test":
+        # Section 4's mechanism: A gives B and C through two Arrhenius
+        # reactions (theta = 0; A = 0.05 and 0.02 s^-1, parameters the paper
+        # does not print); A = 1, B = C = 0 plus 0.1 * (flattened index + 1)
+        # over the concatenated cells; T, P and parameters equal in all cells
+        C = n_cells or 1000
+        m = mechanism_from_lists(3, [([0], [(1, 1.0)], 0.05, 0.0, RXN_THERMAL),
+                                     ([0], [(2, 1.0)], 0.02, 0.0, RXN_THERMAL)])
+        flat = np.concatenate([np.array([1.0, 0.0, 0.0]) + 0.1 * (c * 3 + np.arange(3) + 1) for c in range(C)])
+        c = Cells(T=np.full(C, 298.0), P=np.full(C, 1013.25), jscale=np.ones(C), y0=flat.reshape(C, 3).T.copy())
+        return m, c, 60.0
     if name == "adjoint10k":
         m = mech_medium()
         c = make_cells(m, n_cells or 10000, seed=1005)

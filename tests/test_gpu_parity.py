@@ -491,3 +491,72 @@ def test_autograd_deriv(dev, oracle_mod):
     assert np.all(np.abs(f.detach().cpu().numpy() - f_ref) <= 1e-11 * fs)
     assert np.all(np.abs(y.grad.cpu().numpy() - gy_ref) <= 1e-11 * by)
     assert np.all(np.abs(lnk.grad.cpu().numpy() - gk_ref) <= 1e-11 * bk)
+
+
+# ---- the paper's Multi-cells mode -------------------------------------------
+
+def _multicell(b, dt, opts_kw=None, atol=None):
+    import oracle as orc
+    kw = dict(opts_kw or {})
+    if atol is not None:
+        kw["atol"] = atol
+    y = b.y_dev()
+    st, stats = b.cells.step_multicell(y, dt, mcchem.default_opts(**kw))
+    torch.cuda.synchronize()
+    k = b.o.rate_constants(b.c.T, b.c.jscale)
+    yo, so, sto = b.o.solve_multicell(k, b.c.y0, dt, orc.default_opts(**kw))
+    return y.cpu().numpy()[:, :b.C], st.cpu().numpy(), mcchem.stats_numpy(stats), yo, so, sto
+
+
+@pytest.mark.parametrize("C", [1, 37, 1000])
+def test_multicell_paper_mechanism(dev, oracle_mod, C):
+    m, c, dt = synth.workload("paper_test", C)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    yg, sg, stg, yo, so, sto = _multicell(b, dt, atol=1e-14)
+    assert so == 0 and np.all(sg == 0)
+    assert _within(yg, yo, 1e-14) <= 1.0
+    # one shared step sequence: every cell reports the system's counters
+    assert np.all(stg["steps"] == stg["steps"][0]) and abs(int(stg["steps"][0]) - int(sto["steps"])) <= 2
+    ks = 0.07
+    A = c.y0[0] * math.exp(-ks * dt)
+    exact = np.stack([A, c.y0[1] + 0.05 / ks * (c.y0[0] - A), c.y0[2] + 0.02 / ks * (c.y0[0] - A)])
+    assert _within(yg, exact, 1e-14) <= 1.0
+
+
+@pytest.mark.parametrize("name,n", [("small10", 10), ("medium10k", 64)])
+def test_multicell_parity(dev, oracle_mod, name, n):
+    m, c, dt = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=n + 3, oracle_mod=oracle_mod)
+    yg, sg, stg, yo, so, sto = _multicell(b, dt)
+    assert so == 0 and np.all(sg == 0)
+    assert _within(yg, yo, 1.0) <= 1.0
+    assert abs(int(stg["steps"][0]) - int(sto["steps"])) <= 0.05 * int(sto["steps"]) + 2
+
+
+def test_multicell_one_cell_is_per_cell_and_deterministic(dev):
+    m, c, dt = synth.workload("medium10k", 1)
+    b = Batch(dev, m, c)
+    y1, y2, y3 = b.y_dev(), b.y_dev(), b.y_dev()
+    b.cells.step(y1, dt)
+    b.cells.step_multicell(y2, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    m, c, dt = synth.workload("small10")
+    b = Batch(dev, m, c)
+    y1, y2 = b.y_dev(), b.y_dev()
+    b.cells.step_multicell(y1, dt)
+    b.cells.step_multicell(y2, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+def test_multicell_limits(dev):
+    m, c, dt = synth.workload("paper_test", 1)
+    h = mcchem.Mechanism(m)
+    big = mcchem.Cells(h, 300000)
+    big.bind(torch.full((300000,), 298.0, dtype=torch.float64, device=dev))
+    y = torch.ones((3, 300000), dtype=torch.float64, device=dev)
+    with pytest.raises(mcchem.MccError, match="at most"):
+        big.step_multicell(y, dt)
+    with pytest.raises(mcchem.MccError, match="steps_per_launch"):
+        big.step_multicell(y, dt, mcchem.default_opts(steps_per_launch=2))
