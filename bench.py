@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--multicell", action="store_true",
                     help="the paper's Multi-cells mode: all cells one system with a shared step size "
                          "(the batch must fit on the device at once)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="time the paper's Derivative kernel (thread per reaction, atomic adds; record and "
+                         "inverted reaction data; with and without per-call host-device copies) beside "
+                         "this library's f kernel, and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -190,6 +194,64 @@ def bench_mixed(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_ablation(args):
+    """f for every cell of the workload, four ways, each the median of
+    --fj-reps launches timed with events on one stream."""
+    import numpy as np
+    import torch
+
+    from paper_2501_00011_amd import mcchem, synth
+    m, c, dt = synth.workload(args.workload, args.cells)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mech = mcchem.Mechanism(m, device=0)
+    C = c.n_cells
+    cells = mcchem.Cells(mech, C)
+    cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
+    y = torch.from_numpy(c.y0).to(dev)
+    f = torch.empty_like(y)
+    k_cm = cells.rate_constants().t().contiguous()          # [C][R], the paper's layout
+    y_cm = y.t().contiguous()
+    f_cm = torch.empty_like(y_cm)
+    y_host = y_cm.cpu().pin_memory()
+    f_host = torch.empty_like(y_cm, device="cpu").pin_memory()
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(args.fj_reps, 1)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            ts.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ts])) * 1e3  # us
+
+    def paper_with_copies():
+        y_cm.copy_(y_host, non_blocking=True)
+        mech.paper_deriv(y_cm, k_cm, f_cm, inverted=True, stream=stream)
+        f_host.copy_(f_cm, non_blocking=True)
+
+    res = {
+        "ours_generated_f_us": timed(lambda: cells.deriv(y, f, stream=stream)),
+        "paper_records_us": timed(lambda: mech.paper_deriv(y_cm, k_cm, f_cm, inverted=False, stream=stream)),
+        "paper_inverted_us": timed(lambda: mech.paper_deriv(y_cm, k_cm, f_cm, inverted=True, stream=stream)),
+        "paper_inverted_with_copies_us": timed(paper_with_copies),
+    }
+    torch.cuda.synchronize()
+    fb = mech.op_counts()["f_bytes"] * C
+    out = {"metric": "f evaluation time (us, median)", "workload": f"{m.n_species} species / {m.n_reactions} "
+           f"reactions, {C} cells", "f_bytes_algorithmic": fb, **{k: round(v, 2) for k, v in res.items()},
+           "inversion_speedup": res["paper_records_us"] / res["paper_inverted_us"],
+           "copy_share_of_paper_call": 1.0 - res["paper_inverted_us"] / res["paper_inverted_with_copies_us"],
+           "ours_vs_paper_inverted": res["paper_inverted_us"] / res["ours_generated_f_us"],
+           "ours_f_GBps": fb / res["ours_generated_f_us"] / 1e3}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -199,6 +261,9 @@ def main():
         print("bench.py runs on one GPU only: the cells of this workload are independent and this "
               "build measures one GPU's share; use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.ablation:
+        bench_ablation(args)
+        return
     if args.workload == "mixed100k":
         bench_mixed(args)
         return

@@ -261,6 +261,17 @@ mcc_status mcc_calc_deriv_jac(const mcc_cells *cells, const double *y, double *f
 mcc_status mcc_calc_vjp(const mcc_cells *cells, const double *y, const double *v, double *gy, double *glnk,
                         void *stream);
 
+/* Ablation (measurement aid, not the library's path): the paper's GPU
+ * Derivative kernel (Section 3) -- one thread per (cell, reaction), 1024
+ * threads per block, f accumulated with atomic adds -- on the paper's
+ * concatenated layout: y, f device [n_cells][n_species] (species i of cell c
+ * at c * n_species + i), k device [n_cells][n_reactions].  inverted = 0
+ * reads the reaction data as one record per reaction, 1 as one array per
+ * parameter (the paper's inversion).  f is zeroed by the call.  MCC_ERR_MECH
+ * if a reaction has more than 4 products. */
+mcc_status mcc_ablation_paper_deriv(const mcc_mech *mech, int64_t n_cells, const double *y, const double *k,
+                                    double *f, int32_t inverted, void *stream);
+
 /* Replace the batch's rate constants by caller values (device [n_reactions]
  * [ld], copied on `stream`), e.g. k = exp(ln k) of a parameter being
  * differentiated; the batch then counts as bound. */

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libmcchem.so")
 SOURCES = ["csrc/api.hip", "csrc/kernels_fj.hip", "csrc/kernels_solve.hip", "csrc/mech_compile.cpp",
-           "csrc/mech_emulate.cpp", "csrc/fj_codegen.cpp"]
+           "csrc/mech_emulate.cpp", "csrc/fj_codegen.cpp", "csrc/kernels_paper.hip"]
 ARCH = os.environ.get("MCC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions stay off: the library computes in FP64, and packed

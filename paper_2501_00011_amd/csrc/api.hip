@@ -21,6 +21,8 @@ struct mcc_mech {
     const FjRec *fj_recs = nullptr;
     const FjChunk *fj_chunks = nullptr;
     const int32_t *fj_items = nullptr;
+    const int32_t *paper_rec = nullptr, *paper_rec_inv = nullptr;
+    const double *paper_yld = nullptr, *paper_yld_inv = nullptr;
     const double *A = nullptr, *theta = nullptr;
     const int32_t *vspecies = nullptr, *rx_reac = nullptr, *part = nullptr;
     const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
@@ -206,6 +208,8 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
     const size_t o_monos = pk.add(t.fj_monos), o_recs = pk.add(t.fj_recs);
     const size_t o_chunks = pk.add(t.fj_chunks), o_items = pk.add(t.fj_items);
+    const size_t o_prec = pk.add(t.paper_rec), o_pyld = pk.add(t.paper_yld);
+    const size_t o_preci = pk.add(t.paper_rec_inv), o_pyldi = pk.add(t.paper_yld_inv);
     const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
     const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
@@ -226,6 +230,10 @@ mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out
     m->fj_recs = (const FjRec *)(b + o_recs);
     m->fj_chunks = (const FjChunk *)(b + o_chunks);
     m->fj_items = (const int32_t *)(b + o_items);
+    m->paper_rec = (const int32_t *)(b + o_prec);
+    m->paper_yld = (const double *)(b + o_pyld);
+    m->paper_rec_inv = (const int32_t *)(b + o_preci);
+    m->paper_yld_inv = (const double *)(b + o_pyldi);
 
     m->vspecies = (const int32_t *)(b + o_perm);
     m->rx_reac = (const int32_t *)(b + o_rxr);
@@ -519,6 +527,23 @@ mcc_status mcc_calc_vjp(const mcc_cells *c, const double *y, const double *v, do
     hipError_t e = hipModuleLaunchKernel(c->mech->vjp_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
                                          args, nullptr);
     if (e != hipSuccess) return hip_error(e, "generated VJP kernel launch");
+    return ok();
+}
+
+mcc_status mcc_ablation_paper_deriv(const mcc_mech *m, int64_t n_cells, const double *y, const double *k,
+                                    double *f, int32_t inverted, void *stream)
+{
+    if (!m) return set_error(MCC_ERR_INVALID_ARG, "mech is null");
+    if (m->device < 0) return set_error(MCC_ERR_STATE, "mechanism was compiled host-only (device -1)");
+    if (n_cells < 0) return set_error(MCC_ERR_INVALID_ARG, "n_cells < 0");
+    if (!m->t.paper_ok) return set_error(MCC_ERR_MECH, "a reaction has more products than the paper-layout records hold");
+    if (n_cells == 0) return ok();
+    if (!y || !k || !f) return set_error(MCC_ERR_INVALID_ARG, "null array");
+    if (n_cells * (int64_t)m->t.R > ((int64_t)1 << 40)) return set_error(MCC_ERR_INVALID_ARG, "too many cells");
+    DeviceGuard g(m->device);
+    hipError_t e = launch_paper_deriv(inverted ? m->paper_rec_inv : m->paper_rec, inverted ? m->paper_yld_inv : m->paper_yld,
+                                      inverted != 0, y, k, f, m->t.N, m->t.R, n_cells, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "paper Derivative kernel launch");
     return ok();
 }
 

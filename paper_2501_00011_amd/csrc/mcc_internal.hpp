@@ -87,6 +87,10 @@ struct HostTables {
     std::vector<int32_t> rx_sp;       // [3 * R]
     std::vector<int32_t> nu_ptr, nu_sp;
     std::vector<double> nu_coef;
+    // the paper's Derivative kernel data (ablation): records and inverted
+    std::vector<int32_t> paper_rec, paper_rec_inv;
+    std::vector<double> paper_yld, paper_yld_inv;
+    bool paper_ok = false;  // at most kPaperProd products per reaction
 
     // Solver.  Positions p = 0..N-1 are the elimination (fill-reducing)
     // order; every position lives at a virtual index v = slot * 64 + lane of
@@ -188,7 +192,14 @@ hipError_t launch_rates(const RatesParams &p, hipStream_t s);
 hipError_t launch_fj(const FJParams &p, hipStream_t s);
 // Mechanism-specialised f/J kernel (same work items, compiled with hipRTC).
 std::string generate_fj_source(const HostTables &t);
-std::string generate_vjp_source(const HostTables &t);  // appended to the f/J source: one module
+std::string generate_vjp_source(const HostTables &t);
+// Ablation of the paper's Derivative kernel: reaction data as records
+// [reaction][kPaperRec] (n_reac, 3 reactants, n_prod, kPaperProd products)
+// with yields [reaction][kPaperProd], or inverted [parameter][reaction].
+constexpr int kPaperProd = 4;
+constexpr int kPaperRec = 5 + kPaperProd;
+hipError_t launch_paper_deriv(const int32_t *rec, const double *yld, bool inverted, const double *y,
+                              const double *k, double *f, int N, int R, int64_t n_cells, hipStream_t s);  // appended to the f/J source: one module
 constexpr int kVjpRxnGroup = 16;  // reactions per d/d ln k work item
 bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log);
 hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);

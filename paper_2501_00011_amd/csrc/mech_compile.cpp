@@ -225,6 +225,32 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
         t->nu_ptr.push_back((int32_t)t->nu_sp.size());
     }
 
+    // ---- the paper's Derivative kernel data (ablation only) ---------------
+    t->paper_ok = true;
+    t->paper_rec.assign((size_t)R * kPaperRec, 0);
+    t->paper_yld.assign((size_t)R * kPaperProd, 0.0);
+    for (int j = 0; j < R; ++j) {
+        const int nr = d->reac_ptr[j + 1] - d->reac_ptr[j], np = d->prod_ptr[j + 1] - d->prod_ptr[j];
+        if (np > kPaperProd) {
+            t->paper_ok = false;
+            continue;
+        }
+        int32_t *q = &t->paper_rec[(size_t)j * kPaperRec];
+        q[0] = nr;
+        for (int a = 0; a < nr; ++a) q[1 + a] = d->reac_idx[d->reac_ptr[j] + a];
+        q[4] = np;
+        for (int a = 0; a < np; ++a) {
+            q[5 + a] = d->prod_idx[d->prod_ptr[j] + a];
+            t->paper_yld[(size_t)j * kPaperProd + a] = d->prod_yield[d->prod_ptr[j] + a];
+        }
+    }
+    t->paper_rec_inv.assign((size_t)R * kPaperRec, 0);
+    t->paper_yld_inv.assign((size_t)R * kPaperProd, 0.0);
+    for (int j = 0; j < R; ++j) {
+        for (int p = 0; p < kPaperRec; ++p) t->paper_rec_inv[(size_t)p * R + j] = t->paper_rec[(size_t)j * kPaperRec + p];
+        for (int p = 0; p < kPaperProd; ++p) t->paper_yld_inv[(size_t)p * R + j] = t->paper_yld[(size_t)j * kPaperProd + p];
+    }
+
     // ---- streaming f/J tables (species order) ------------------------------
     // Units: an f row i (monomials = the rates of the reactions that change
     // i) and a J column s (monomials = the partials d r_j / d y_s through each

@@ -73,6 +73,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
         "mcc_debug_fj_source": ([vp, vp, i64, vp], ctypes.c_int),
         "mcc_debug_compile_fj": ([vp, ctypes.c_char_p, vp], ctypes.c_int),
@@ -203,6 +204,19 @@ class Mechanism:
         n = ctypes.c_int64()
         _check(library().mcc_debug_compile_fj(self._h, arch.encode(), ctypes.byref(n)))
         return n.value
+
+    def paper_deriv(self, y_cm, k_cm, f_cm=None, inverted=False, stream=None):
+        """Ablation: the paper's Derivative kernel on cell-major arrays
+        y [C][N], k [C][R] -> f [C][N] (device float64)."""
+        import torch
+        C = y_cm.shape[0]
+        if f_cm is None:
+            f_cm = torch.empty_like(y_cm)
+        _check(library().mcc_ablation_paper_deriv(
+            self._h, C, _dptr(y_cm, "y", torch.float64, (C, self.n_species)),
+            _dptr(k_cm, "k", torch.float64, (C, self.n_reactions)),
+            _dptr(f_cm, "f", torch.float64, (C, self.n_species)), int(bool(inverted)), _stream_ptr(stream)))
+        return f_cm
 
     def schedule_info(self) -> dict:
         """Sizes of the solver schedule (testing aid)."""

@@ -560,3 +560,20 @@ def test_multicell_limits(dev):
         big.step_multicell(y, dt)
     with pytest.raises(mcchem.MccError, match="steps_per_launch"):
         big.step_multicell(y, dt, mcchem.default_opts(steps_per_launch=2))
+
+
+# ---- ablation: the paper's Derivative kernel -------------------------------
+
+@pytest.mark.parametrize("inverted", [False, True])
+def test_paper_deriv_kernel(dev, oracle_mod, inverted):
+    """The paper's one-thread-per-reaction kernel with atomic adds, on its
+    concatenated cell-major layout, computes f (to rounding: the atomic adds
+    sum in any order)."""
+    m, c, _ = synth.workload("medium10k", 500)
+    o = oracle_mod.Oracle(m)
+    k = o.rate_constants(c.T, c.jscale)
+    h = mcchem.Mechanism(m)
+    f = h.paper_deriv(_t(c.y0.T, dev), _t(k.T, dev), inverted=inverted)
+    torch.cuda.synchronize()
+    f_ref, fs = o.deriv(k, c.y0)
+    assert np.all(np.abs(f.cpu().numpy().T - f_ref) <= 1e-12 * fs)
