@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--multicell", action="store_true",
                     help="the paper's Multi-cells mode: all cells one system with a shared step size "
                          "(the batch must fit on the device at once)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the solver's dense-tail size by timing each choice on the first 2,048 cells "
+                         "(untimed, before the warm-up)")
     ap.add_argument("--ablation", action="store_true",
                     help="time the paper's Derivative kernel (thread per reaction, atomic adds; record and "
                          "inverted reaction data; with and without per-call host-device copies) beside "
@@ -204,7 +207,13 @@ def bench_ablation(args):
     m, c, dt = synth.workload(args.workload, args.cells)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    mech = mcchem.Mechanism(m, device=0)
+    tuned = None
+    if args.autotune:
+        n = min(2048, c.n_cells)
+        sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
+        mech, tuned = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts())
+    else:
+        mech = mcchem.Mechanism(m, device=0)
     C = c.n_cells
     cells = mcchem.Cells(mech, C)
     cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
@@ -274,7 +283,13 @@ def main():
 
     m, c, dt = synth.workload(args.workload, args.cells)
     dev = torch.device("cuda:0")
-    mech = mcchem.Mechanism(m, device=0)
+    tuned = None
+    if args.autotune:
+        n = min(2048, c.n_cells)
+        sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
+        mech, tuned = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts())
+    else:
+        mech = mcchem.Mechanism(m, device=0)
     C = c.n_cells
     cells = mcchem.Cells(mech, C)
     T = torch.from_numpy(c.T).to(dev)
@@ -370,7 +385,9 @@ def main():
                                f"one {dt:g} s BDF step + rate constants + fused f/J per step",
                    "cells": C, "species": m.n_species, "reactions": m.n_reactions, "dt_s": dt,
                    "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch,
-                   "step_control": "multi-cells (shared)" if args.multicell else "per cell"},
+                   "step_control": "multi-cells (shared)" if args.multicell else "per cell",
+                   "dense_tail": mech.schedule_info()["dense_tail"],
+                   "autotune_ms": {str(k): round(v, 2) for k, v in tuned.items()} if tuned else None},
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,

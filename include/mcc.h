@@ -145,6 +145,24 @@ mcc_status mcc_solver_opts_default(mcc_solver_opts *opts);
  * data share), MCC_ERR_OOM, MCC_ERR_DEVICE.  On success *out owns the tables. */
 mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out);
 
+/* Choices the mechanism compiler otherwise makes itself.  dense_tail: the
+ * number of trailing pivots of the solver's LU factorised as a dense block
+ * in registers, one of 0, 32, 48, 64 (at most n_species), or -1 for the
+ * compiler's cost model.  Results are the same mathematics either way; the
+ * rounding order of the LU differs.  reserved: zero. */
+typedef struct {
+    int32_t dense_tail;
+    int32_t reserved[7];
+} mcc_mech_config;
+
+/* Fill *cfg with the defaults (dense_tail -1). */
+mcc_status mcc_mech_config_default(mcc_mech_config *cfg);
+
+/* mcc_mech_create with a configuration (NULL = defaults); an invalid choice
+ * gives MCC_ERR_INVALID_ARG.  Used by the solver autotuner, which times the
+ * dense-tail sizes on a sample of cells. */
+mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_mech_config *cfg, mcc_mech **out);
+
 /* Sizes of a compiled mechanism (any output pointer may be NULL):
  * species, reactions, Jacobian nonzeros (diagonal included), LU nonzeros
  * after fill, and the dynamic local-data-share bytes one cell of the solver

@@ -132,16 +132,34 @@ mcc_status mcc_solver_opts_default(mcc_solver_opts *o)
     return ok();
 }
 
+mcc_status mcc_mech_config_default(mcc_mech_config *cfg)
+{
+    if (!cfg) return set_error(MCC_ERR_INVALID_ARG, "cfg is null");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->dense_tail = -1;
+    return ok();
+}
+
 mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out)
+{
+    return mcc_mech_create_ex(desc, device, nullptr, out);
+}
+
+mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_mech_config *cfg, mcc_mech **out)
 {
     if (!desc || !out) return set_error(MCC_ERR_INVALID_ARG, "desc and out must not be null");
     *out = nullptr;
     if (device < -1) return set_error(MCC_ERR_INVALID_ARG, "device index out of range");
+    mcc_mech_config c;
+    if (cfg)
+        c = *cfg;
+    else
+        mcc_mech_config_default(&c);
 
     mcc_mech *m = new (std::nothrow) mcc_mech;
     if (!m) return set_error(MCC_ERR_OOM, "host allocation failed");
     std::string err;
-    mcc_status st = compile_mechanism(desc, &m->t, &err);
+    mcc_status st = compile_mechanism(desc, c.dense_tail, &m->t, &err);
     if (st != MCC_OK) {
         delete m;
         return set_error(st, err);

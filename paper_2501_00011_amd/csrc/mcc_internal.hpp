@@ -125,7 +125,7 @@ struct HostTables {
 };
 
 // Validates desc and fills t.  Returns MCC_OK or MCC_ERR_MECH with *err set.
-mcc_status compile_mechanism(const mcc_mech_desc *desc, HostTables *t, std::string *err);
+mcc_status compile_mechanism(const mcc_mech_desc *desc, int dense_tail, HostTables *t, std::string *err);
 
 // Host emulation of the solver's table-driven phases (testing aid).
 int emulate_cell(const HostTables &t, const double *k, const double *y_species, double c,

@@ -164,7 +164,7 @@ int emit_blocks(std::vector<std::vector<T>> &lanes, const T &pad, std::vector<T>
 
 }  // namespace
 
-mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string *err)
+mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables *t, std::string *err)
 {
     if (!validate(d, err)) return MCC_ERR_MECH;
     const int N = d->n_species, R = d->n_reactions;
@@ -423,7 +423,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
     // first F = N - M pivots by the level-scheduled sparse op streams.  M is
     // chosen from {0, 32, 48, 64} by a cost model (cycles of one wavefront:
     // ~1000 per sparse block, ~8 per dense (pivot, column) pair) with the LDS
-    // the tail adds priced in; MCC_DENSE_TAIL overrides the choice.
+    // the tail adds priced in; a caller's configuration overrides the choice.
     auto tail_density = [&](int m) {
         double nzc = 0;
         for (int i = N - m; i < N; ++i)
@@ -457,9 +457,12 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, HostTables *t, std::string 
                 M = m;
             }
         }
-        if (const char *env = std::getenv("MCC_DENSE_TAIL")) {
-            const int m = std::atoi(env);
-            if ((m == 0 || m == 32 || m == 48 || m == 64) && m <= N) M = m;
+        if (dense_tail >= 0) {  // the caller's choice (e.g. an autotuner's)
+            if (!(dense_tail == 0 || dense_tail == 32 || dense_tail == 48 || dense_tail == 64) || dense_tail > N) {
+                *err = "dense_tail must be -1, 0, 32, 48 or 64, and at most the number of species";
+                return MCC_ERR_INVALID_ARG;
+            }
+            M = dense_tail;
         }
     }
     const int F = N - M;

@@ -64,6 +64,8 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_version": ([], ctypes.c_char_p),
         "mcc_solver_opts_default": ([vp], ctypes.c_int),
         "mcc_mech_create": ([vp, ctypes.c_int, vp], ctypes.c_int),
+        "mcc_mech_create_ex": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
+        "mcc_mech_config_default": ([vp], ctypes.c_int),
         "mcc_mech_info": ([vp, pi32, pi32, pi32, pi32, pi32], ctypes.c_int),
         "mcc_mech_jac_pattern": ([vp, vp, vp], ctypes.c_int),
         "mcc_mech_op_counts": ([vp, vp], ctypes.c_int),
@@ -134,7 +136,7 @@ def _dptr(t, what, dtype=None, shape=None):
 class Mechanism:
     """A compiled mechanism resident on one GPU (mcc_mech_create)."""
 
-    def __init__(self, mech, device: int = 0):
+    def __init__(self, mech, device: int = 0, dense_tail: int = -1):
         L = library()
         self.source = mech
         arrays = [np.ascontiguousarray(a, dtype=dt) for a, dt in (
@@ -143,7 +145,10 @@ class Mechanism:
             (mech.A, np.float64), (mech.theta, np.float64))]
         desc = _MechDesc(int(mech.n_species), int(mech.n_reactions), *[a.ctypes.data for a in arrays])
         h = ctypes.c_void_p()
-        _check(L.mcc_mech_create(ctypes.addressof(desc), int(device), ctypes.byref(h)))
+        cfg = (ctypes.c_int32 * 8)()
+        _check(L.mcc_mech_config_default(ctypes.addressof(cfg)))
+        cfg[0] = int(dense_tail)
+        _check(L.mcc_mech_create_ex(ctypes.addressof(desc), int(device), ctypes.addressof(cfg), ctypes.byref(h)))
         self._h = h
         self.device = int(device)
         n, r, nnz, lu, lds = (ctypes.c_int32() for _ in range(5))
@@ -400,3 +405,50 @@ def _hip_runtime():
 def _check_hip(e):
     if e != 0:
         raise MccError(f"hipMemcpy failed with {e}")
+
+
+def autotune_solver(mech, cells, dt: float, opts: SolverOpts | None = None, device: int = 0,
+                    candidates=(0, 32, 48, 64), reps: int = 2):
+    """Pick the solver's dense-tail size for `mech` by measurement: every
+    candidate the mechanism admits is compiled, and one outer step of the
+    sample `cells` (a synth.Cells; a few thousand cells fill the device) is
+    timed with HIP events, best of `reps` after one warm-up.  Returns
+    (Mechanism compiled with the fastest choice, {choice: ms})."""
+    import torch
+    dev = torch.device(f"cuda:{device}")
+    T = torch.from_numpy(np.ascontiguousarray(cells.T)).to(dev)
+    P = torch.from_numpy(np.ascontiguousarray(cells.P)).to(dev)
+    s = torch.from_numpy(np.ascontiguousarray(cells.jscale)).to(dev)
+    y0 = torch.from_numpy(np.ascontiguousarray(cells.y0)).to(dev)
+    times, best = {}, None
+    for m_tail in candidates:
+        if m_tail > mech.n_species:
+            continue
+        try:
+            h = Mechanism(mech, device=device, dense_tail=m_tail)
+        except MccError:
+            continue  # this choice does not fit the solver's register slots or LDS
+        c = Cells(h, cells.n_cells)
+        c.bind(T, P, s)
+        y = torch.empty_like(y0)
+        ts = []
+        for r in range(reps + 1):
+            y.copy_(y0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            c.step(y, dt, opts, want_stats=False)
+            b.record()
+            torch.cuda.synchronize()
+            if r > 0:
+                ts.append(a.elapsed_time(b))
+        times[m_tail] = min(ts)
+        c.close()
+        if best is None or times[m_tail] < times[best[0]]:
+            if best is not None:
+                best[1].close()
+            best = (m_tail, h)
+        else:
+            h.close()
+    if best is None:
+        raise MccError("no dense-tail choice compiles for this mechanism")
+    return best[1], times

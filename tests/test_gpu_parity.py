@@ -577,3 +577,23 @@ def test_paper_deriv_kernel(dev, oracle_mod, inverted):
     torch.cuda.synchronize()
     f_ref, fs = o.deriv(k, c.y0)
     assert np.all(np.abs(f.cpu().numpy().T - f_ref) <= 1e-12 * fs)
+
+
+def test_autotune_solver(dev, oracle_mod):
+    """The autotuner times the admissible dense-tail sizes and returns the
+    fastest; the tuned mechanism meets the solver's parity bar."""
+    m, c, dt = synth.workload("medium10k", 600)
+    h, times = mcchem.autotune_solver(m, c, dt, reps=1)
+    assert set(times) == {0, 32, 48, 64} and all(t > 0 for t in times.values())
+    best = min(times, key=times.get)
+    assert h.schedule_info()["dense_tail"] == best
+    sub = synth.Cells(T=c.T[:40], P=c.P[:40], jscale=c.jscale[:40], y0=c.y0[:, :40])
+    b = Batch.__new__(Batch)
+    b.m, b.c, b.C, b.ld, b.dev, b.h = m, sub, 40, 40, dev, h
+    b.cells = mcchem.Cells(h, 40)
+    b.T, b.P, b.s = _t(sub.T, dev), _t(sub.P, dev), _t(sub.jscale, dev)
+    b.cells.bind(b.T, b.P, b.s)
+    b.o = oracle_mod.Oracle(m)
+    yg, sg, _, yo, so, _ = _solve_parity(b, dt)
+    assert np.all(sg == 0) and np.all(so == 0)
+    assert _within(yg, yo, 1.0) <= 1.0

@@ -123,3 +123,23 @@ def test_fj_kernel_kind_validation():
     h.set_fj_kernel(mcchem.Mechanism.FJ_GENERATED)
     with pytest.raises(mcchem.MccError):
         h.set_fj_kernel(7)
+
+
+def test_dense_tail_configuration():
+    """The caller may fix the dense-tail size; every admissible choice gives
+    tables that solve the Newton system correctly; invalid choices fail."""
+    m = synth.mech_medium()
+    for M in (0, 32, 48, 64):
+        h = mcchem.Mechanism(m, device=-1, dense_tail=M)
+        assert h.schedule_info()["dense_tail"] == M
+        rng = np.random.default_rng(M)
+        y = synth.make_cells(m, 1, seed=9).y0[:, 0]
+        k = rng.uniform(1e-3, 1.0, m.n_reactions)
+        b = rng.normal(size=m.n_species)
+        f, x, viol = h.emulate_cell(k, y, 1e-3, b)
+        assert viol == 0 and np.all(np.isfinite(x))
+    for bad in (16, 200):
+        with pytest.raises(mcchem.MccError, match="status 1"):
+            mcchem.Mechanism(m, device=-1, dense_tail=bad)
+    with pytest.raises(mcchem.MccError):
+        mcchem.Mechanism(synth.mech_small(), device=-1, dense_tail=32)
