@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -34,7 +36,7 @@ struct mcc_mech {
     int fj_kind = MCC_FJ_GENERATED;
     std::string arch;
     hipModule_t fj_mod = nullptr;
-    hipFunction_t fj_fn = nullptr, vjp_fn = nullptr;
+    hipFunction_t fj_fn = nullptr, fj2_fn = nullptr, vjp_fn = nullptr, vjp2_fn = nullptr;
 };
 
 struct mcc_cells {
@@ -334,8 +336,7 @@ mcc_status mcc_mech_destroy(mcc_mech *m)
         hipError_t e = hipModuleUnload(m->fj_mod);
         if (e != hipSuccess) return hip_error(e, "hipModuleUnload");
         m->fj_mod = nullptr;
-        m->fj_fn = nullptr;
-        m->vjp_fn = nullptr;
+        m->fj_fn = m->fj2_fn = m->vjp_fn = m->vjp2_fn = nullptr;
     }
     if (m->dev_buf) {
         hipError_t e = hipFree(m->dev_buf);
@@ -356,7 +357,7 @@ mcc_status mcc_mech_set_fj_kernel(mcc_mech *m, int32_t kind)
 mcc_status mcc_debug_fj_source(const mcc_mech *m, char *buf, int64_t cap, int64_t *len)
 {
     if (!m || !len || (cap > 0 && !buf) || cap < 0) return set_error(MCC_ERR_INVALID_ARG, "bad argument");
-    const std::string src = generate_fj_source(m->t) + generate_vjp_source(m->t);
+    const std::string src = generate_module_source(m->t);
     *len = (int64_t)src.size();
     if (cap > 0) {
         const size_t n = std::min((size_t)cap, src.size() + 1);
@@ -370,7 +371,7 @@ mcc_status mcc_debug_compile_fj(const mcc_mech *m, const char *arch, int64_t *co
     if (!m || !arch || !code_bytes) return set_error(MCC_ERR_INVALID_ARG, "null argument");
     std::vector<char> code;
     std::string log;
-    if (!compile_fj_source(generate_fj_source(m->t) + generate_vjp_source(m->t), arch, &code, &log))
+    if (!compile_fj_source(generate_module_source(m->t), arch, &code, &log))
         return set_error(MCC_ERR_DEVICE, "generated f/J kernel does not compile: " + log);
     *code_bytes = (int64_t)code.size();
     return ok();
@@ -444,26 +445,85 @@ mcc_status mcc_cells_rate_constants(const mcc_cells *c, const double **k)
     return ok();
 }
 
+static bool aligned16(const void *p) { return p == nullptr || ((uintptr_t)p & 15) == 0; }
+
+// Launches a generated kernel over cells [0, n_cells): the two-cell variant
+// (fn2) over whole pairs when ld is even and every array is 16-byte aligned,
+// the one-cell variant (fn) over the rest.  arrays: the kernel's pointer
+// arguments in order (null allowed for an unused output).
+static mcc_status launch_generated(hipFunction_t fn, hipFunction_t fn2, std::vector<const void *> arrays,
+                                   int64_t n_cells, int64_t ld, int item_begin, int n_items, void *stream)
+{
+    if (n_items == 0 || n_cells == 0) return ok();
+    bool pair = ld % 2 == 0;
+    for (const void *a : arrays) pair = pair && aligned16(a);
+    const int64_t n_pair_cells = pair ? n_cells / 2 * 2 : 0;
+    auto go = [&](hipFunction_t f, int64_t lanes, int64_t c_begin, int64_t n_end) -> mcc_status {
+        const int64_t n_tiles = (lanes + 63) / 64;
+        const int64_t blocks = (n_tiles + 7) / 8 * 8 * n_items;
+        if (lanes <= 0) return ok();
+        if (blocks > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "too many cells for one launch");
+        std::vector<void *> args;
+        for (const void *&a : arrays) args.push_back((void *)&a);
+        long long nc = n_end, ldl = ld, cb = c_begin;
+        int ib = item_begin, ni = n_items, nt = (int)n_tiles;
+        for (void *a : {(void *)&nc, (void *)&ldl, (void *)&cb, (void *)&ib, (void *)&ni, (void *)&nt}) args.push_back(a);
+        hipError_t e = hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream, args.data(),
+                                             nullptr);
+        if (e != hipSuccess) return hip_error(e, "generated kernel launch");
+        return ok();
+    };
+    mcc_status st = go(fn2, n_pair_cells / 2, 0, n_pair_cells);
+    if (st != MCC_OK) return st;
+    return go(fn, n_cells - n_pair_cells, n_pair_cells, n_cells);
+}
+
+// Code objects of generated kernels, compiled once per process for each
+// (architecture, source): mechanisms created again reuse them (a compile
+// takes seconds; loading a module, microseconds).
+static bool cached_code(const std::string &src, const std::string &arch, const std::vector<char> **code,
+                        std::string *log)
+{
+    static std::mutex mu;
+    static std::map<std::string, std::vector<char>> cache;
+    const std::string key = arch + '\n' + src;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *code = &it->second;
+            return true;
+        }
+    }
+    std::vector<char> obj;
+    if (!compile_fj_source(src, arch, &obj, log)) return false;
+    std::lock_guard<std::mutex> g(mu);
+    auto ins = cache.emplace(key, std::move(obj));  // map nodes never move: the pointer stays valid
+    *code = &ins.first->second;
+    return true;
+}
+
 // Generates, compiles (hipRTC) and loads the mechanism's f/J kernel once.
 static mcc_status ensure_fj_module(mcc_mech *m)
 {
     if (m->fj_fn) return ok();
-    std::vector<char> code;
+    const std::vector<char> *code = nullptr;
     std::string log;
-    if (!compile_fj_source(generate_fj_source(m->t) + generate_vjp_source(m->t), m->arch, &code, &log))
+    if (!cached_code(generate_module_source(m->t), m->arch, &code, &log))
         return set_error(MCC_ERR_DEVICE, "generated f/J kernel does not compile: " + log);
-    hipError_t e = hipModuleLoadData(&m->fj_mod, code.data());
+    hipError_t e = hipModuleLoadData(&m->fj_mod, code->data());
     if (e != hipSuccess) {
         m->fj_mod = nullptr;
         return hip_error(e, "hipModuleLoadData (generated f/J kernel)");
     }
     e = hipModuleGetFunction(&m->fj_fn, m->fj_mod, "mcc_fj_generated");
+    if (e == hipSuccess) e = hipModuleGetFunction(&m->fj2_fn, m->fj_mod, "mcc_fj_generated2");
     if (e == hipSuccess) e = hipModuleGetFunction(&m->vjp_fn, m->fj_mod, "mcc_vjp_generated");
+    if (e == hipSuccess) e = hipModuleGetFunction(&m->vjp2_fn, m->fj_mod, "mcc_vjp_generated2");
     if (e != hipSuccess) {
         (void)hipModuleUnload(m->fj_mod);
         m->fj_mod = nullptr;
-        m->fj_fn = nullptr;
-        m->vjp_fn = nullptr;
+        m->fj_fn = m->fj2_fn = m->vjp_fn = m->vjp2_fn = nullptr;
         return hip_error(e, "hipModuleGetFunction (generated f/J kernel)");
     }
     return ok();
@@ -508,16 +568,8 @@ static mcc_status run_fj(const mcc_cells *c, const double *y, double *f, double 
     }
     mcc_status st = ensure_fj_module(c->mech);
     if (st != MCC_OK) return st;
-    const int64_t blocks = (int64_t)((p.n_tiles + 7) / 8) * 8 * p.n_items;
-    if (p.n_items == 0) return ok();
-    if (blocks > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "too many cells for one f/J launch");
-    long long n_cells = p.n_cells, ld = p.ld;
-    int item_begin = p.item_begin, n_items = p.n_items, n_tiles = p.n_tiles;
-    void *args[] = {&p.y, &p.k, &p.f, &p.jac, &n_cells, &ld, &item_begin, &n_items, &n_tiles};
-    hipError_t e = hipModuleLaunchKernel(c->mech->fj_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
-                                         args, nullptr);
-    if (e != hipSuccess) return hip_error(e, "generated f/J kernel launch");
-    return ok();
+    return launch_generated(c->mech->fj_fn, c->mech->fj2_fn, {p.y, p.k, p.f, p.jac}, p.n_cells, p.ld, p.item_begin,
+                            p.n_items, stream);
 }
 
 mcc_status mcc_calc_vjp(const mcc_cells *c, const double *y, const double *v, double *gy, double *glnk,
@@ -533,19 +585,10 @@ mcc_status mcc_calc_vjp(const mcc_cells *c, const double *y, const double *v, do
     mcc_status st = ensure_fj_module(c->mech);
     if (st != MCC_OK) return st;
     const int n_ritems = (t.R + kVjpRxnGroup - 1) / kVjpRxnGroup;
-    int item_begin = gy ? 0 : t.n_jitems;
-    int n_items = (gy ? t.n_jitems : 0) + (glnk ? n_ritems : 0);
-    int n_tiles = (int)((c->n_cells + 63) / 64);
-    const int64_t blocks = (int64_t)((n_tiles + 7) / 8) * 8 * n_items;
-    if (n_items == 0) return ok();
-    if (blocks > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "too many cells for one launch");
-    const double *k = c->k;
-    long long n_cells = c->n_cells, ld = c->ld;
-    void *args[] = {&y, &k, &v, &gy, &glnk, &n_cells, &ld, &item_begin, &n_items, &n_tiles};
-    hipError_t e = hipModuleLaunchKernel(c->mech->vjp_fn, (unsigned)blocks, 1, 1, 64, 1, 1, 0, (hipStream_t)stream,
-                                         args, nullptr);
-    if (e != hipSuccess) return hip_error(e, "generated VJP kernel launch");
-    return ok();
+    const int item_begin = gy ? 0 : t.n_jitems;
+    const int n_items = (gy ? t.n_jitems : 0) + (glnk ? n_ritems : 0);
+    return launch_generated(c->mech->vjp_fn, c->mech->vjp2_fn, {y, c->k, v, gy, glnk}, c->n_cells, c->ld, item_begin,
+                            n_items, stream);
 }
 
 mcc_status mcc_ablation_paper_deriv(const mcc_mech *m, int64_t n_cells, const double *y, const double *k,

@@ -32,25 +32,73 @@ std::string lit(double v)
 
 }  // namespace
 
-std::string generate_fj_source(const HostTables &t)
+// Token placeholders of the generated bodies, filled per variant: @V@ the
+// per-cell value type (double, or the two-cell pair d2), @L@ the row stride
+// in values (ld, or ld / 2), @Z@ a zero value.
+namespace {
+
+std::string fill(std::string s, bool pair)
 {
-    const int N = t.N;
+    const std::pair<const char *, const char *> rep[] = {
+        {"@V@", pair ? "d2" : "double"}, {"@L@", pair ? "ldv" : "ld"}, {"@Z@", pair ? "d2{0.0, 0.0}" : "0.0"}};
+    for (const auto &r : rep)
+        for (size_t at = s.find(r.first); at != std::string::npos; at = s.find(r.first, at)) s.replace(at, 3, r.second);
+    return s;
+}
+
+// Kernel head: block -> (64-lane tile, work item), the tiles of one XCD
+// together.  One-cell variant: lane = cell c_begin + tile * 64 + lane.  Pair
+// variant: lane = cells 2c and 2c + 1 with c = tile * 64 + lane, 16-byte
+// accesses (the caller guarantees an even ld, 16-byte aligned arrays and
+// whole pairs: n_cells even).
+std::string head(const char *name, const char *args, const char *ptrs, bool pair)
+{
     std::ostringstream o;
-    o << "// generated f/J kernel: " << N << " species, " << t.R << " reactions, " << t.nnz << " Jacobian nonzeros\n"
-      << "extern \"C\" __global__ __launch_bounds__(64) void mcc_fj_generated(\n"
-      << "    const double *__restrict__ y, const double *__restrict__ k, double *__restrict__ f,\n"
-      << "    double *__restrict__ jac, long long n_cells, long long ld, int item_begin, int n_items, int n_tiles)\n"
+    o << "extern \"C\" __global__ __launch_bounds__(64) void " << name << (pair ? "2" : "") << "(\n" << args
+      << ", long long n_cells, long long ld, long long c_begin, int item_begin, int n_items, int n_tiles)\n"
       << "{\n"
       << "    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;\n"
       << "    const int item = item_begin + q % n_items, tile = (q / n_items) * 8 + xcd;\n"
-      << "    if (tile >= n_tiles) return;\n"
-      << "    const long long c = (long long)tile * 64 + threadIdx.x;\n"
-      << "    if (c >= n_cells) return;\n"
-      << "    const double *__restrict__ Y = y + c;\n"
-      << "    const double *__restrict__ K = k + c;\n"
-      << "    double *__restrict__ F = f + c;\n"
-      << "    double *__restrict__ G = jac + c;\n"
+      << "    if (tile >= n_tiles) return;\n";
+    if (pair)
+        o << "    const long long c = (long long)tile * 64 + threadIdx.x;  // pair index\n"
+          << "    if (2 * c + 1 >= n_cells) return;\n"
+          << "    const long long ldv = ld >> 1;\n"
+          << "    (void)c_begin;\n";
+    else
+        o << "    const long long c = c_begin + (long long)tile * 64 + threadIdx.x;\n"
+          << "    if (c >= n_cells) return;\n";
+    o << ptrs;
+    return o.str();
+}
+
+}  // namespace
+
+std::string generate_preamble()
+{
+    return "// generated per mechanism; d2 = the values of two adjacent cells\n"
+           "struct __attribute__((aligned(16))) d2 { double x, y; };\n"
+           "__device__ __forceinline__ d2 operator+(d2 a, d2 b) { return d2{a.x + b.x, a.y + b.y}; }\n"
+           "__device__ __forceinline__ d2 operator*(d2 a, d2 b) { return d2{a.x * b.x, a.y * b.y}; }\n"
+           "__device__ __forceinline__ d2 operator*(double s, d2 b) { return d2{s * b.x, s * b.y}; }\n"
+           "__device__ __forceinline__ d2 &operator+=(d2 &a, d2 b) { a.x += b.x; a.y += b.y; return a; }\n";
+}
+
+std::string generate_fj_source(const HostTables &t, bool pair)
+{
+    const int N = t.N;
+    std::ostringstream o;
+    o << "// f/J kernel: " << N << " species, " << t.R << " reactions, " << t.nnz << " Jacobian nonzeros\n"
+      << head("mcc_fj_generated",
+              "    const double *__restrict__ y, const double *__restrict__ k, double *__restrict__ f,\n"
+              "    double *__restrict__ jac",
+              "    const @V@ *__restrict__ Y = (const @V@ *)y + c;\n"
+              "    const @V@ *__restrict__ K = (const @V@ *)k + c;\n"
+              "    @V@ *__restrict__ F = (@V@ *)f + c;\n"
+              "    @V@ *__restrict__ G = (@V@ *)jac + c;\n",
+              pair)
       << "    switch (item) {\n";
+
     const int n_items = t.n_fitems + t.n_jitems;
     for (int it = 0; it < n_items; ++it) {
         o << "    case " << it << ": {\n";
@@ -65,8 +113,8 @@ std::string generate_fj_source(const HostTables &t)
                     if (f3 >= 0) ys.insert(f3);
             }
         }
-        for (int j : ks) o << "        const double k" << j << " = K[" << j << " * ld];\n";
-        for (int r : ys) o << "        const double y" << r << " = Y[" << r << " * ld];\n";
+        for (int j : ks) o << "        const @V@ k" << j << " = K[" << j << " * @L@];\n";
+        for (int r : ys) o << "        const @V@ y" << r << " = Y[" << r << " * @L@];\n";
         for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
             const FjChunk &ch = t.fj_chunks[ci];
             o << "        {\n";
@@ -79,9 +127,9 @@ std::string generate_fj_source(const HostTables &t)
                 for (int f3 : {m.a, m.b, m.c})
                     if (f3 >= 0) e += (e.empty() ? "" : " * ") + ("y" + std::to_string(f3));
                 mono[qm] = "m" + std::to_string(qm);
-                o << "            const double " << mono[qm] << " = " << e << ";\n";
+                o << "            const @V@ " << mono[qm] << " = " << e << ";\n";
             }
-            o << "            double acc = 0.0;\n";
+            o << "            @V@ acc = @Z@;\n";
             for (int r = 0; r < ch.n_rec; ++r) {
                 const FjRec &rec = t.fj_recs[ch.rec_begin + r];
                 const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
@@ -91,14 +139,14 @@ std::string generate_fj_source(const HostTables &t)
                     if (slot >= kFjQmax || rec.coef[qq] == 0.0 || mono[slot].empty()) continue;
                     sum += (sum.empty() ? "" : " + ") + lit(rec.coef[qq]) + " * " + mono[slot];
                 }
-                if (sum.empty()) sum = "0.0";
+                if (sum.empty()) sum = "@Z@";
                 if (!(flags & (kFjKeep | kFjStore))) {
-                    if (sum == "0.0") continue;  // padding record
+                    if (sum == "@Z@") continue;  // padding record
                 }
                 o << "            acc " << ((flags & kFjKeep) ? "+=" : "=") << " " << sum << ";\n";
                 if (flags & kFjStore) {
-                    const std::string dst = row < (uint32_t)N ? "F[" + std::to_string(row) + " * ld]"
-                                                              : "G[" + std::to_string(row - N) + " * ld]";
+                    const std::string dst = row < (uint32_t)N ? "F[" + std::to_string(row) + " * @L@]"
+                                                              : "G[" + std::to_string(row - N) + " * @L@]";
                     o << "            " << dst << ((flags & kFjAdd) ? " += acc;\n" : " = acc;\n");
                 }
             }
@@ -107,7 +155,7 @@ std::string generate_fj_source(const HostTables &t)
         o << "    } break;\n";
     }
     o << "    default: break;\n    }\n}\n";
-    return o.str();
+    return fill(o.str(), pair);
 }
 
 }  // namespace mcc
@@ -121,7 +169,7 @@ namespace mcc {
 // spans two items).  Items n_jitems .. are groups of kVjpRxnGroup reactions:
 // glnk_j = r_j * sum_i nu_ij v_i, the derivative of v.f with respect to
 // ln k_j (f is linear in each k_j).
-std::string generate_vjp_source(const HostTables &t)
+std::string generate_vjp_source(const HostTables &t, bool pair)
 {
     const int N = t.N, R = t.R;
     std::vector<int> entry_row(t.nnz), entry_col(t.nnz);
@@ -131,22 +179,17 @@ std::string generate_vjp_source(const HostTables &t)
             entry_col[e] = t.col_idx[e];
         }
     std::ostringstream o;
-    o << "extern \"C\" __global__ __launch_bounds__(64) void mcc_vjp_generated(\n"
-      << "    const double *__restrict__ y, const double *__restrict__ k, const double *__restrict__ v,\n"
-      << "    double *__restrict__ gy, double *__restrict__ glnk, long long n_cells, long long ld, int item_begin,\n"
-      << "    int n_items, int n_tiles)\n"
-      << "{\n"
-      << "    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;\n"
-      << "    const int item = item_begin + q % n_items, tile = (q / n_items) * 8 + xcd;\n"
-      << "    if (tile >= n_tiles) return;\n"
-      << "    const long long c = (long long)tile * 64 + threadIdx.x;\n"
-      << "    if (c >= n_cells) return;\n"
-      << "    const double *__restrict__ Y = y + c;\n"
-      << "    const double *__restrict__ K = k + c;\n"
-      << "    const double *__restrict__ V = v + c;\n"
-      << "    double *__restrict__ GY = gy + c;\n"
-      << "    double *__restrict__ GK = glnk + c;\n"
+    o << head("mcc_vjp_generated",
+              "    const double *__restrict__ y, const double *__restrict__ k, const double *__restrict__ v,\n"
+              "    double *__restrict__ gy, double *__restrict__ glnk",
+              "    const @V@ *__restrict__ Y = (const @V@ *)y + c;\n"
+              "    const @V@ *__restrict__ K = (const @V@ *)k + c;\n"
+              "    const @V@ *__restrict__ V = (const @V@ *)v + c;\n"
+              "    @V@ *__restrict__ GY = (@V@ *)gy + c;\n"
+              "    @V@ *__restrict__ GK = (@V@ *)glnk + c;\n",
+              pair)
       << "    switch (item) {\n";
+
     int case_no = 0;
     for (int it = t.n_fitems; it < t.n_fitems + t.n_jitems; ++it, ++case_no) {
         o << "    case " << case_no << ": {\n";
@@ -168,10 +211,10 @@ std::string generate_vjp_source(const HostTables &t)
                 }
             }
         }
-        for (int j : ks) o << "        const double k" << j << " = K[" << j << " * ld];\n";
-        for (int r : ys) o << "        const double y" << r << " = Y[" << r << " * ld];\n";
-        for (int r : vs) o << "        const double v" << r << " = V[" << r << " * ld];\n";
-        for (int sc : cols) o << "        double g" << sc << " = 0.0;\n";
+        for (int j : ks) o << "        const @V@ k" << j << " = K[" << j << " * @L@];\n";
+        for (int r : ys) o << "        const @V@ y" << r << " = Y[" << r << " * @L@];\n";
+        for (int r : vs) o << "        const @V@ v" << r << " = V[" << r << " * @L@];\n";
+        for (int sc : cols) o << "        @V@ g" << sc << " = @Z@;\n";
         for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
             const FjChunk &ch = t.fj_chunks[ci];
             o << "        {\n";
@@ -184,9 +227,9 @@ std::string generate_vjp_source(const HostTables &t)
                 for (int f3 : {m.a, m.b, m.c})
                     if (f3 >= 0) e += (e.empty() ? "" : " * ") + ("y" + std::to_string(f3));
                 mono[qm] = "m" + std::to_string(qm);
-                o << "            const double " << mono[qm] << " = " << e << ";\n";
+                o << "            const @V@ " << mono[qm] << " = " << e << ";\n";
             }
-            o << "            double acc = 0.0;\n";
+            o << "            @V@ acc = @Z@;\n";
             for (int r = 0; r < ch.n_rec; ++r) {
                 const FjRec &rec = t.fj_recs[ch.rec_begin + r];
                 const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
@@ -196,8 +239,8 @@ std::string generate_vjp_source(const HostTables &t)
                     if (slot >= kFjQmax || rec.coef[qq] == 0.0 || mono[slot].empty()) continue;
                     sum += (sum.empty() ? "" : " + ") + lit(rec.coef[qq]) + " * " + mono[slot];
                 }
-                if (sum.empty()) sum = "0.0";
-                if (!(flags & (kFjKeep | kFjStore)) && sum == "0.0") continue;
+                if (sum.empty()) sum = "@Z@";
+                if (!(flags & (kFjKeep | kFjStore)) && sum == "@Z@") continue;
                 o << "            acc " << ((flags & kFjKeep) ? "+=" : "=") << " " << sum << ";\n";
                 if ((flags & kFjStore) && row >= (uint32_t)N) {
                     const int e = (int)row - N;
@@ -206,7 +249,7 @@ std::string generate_vjp_source(const HostTables &t)
             }
             o << "            (void)acc;\n        }\n";
         }
-        for (int sc : cols) o << "        GY[" << sc << " * ld] = g" << sc << ";\n";
+        for (int sc : cols) o << "        GY[" << sc << " * @L@] = g" << sc << ";\n";
         o << "    } break;\n";
     }
     for (int j0 = 0; j0 < R; j0 += kVjpRxnGroup, ++case_no) {
@@ -218,22 +261,28 @@ std::string generate_vjp_source(const HostTables &t)
                 if (t.rx_sp[3 * j + q] >= 0) ys.insert(t.rx_sp[3 * j + q]);
             for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) vs.insert(t.nu_sp[e]);
         }
-        for (int r : ys) o << "        const double y" << r << " = Y[" << r << " * ld];\n";
-        for (int r : vs) o << "        const double v" << r << " = V[" << r << " * ld];\n";
+        for (int r : ys) o << "        const @V@ y" << r << " = Y[" << r << " * @L@];\n";
+        for (int r : vs) o << "        const @V@ v" << r << " = V[" << r << " * @L@];\n";
         for (int j = j0; j < j1; ++j) {
-            std::string rate = "K[" + std::to_string(j) + " * ld]";
+            std::string rate = "K[" + std::to_string(j) + " * @L@]";
             for (int q = 0; q < 3; ++q)
                 if (t.rx_sp[3 * j + q] >= 0) rate += " * y" + std::to_string(t.rx_sp[3 * j + q]);
             std::string w;
             for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e)
                 w += (w.empty() ? "" : " + ") + lit(t.nu_coef[e]) + " * v" + std::to_string(t.nu_sp[e]);
-            if (w.empty()) w = "0.0";
-            o << "        GK[" << j << " * ld] = (" << rate << ") * (" << w << ");\n";
+            if (w.empty()) w = "@Z@";
+            o << "        GK[" << j << " * @L@] = (" << rate << ") * (" << w << ");\n";
         }
         o << "    } break;\n";
     }
     o << "    default: break;\n    }\n}\n";
-    return o.str();
+    return fill(o.str(), pair);
+}
+
+std::string generate_module_source(const HostTables &t)
+{
+    return generate_preamble() + generate_fj_source(t, false) + generate_fj_source(t, true) +
+           generate_vjp_source(t, false) + generate_vjp_source(t, true);
 }
 
 bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log)

@@ -190,9 +190,11 @@ constexpr int kStateScalars = 16;
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_rates(const RatesParams &p, hipStream_t s);
 hipError_t launch_fj(const FJParams &p, hipStream_t s);
-// Mechanism-specialised f/J kernel (same work items, compiled with hipRTC).
-std::string generate_fj_source(const HostTables &t);
-std::string generate_vjp_source(const HostTables &t);
+// Mechanism-specialised f/J and VJP kernels (same work items, compiled with
+// hipRTC), each in a one-cell and a two-cell (16-byte access) variant.
+std::string generate_fj_source(const HostTables &t, bool pair);
+std::string generate_vjp_source(const HostTables &t, bool pair);
+std::string generate_module_source(const HostTables &t);  // preamble + all four
 // Ablation of the paper's Derivative kernel: reaction data as records
 // [reaction][kPaperRec] (n_reac, 3 reactants, n_prod, kPaperProd products)
 // with yields [reaction][kPaperProd], or inverted [parameter][reaction].

@@ -597,3 +597,22 @@ def test_autotune_solver(dev, oracle_mod):
     yg, sg, _, yo, so, _ = _solve_parity(b, dt)
     assert np.all(sg == 0) and np.all(so == 0)
     assert _within(yg, yo, 1.0) <= 1.0
+
+
+@pytest.mark.parametrize("n,ld", [(333, 334), (334, 334), (1, 2)])
+def test_vjp_pair_and_remainder(dev, oracle_mod, n, ld):
+    """Even leading dimension: the two-cell kernel over whole pairs, the
+    one-cell kernel for an odd last cell."""
+    m, c, _ = synth.workload("medium10k", n)
+    b = Batch(dev, m, c, ld=ld, oracle_mod=oracle_mod)
+    v = np.random.default_rng(15).normal(size=c.y0.shape)
+    gy, gk = b.cells.vjp(b.y_dev(), _t(_padded(v, ld), dev))
+    f, J = b.cells.deriv_jac(b.y_dev())
+    torch.cuda.synchronize()
+    k = b.o.rate_constants(c.T, c.jscale)
+    gy_ref, gk_ref = b.o.vjp(k, c.y0, v)
+    _, Js = b.o.jac(k, c.y0)
+    by, bk = _vjp_bounds(m, k, c.y0, v, Js)
+    assert np.all(np.abs(gy.cpu().numpy()[:, :n] - gy_ref) <= 1e-12 * by)
+    assert np.all(np.abs(gk.cpu().numpy()[:, :n] - gk_ref) <= 1e-12 * bk)
+    _check_fj(b, f.cpu().numpy()[:, :n], J.cpu().numpy()[:, :n], c.y0)
