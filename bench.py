@@ -32,7 +32,7 @@ SOLVE_SOURCES = ["paper_2501_00011_amd/csrc/kernels_solve.hip", "paper_2501_0001
                  "paper_2501_00011_amd/csrc/mech_compile.cpp"]
 FJ_SOURCES = ["paper_2501_00011_amd/csrc/fj_codegen.cpp", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
               "paper_2501_00011_amd/csrc/mech_compile.cpp"]
-FJ_KERNEL = "mcc_fj_generated"
+FJ_KERNEL = "mcc_fj_generated2"  # the two-cell variant (even leading dimension)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_medium10k.txt")
 
 
@@ -397,7 +397,7 @@ def main():
                         "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
                         "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
                         "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
-        "vjp_roofline": {"kernel": "mcc_vjp_generated (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
+        "vjp_roofline": {"kernel": "mcc_vjp_generated2 (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
                          "achieved": vj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vj_gbs / HBM_PEAK_GBS,
                          "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes},
         "solver": {"failed_cells": int((st != 0).sum()),
