@@ -64,6 +64,22 @@ def default_opts(rtol=1e-8, atol=1.0, **kw) -> Opts:
     return o
 
 
+class Tape:
+    """An owned step tape of the oracle (freed with the object)."""
+
+    def __init__(self, lib):
+        self.lib = lib
+        self.h = lib.orc_tape_new()
+
+    def __len__(self):
+        return int(self.lib.orc_tape_size(self.h))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.orc_tape_free(self.h)
+            self.h = None
+
+
 class Oracle:
     """ctypes view of liboracle.so bound to one mechanism."""
 
@@ -85,6 +101,15 @@ class Oracle:
         L.orc_jac.argtypes = [vp, i64, vp, vp, vp, vp]
         L.orc_vjp.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.orc_solve_multicell.argtypes = [vp, i64, vp, vp, dbl, vp, vp]
+        L.orc_tape_new.restype = vp
+        L.orc_tape_free.argtypes = [vp]
+        L.orc_tape_size.argtypes = [vp]
+        L.orc_tape_size.restype = i64
+        L.orc_cell_solve_taped.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
+        L.orc_cell_solve_taped.restype = ctypes.c_int
+        L.orc_cell_replay.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_cell_replay.restype = ctypes.c_int
+        L.orc_cell_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
         L.orc_solve_multicell.restype = ctypes.c_int
         L.orc_solve.argtypes = [vp, i64, vp, vp, dbl, vp, vp, vp, ctypes.c_int]
         L.orc_solve.restype = ctypes.c_int
@@ -172,6 +197,41 @@ class Oracle:
         s = self.lib.orc_solve_multicell(self._mp(), C, k.ctypes.data, y.ctypes.data, float(dt),
                                          ctypes.addressof(o), stats.ctypes.data)
         return y, int(s), stats[0]
+
+    # -- reverse mode through one outer step of one cell --------------------
+    def solve_taped(self, k_cell, y0_cell, dt, opts: Opts | None = None):
+        """One outer step of one cell (k [R], y0 [N]) recording its step
+        tape.  Returns (y, status, stats, tape)."""
+        k = np.ascontiguousarray(k_cell, dtype=np.float64)
+        y = np.array(y0_cell, dtype=np.float64, copy=True)
+        st = np.zeros(1, dtype=STATS_DTYPE)
+        tape = Tape(self.lib)
+        o = opts or default_opts()
+        s = self.lib.orc_cell_solve_taped(self._mp(), k.ctypes.data, y.ctypes.data, float(dt), ctypes.addressof(o),
+                                          st.ctypes.data, tape.h)
+        return y, int(s), st[0], tape
+
+    def replay(self, k_cell, y0_cell, tape):
+        """The tape's frozen step sequence run again with these k and y0
+        (implicit steps solved to convergence).  Returns (y, replay tape)."""
+        k = np.ascontiguousarray(k_cell, dtype=np.float64)
+        y0 = np.ascontiguousarray(y0_cell, dtype=np.float64)
+        y = np.empty_like(y0)
+        out = Tape(self.lib)
+        if self.lib.orc_cell_replay(self._mp(), k.ctypes.data, y0.ctypes.data, tape.h, y.ctypes.data, out.h):
+            raise RuntimeError("replay: a Newton matrix is singular")
+        return y, out
+
+    def adjoint(self, k_cell, y0_cell, replay_tape, lam_y):
+        """Discrete adjoint of a replayed tape: (dL/dy0 [N], dL/d ln k [R])
+        for dL/dy(dt) = lam_y."""
+        k = np.ascontiguousarray(k_cell, dtype=np.float64)
+        y0 = np.ascontiguousarray(y0_cell, dtype=np.float64)
+        lam = np.array(lam_y, dtype=np.float64, copy=True)
+        g = np.empty(self.R)
+        self.lib.orc_cell_adjoint(self._mp(), k.ctypes.data, y0.ctypes.data, replay_tape.h, lam.ctypes.data,
+                                  g.ctypes.data)
+        return lam, g
 
     def rescale_differences(self, D, order, rho):
         """Backward differences D [order+1][N] re-sampled at spacing rho*h."""

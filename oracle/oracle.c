@@ -330,11 +330,10 @@ static double bdf_gamma(int j)
  * the values at the new points are R(rho)^T D, the differences of values at
  * unit spacing are obtained with U = R(1) (an involution), so the new
  * differences are (R(rho) U)^T D. */
-static void rescale_differences(int N, double *D, int order, double rho)
+/* RU[j][i]: D'_i = sum_j RU[j][i] D_j (i, j <= order). */
+static void rescale_matrix(int order, double rho, double RU[ORC_MAXORD + 1][ORC_MAXORD + 1])
 {
     double R[ORC_MAXORD + 1][ORC_MAXORD + 1], U[ORC_MAXORD + 1][ORC_MAXORD + 1];
-    double RU[ORC_MAXORD + 1][ORC_MAXORD + 1];
-    double tmp[ORC_MAXORD + 1];
     const int n = order + 1;
     for (int j = 0; j < n; ++j) {
         R[0][j] = 1.0;
@@ -351,6 +350,14 @@ static void rescale_differences(int N, double *D, int order, double rho)
                 s += R[i][l] * U[l][j];
             RU[i][j] = s;
         }
+}
+
+static void rescale_differences(int N, double *D, int order, double rho)
+{
+    double RU[ORC_MAXORD + 1][ORC_MAXORD + 1];
+    double tmp[ORC_MAXORD + 1];
+    const int n = order + 1;
+    rescale_matrix(order, rho, RU);
     for (int s = 0; s < N; ++s) {
         for (int i = 0; i < n; ++i) {
             double acc = 0.0;
@@ -398,10 +405,64 @@ static void work_free(orc_work *wk)
     free(wk->d); free(wk->ycur); free(wk->rhs); free(wk->tmp); free(wk->J); free(wk->piv);
 }
 
+/* Accepting a step of order k with Newton correction d: the new differences
+ * are D_{k+2} = d - D_{k+1}, D_{k+1} = d, then D_j += D_{j+1} for j = k..0. */
+static void accept_differences(int N, double *D, const double *d, int order)
+{
+    for (int i = 0; i < N; ++i) {
+        D[(size_t)(order + 2) * N + i] = d[i] - D[(size_t)(order + 1) * N + i];
+        D[(size_t)(order + 1) * N + i] = d[i];
+    }
+    for (int j = order; j >= 0; --j)
+        for (int i = 0; i < N; ++i)
+            D[(size_t)j * N + i] += D[(size_t)(j + 1) * N + i];
+}
+
+/* ------------------------------------------- the step tape (reverse mode) */
+
+/* The sequence of operations one outer step applied to the backward
+ * differences, recorded so that the same discrete map can be replayed with
+ * other parameters and differentiated in reverse: START (D_0 = y0,
+ * D_1 = h f(y0)), RESCALE (D <- re-sampled at spacing rho * h, orders
+ * 0..order), STEP (an accepted step of the given order with c = h / gamma_k,
+ * followed by N values: the converged state z = the new D_0).  Each entry:
+ * type, order, value, then the payload. */
+enum { TAPE_START = 0, TAPE_RESCALE = 1, TAPE_STEP = 2 };
+typedef struct {
+    double *v;
+    size_t n, cap;
+} orc_tape;
+
+static void tape_push(orc_tape *t, double x)
+{
+    if (t->n == t->cap) {
+        t->cap = t->cap ? 2 * t->cap : 1024;
+        t->v = realloc(t->v, sizeof(double) * t->cap);
+    }
+    t->v[t->n++] = x;
+}
+
+static void tape_op(orc_tape *t, int type, int order, double x, const double *payload, int n)
+{
+    if (!t) return;
+    tape_push(t, type);
+    tape_push(t, order);
+    tape_push(t, x);
+    for (int i = 0; i < n; ++i) tape_push(t, payload[i]);
+}
+
+static void rescale_differences(int N, double *D, int order, double rho);
+
+static void rescale_rec(int N, double *D, int order, double rho, orc_tape *tape)
+{
+    rescale_differences(N, D, order, rho);
+    tape_op(tape, TAPE_RESCALE, order, rho, NULL, 0);
+}
+
 /* Integrate y' = f(y) of one cell from t = 0 to t = dt; y is overwritten
  * with y(dt).  Returns an ORC_* status. */
 static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
-                      const orc_opts *o, orc_stats *st, orc_work *wk)
+                      const orc_opts *o, orc_stats *st, orc_work *wk, orc_tape *tape)
 {
     const int N = m->n_species;
     const int maxord = o->max_order < 1 ? 1 : (o->max_order > ORC_MAXORD ? ORC_MAXORD : o->max_order);
@@ -435,6 +496,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         D[i] = y[i];
         D[(size_t)N + i] = h * wk->f[i];
     }
+    tape_op(tape, TAPE_START, 0, h, NULL, 0);
     int order = 1, n_equal = 0, attempts = 0;
     double t = 0.0;
 
@@ -452,7 +514,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
             landing = 0;
             if (h >= dt - t) {
                 const double hn = dt - t;
-                rescale_differences(N, D, order, hn / h);
+                rescale_rec(N, D, order, hn / h, tape);
                 h = hn;
                 n_equal = 0;
                 landing = 1;
@@ -509,7 +571,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
             }
             if (!converged) {
                 st->newton_fails++;
-                rescale_differences(N, D, order, o->fac_newton_fail);
+                rescale_rec(N, D, order, o->fac_newton_fail, tape);
                 h *= o->fac_newton_fail;
                 n_equal = 0;
                 if (h < o->h_min_rel * dt || t + h == t) {
@@ -525,7 +587,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
                 st->rejects++;
                 double fac = o->safety * pow(err_norm, -1.0 / (order + 1));
                 if (fac < o->fac_min) fac = o->fac_min;
-                rescale_differences(N, D, order, fac);
+                rescale_rec(N, D, order, fac, tape);
                 h *= fac;
                 n_equal = 0;
                 if (h < o->h_min_rel * dt || t + h == t) {
@@ -540,13 +602,8 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         /* accept: t advances, differences are updated */
         t = landing ? dt : t + h;
         st->steps++;
-        for (int i = 0; i < N; ++i) {
-            D[(size_t)(order + 2) * N + i] = wk->d[i] - D[(size_t)(order + 1) * N + i];
-            D[(size_t)(order + 1) * N + i] = wk->d[i];
-        }
-        for (int j = order; j >= 0; --j)
-            for (int i = 0; i < N; ++i)
-                D[(size_t)j * N + i] += D[(size_t)(j + 1) * N + i];
+        accept_differences(N, D, wk->d, order);
+        tape_op(tape, TAPE_STEP, order, h / bdf_gamma(order), D, N);  /* z = the new D_0 */
         n_equal++;
         if (t >= dt)
             break;
@@ -566,7 +623,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         double fac = o->safety * best;
         if (fac > o->fac_max) fac = o->fac_max;
         order = new_order;
-        rescale_differences(N, D, order, fac);
+        rescale_rec(N, D, order, fac, tape);
         h *= fac;
         n_equal = 0;
     }
@@ -604,7 +661,7 @@ int orc_solve(const orc_mech *m, int64_t n_cells, const double *k, double *y, do
             orc_stats st;
             gather_cell(k, R, n_cells, c, kc);
             gather_cell(y, N, n_cells, c, yc);
-            const int s = cell_solve(m, kc, yc, dt, o, &st, &wk);
+            const int s = cell_solve(m, kc, yc, dt, o, &st, &wk, NULL);
             scatter_cell(yc, N, n_cells, c, y);
             status[c] = s;
             if (stats) stats[c] = st;
@@ -614,6 +671,203 @@ int orc_solve(const orc_mech *m, int64_t n_cells, const double *k, double *y, do
         work_free(&wk);
     }
     return failed;
+}
+
+/* ------------------------------------ replay and adjoint of a taped step */
+
+orc_tape *orc_tape_new(void) { return calloc(1, sizeof(orc_tape)); }
+void orc_tape_free(orc_tape *t)
+{
+    if (t) free(t->v);
+    free(t);
+}
+int64_t orc_tape_size(const orc_tape *t) { return (int64_t)t->n; }
+
+/* One outer step of one cell as cell_solve, recording the tape.  kc [R],
+ * y [N] in/out. */
+int orc_cell_solve_taped(const orc_mech *m, const double *kc, double *y, double dt, const orc_opts *o,
+                         orc_stats *st, orc_tape *tape)
+{
+    orc_work wk;
+    work_alloc(&wk, m->n_species);
+    tape->n = 0;
+    const int s = cell_solve(m, kc, y, dt, o, st, &wk, tape);
+    work_free(&wk);
+    return s;
+}
+
+/* Newton matrix M = I - c J(z), factored. */
+static int newton_matrix_at(const orc_mech *m, const double *kc, const double *z, double c, double *J, int *piv)
+{
+    const int N = m->n_species;
+    cell_jac(m, kc, z, J, NULL);
+    for (size_t q = 0; q < (size_t)N * N; ++q) J[q] = -c * J[q];
+    for (int i = 0; i < N; ++i) J[(size_t)i * N + i] += 1.0;
+    return lu_factor(N, J, piv);
+}
+
+/* The taped discrete map with the step sequence frozen: the same operations
+ * on the differences, every implicit step solved again with these kc and y0
+ * by Newton's method with a fresh Jacobian per iteration until the
+ * correction stops changing (at most 50 iterations).  Writes y(dt) and a
+ * copy of the tape whose STEP payloads are the replay's converged states
+ * (the points the adjoint linearises at).  Returns 0, or 1 if a solve fails. */
+int orc_cell_replay(const orc_mech *m, const double *kc, const double *y0, const orc_tape *tape, double *y,
+                    orc_tape *out)
+{
+    const int N = m->n_species;
+    double *D = calloc((size_t)(ORC_MAXORD + 3) * N, sizeof(double));
+    double *ypred = malloc(sizeof(double) * N), *psi = malloc(sizeof(double) * N), *d = malloc(sizeof(double) * N);
+    double *z = malloc(sizeof(double) * N), *f = malloc(sizeof(double) * N), *r = malloc(sizeof(double) * N);
+    double *J = malloc(sizeof(double) * (size_t)N * N);
+    int *piv = malloc(sizeof(int) * N), bad = 0;
+    out->n = 0;
+    size_t p = 0;
+    while (p < tape->n && !bad) {
+        const int type = (int)tape->v[p], order = (int)tape->v[p + 1];
+        const double x = tape->v[p + 2];
+        p += 3;
+        if (type == TAPE_START) {
+            cell_deriv(m, kc, y0, f, NULL);
+            memset(D, 0, sizeof(double) * (size_t)(ORC_MAXORD + 3) * N);
+            for (int i = 0; i < N; ++i) {
+                D[i] = y0[i];
+                D[(size_t)N + i] = x * f[i];
+            }
+            tape_op(out, TAPE_START, 0, x, NULL, 0);
+        } else if (type == TAPE_RESCALE) {
+            rescale_rec(N, D, order, x, out);
+        } else {
+            const int k = order;
+            const double c = x, gk = bdf_gamma(k);
+            for (int i = 0; i < N; ++i) {
+                double yp = 0.0, ps = 0.0;
+                for (int j = 0; j <= k; ++j) yp += D[(size_t)j * N + i];
+                for (int j = 1; j <= k; ++j) ps += bdf_gamma(j) * D[(size_t)j * N + i];
+                ypred[i] = yp;
+                psi[i] = ps / gk;
+                d[i] = tape->v[p + i] - yp;  /* start from the taped state */
+            }
+            p += N;
+            /* Newton on d - c f(ypred + d) + psi = 0 */
+            for (int it = 0; it < 50; ++it) {
+                for (int i = 0; i < N; ++i) z[i] = ypred[i] + d[i];
+                cell_deriv(m, kc, z, f, NULL);
+                for (int i = 0; i < N; ++i) r[i] = c * f[i] - psi[i] - d[i];
+                if (newton_matrix_at(m, kc, z, c, J, piv)) { bad = 1; break; }
+                lu_solve(N, J, piv, r);
+                double nr = 0.0;  /* largest correction relative to its own component */
+                for (int i = 0; i < N; ++i) {
+                    d[i] += r[i];
+                    nr = fmax(nr, fabs(r[i]) / (fabs(ypred[i] + d[i]) + 1e-300));
+                }
+                if (nr <= 1e-15) break;
+            }
+            accept_differences(N, D, d, k);
+            tape_op(out, TAPE_STEP, k, c, D, N);
+        }
+    }
+    for (int i = 0; i < N; ++i) y[i] = D[i];
+    free(D); free(ypred); free(psi); free(d); free(z); free(f); free(r); free(J); free(piv);
+    return bad;
+}
+
+/* lam += c * (d f / d ln k)^T mu at z: lam_j += c r_j(z) sum_i nu_ij mu_i. */
+static void add_lnk_term(const orc_mech *m, const double *kc, const double *z, const double *mu, double c,
+                         double *glnk)
+{
+    for (int j = 0; j < m->n_reactions; ++j) {
+        const double r = reaction_rate(m, j, kc[j], z);
+        double w = 0.0;
+        for (int q = m->reac_ptr[j]; q < m->reac_ptr[j + 1]; ++q) w -= mu[m->reac_idx[q]];
+        for (int q = m->prod_ptr[j]; q < m->prod_ptr[j + 1]; ++q) w += m->prod_yield[q] * mu[m->prod_idx[q]];
+        glnk[j] += c * r * w;
+    }
+}
+
+/* Reverse sweep of a replayed tape (the discrete adjoint of the frozen
+ * step sequence).  lam [N]: in, dL/dy(dt); out, dL/dy0.  glnk [R]: out,
+ * dL/d ln k_j.  Each STEP is linearised at its taped converged state z: the
+ * implicit step d - c f(ypred + d) + psi = 0 gives mu = (I - c J(z))^-T lam_d,
+ * then lam_ypred = c J(z)^T mu, lam_psi = -mu, glnk += c (df/dlnk)^T mu. */
+void orc_cell_adjoint(const orc_mech *m, const double *kc, const double *y0, const orc_tape *tape, double *lam,
+                      double *glnk)
+{
+    const int N = m->n_species, R = m->n_reactions, NW = ORC_MAXORD + 3;
+    double *L = calloc((size_t)NW * N, sizeof(double));
+    double *mu = malloc(sizeof(double) * N), *g = malloc(sizeof(double) * N);
+    double *J = malloc(sizeof(double) * (size_t)N * N), *Jt = malloc(sizeof(double) * (size_t)N * N);
+    int *piv = malloc(sizeof(int) * N);
+    for (int j = 0; j < R; ++j) glnk[j] = 0.0;
+    for (int i = 0; i < N; ++i) L[i] = lam[i];  /* y(dt) = D_0 */
+    /* entry offsets, walked backwards */
+    size_t cap = 64, ne = 0, p = 0;
+    size_t *at = malloc(sizeof(size_t) * cap);
+    while (p < tape->n) {
+        if (ne == cap) at = realloc(at, sizeof(size_t) * (cap *= 2));
+        at[ne++] = p;
+        p += 3 + ((int)tape->v[p] == TAPE_STEP ? (size_t)N : 0);
+    }
+    for (size_t e = ne; e-- > 0;) {
+        const size_t q = at[e];
+        const int type = (int)tape->v[q], order = (int)tape->v[q + 1];
+        const double x = tape->v[q + 2];
+        if (type == TAPE_RESCALE) {
+            double RU[ORC_MAXORD + 1][ORC_MAXORD + 1], tmp[ORC_MAXORD + 1];
+            rescale_matrix(order, x, RU);
+            for (int s = 0; s < N; ++s) {
+                for (int j = 0; j <= order; ++j) {
+                    double acc = 0.0;
+                    for (int i = 0; i <= order; ++i) acc += RU[j][i] * L[(size_t)i * N + s];
+                    tmp[j] = acc;
+                }
+                for (int j = 0; j <= order; ++j) L[(size_t)j * N + s] = tmp[j];
+            }
+        } else if (type == TAPE_START) {
+            /* D_0 = y0, D_1 = h f(y0) */
+            cell_jac(m, kc, y0, J, NULL);
+            for (int s = 0; s < N; ++s) {
+                double acc = 0.0;
+                for (int i = 0; i < N; ++i) acc += J[(size_t)i * N + s] * L[(size_t)N + i];
+                lam[s] = L[s] + x * acc;
+            }
+            add_lnk_term(m, kc, y0, L + N, x, glnk);
+        } else {
+            const int k = order;
+            const double c = x, gk = bdf_gamma(k);
+            const double *z = tape->v + q + 3;
+            /* the difference update, reversed */
+            for (int j = 0; j <= k; ++j)
+                for (int i = 0; i < N; ++i) L[(size_t)(j + 1) * N + i] += L[(size_t)j * N + i];
+            for (int i = 0; i < N; ++i) {
+                mu[i] = L[(size_t)(k + 1) * N + i] + L[(size_t)(k + 2) * N + i];  /* lam_d */
+                L[(size_t)(k + 1) * N + i] = -L[(size_t)(k + 2) * N + i];
+                L[(size_t)(k + 2) * N + i] = 0.0;
+            }
+            /* mu = (I - c J(z))^-T lam_d: solve with the transposed matrix */
+            cell_jac(m, kc, z, Jt, NULL);  /* Jt holds J(z) */
+            {
+                double *Mt = malloc(sizeof(double) * (size_t)N * N);
+                for (int i = 0; i < N; ++i)
+                    for (int j = 0; j < N; ++j) Mt[(size_t)i * N + j] = (i == j ? 1.0 : 0.0) - c * Jt[(size_t)j * N + i];
+                lu_factor(N, Mt, piv);
+                lu_solve(N, Mt, piv, mu);
+                free(Mt);
+            }
+            /* lam_ypred = c J^T mu, lam_psi = -mu */
+            for (int s = 0; s < N; ++s) {
+                double acc = 0.0;
+                for (int i = 0; i < N; ++i) acc += Jt[(size_t)i * N + s] * mu[i];
+                g[s] = c * acc;
+            }
+            add_lnk_term(m, kc, z, mu, c, glnk);
+            for (int j = 0; j <= k; ++j)
+                for (int i = 0; i < N; ++i) L[(size_t)j * N + i] += g[i];
+            for (int j = 1; j <= k; ++j)
+                for (int i = 0; i < N; ++i) L[(size_t)j * N + i] -= bdf_gamma(j) / gk * mu[i];
+        }
+    }
+    free(at); free(L); free(mu); free(g); free(J); free(Jt); free(piv);
 }
 
 /* ----------------------------------------------- Multi-cells (Section 3) */

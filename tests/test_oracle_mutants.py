@@ -36,6 +36,12 @@ MUTANTS = {
                            "for (int i = 0; i < N; ++i) acc += vc[i] * J[(size_t)s * N + i];"),
     "vjp_lnk_reactant_sign": ("for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p) acc -= vc[m->reac_idx[p]] * r;",
                               "for (int p = m->reac_ptr[j]; p < m->reac_ptr[j + 1]; ++p) acc += vc[m->reac_idx[p]] * r;"),
+    "adjoint_cascade_direction": ("for (int i = 0; i < N; ++i) L[(size_t)(j + 1) * N + i] += L[(size_t)j * N + i];",
+                                  "for (int i = 0; i < N; ++i) L[(size_t)j * N + i] += L[(size_t)(j + 1) * N + i];"),
+    "adjoint_psi_sign": ("for (int i = 0; i < N; ++i) L[(size_t)j * N + i] -= bdf_gamma(j) / gk * mu[i];",
+                         "for (int i = 0; i < N; ++i) L[(size_t)j * N + i] += bdf_gamma(j) / gk * mu[i];"),
+    "adjoint_untransposed_solve": ("(i == j ? 1.0 : 0.0) - c * Jt[(size_t)j * N + i];",
+                                   "(i == j ? 1.0 : 0.0) - c * Jt[(size_t)i * N + j];"),
     "error_constant": ("err_norm = wrms(N, wk->d, wk->w) / (order + 1);",
                        "err_norm = wrms(N, wk->d, wk->w) / (order + 1) * 1e-3;"),
 }
@@ -189,7 +195,34 @@ def _pin_vjp(lib):
     return True
 
 
-PINS = [_pin_handworked, _pin_fd_homogeneity_balance, _pin_pieces, _pin_closed_forms, _pin_radau_small, _pin_vjp]
+def _pin_adjoint(lib):
+    """The discrete adjoint against central differences of the replayed map."""
+    m = synth.mech_small_thermal()
+    o = oracle_pkg.Oracle(m, lib_path=lib)
+    c = synth.make_cells(m, 1, seed=3)
+    k = o.rate_constants(c.T, c.jscale)[:, 0]
+    y0 = c.y0[:, 0]
+    y, s, _, tape = o.solve_taped(k, y0, 60.0)
+    if s != 0:
+        return False
+    _, rt = o.replay(k, y0, tape)
+    w = np.random.default_rng(3).normal(size=m.n_species) / np.maximum(y, 1.0)
+    lam, g = o.adjoint(k, y0, rt, w)
+    eps = 1e-5
+    for j in range(0, m.n_reactions, 5):
+        kp, km = k.copy(), k.copy()
+        kp[j] *= math.exp(eps)
+        km[j] *= math.exp(-eps)
+        fd = (w @ o.replay(kp, y0, tape)[0] - w @ o.replay(km, y0, tape)[0]) / (2 * eps)
+        if not abs(g[j] - fd) <= 1e-5 * abs(fd) + 1e-8 * np.abs(g).max():
+            return False
+    u = np.random.default_rng(4).normal(size=m.n_species) * y0
+    fd = (w @ o.replay(k, y0 + eps * u, tape)[0] - w @ o.replay(k, y0 - eps * u, tape)[0]) / (2 * eps)
+    return abs(lam @ u - fd) <= 1e-5 * abs(fd) + 1e-12
+
+
+PINS = [_pin_handworked, _pin_fd_homogeneity_balance, _pin_pieces, _pin_closed_forms, _pin_radau_small, _pin_vjp,
+        _pin_adjoint]
 
 
 def test_unmodified_oracle_passes_every_pin():
