@@ -202,6 +202,11 @@ mcc_status mcc_mech_jac_pattern(const mcc_mech *mech, int32_t *row_ptr, int32_t 
 mcc_status mcc_debug_emulate_cell(const mcc_mech *mech, const double *k, const double *y, double c,
                                   const double *b, double *f, double *x, int32_t *violations);
 
+/* Testing aid (host only): as mcc_debug_emulate_cell with the solver tables
+ * of the transposed system, x = (I - c J(y))^-T b (the reverse-mode step). */
+mcc_status mcc_debug_emulate_cell_adjoint(const mcc_mech *mech, const double *k, const double *y, double c,
+                                          const double *b, double *f, double *x, int32_t *violations);
+
 /* Testing aid (host only): f and the sparse J of one cell from the tables of
  * the streaming f/J kernel, run on the host in the kernel's order; k
  * [n_reactions], y [n_species] in, f [n_species], jac [nnz] out (host

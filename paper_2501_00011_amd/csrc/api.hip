@@ -15,6 +15,7 @@ using namespace mcc;
 
 struct mcc_mech {
     HostTables t;
+    HostTables ta;  // solver tables of the transposed system I - c J^T (reverse mode)
     int device = 0;
     void *dev_buf = nullptr;  // every device table, sub-allocated
     // device views
@@ -162,6 +163,7 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     if (!m) return set_error(MCC_ERR_OOM, "host allocation failed");
     std::string err;
     mcc_status st = compile_mechanism(desc, c.dense_tail, &m->t, &err);
+    if (st == MCC_OK) st = compile_mechanism(desc, c.dense_tail, &m->ta, &err, true);
     if (st != MCC_OK) {
         delete m;
         return set_error(st, err);
@@ -292,6 +294,15 @@ mcc_status mcc_debug_emulate_cell(const mcc_mech *m, const double *k, const doub
     if (!m || (!k && m->t.R > 0) || !y || !b || !f || !x || !violations)
         return set_error(MCC_ERR_INVALID_ARG, "null argument");
     *violations = emulate_cell(m->t, k, y, c, b, f, x);
+    return ok();
+}
+
+mcc_status mcc_debug_emulate_cell_adjoint(const mcc_mech *m, const double *k, const double *y, double c,
+                                          const double *b, double *f, double *x, int32_t *violations)
+{
+    if (!m || (!k && m->ta.R > 0) || !y || !b || !f || !x || !violations)
+        return set_error(MCC_ERR_INVALID_ARG, "null argument");
+    *violations = emulate_cell(m->ta, k, y, c, b, f, x);
     return ok();
 }
 

@@ -66,6 +66,7 @@ struct alignas(16) Op16 {
 // ---------------------------------------------------------------------------
 struct HostTables {
     int N = 0, R = 0, nnz = 0, lu_nnz = 0, NS = 0, n_partials = 0;
+    bool transposed = false;  // solver tables for I - c J^T
 
     // Jacobian pattern, species order, CSR with sorted columns, diagonal present.
     std::vector<int32_t> row_ptr, col_idx;
@@ -125,7 +126,9 @@ struct HostTables {
 };
 
 // Validates desc and fills t.  Returns MCC_OK or MCC_ERR_MECH with *err set.
-mcc_status compile_mechanism(const mcc_mech_desc *desc, int dense_tail, HostTables *t, std::string *err);
+// transpose: the solver tables are built for I - c J^T (reverse mode).
+mcc_status compile_mechanism(const mcc_mech_desc *desc, int dense_tail, HostTables *t, std::string *err,
+                             bool transpose = false);
 
 // Host emulation of the solver's table-driven phases (testing aid).
 int emulate_cell(const HostTables &t, const double *k, const double *y_species, double c,

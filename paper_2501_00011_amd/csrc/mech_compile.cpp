@@ -164,7 +164,7 @@ int emit_blocks(std::vector<std::vector<T>> &lanes, const T &pad, std::vector<T>
 
 }  // namespace
 
-mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables *t, std::string *err)
+mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables *t, std::string *err, bool transpose)
 {
     if (!validate(d, err)) return MCC_ERR_MECH;
     const int N = d->n_species, R = d->n_reactions;
@@ -392,13 +392,20 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
     }
 
     // ---- fill-reducing order and symbolic LU (elimination positions) -------
-    t->perm = markowitz_order(pat);
+    // The solver's system: M = I - c J, or with transpose its transpose
+    // I - c J^T (the reverse-mode step), whose pattern is the transposed one.
+    std::vector<std::vector<char>> spat = pat;
+    if (transpose)
+        for (int i = 0; i < N; ++i)
+            for (int s = 0; s < N; ++s) spat[i][s] = pat[s][i];
+    t->transposed = transpose;
+    t->perm = markowitz_order(spat);
     t->iperm.assign(N, 0);
     for (int p = 0; p < N; ++p) t->iperm[t->perm[p]] = p;
     std::vector<std::vector<char>> lp(N, std::vector<char>(N, 0));
     for (int i = 0; i < N; ++i)
         for (int s = 0; s < N; ++s)
-            if (pat[i][s]) lp[t->iperm[i]][t->iperm[s]] = 1;
+            if (spat[i][s]) lp[t->iperm[i]][t->iperm[s]] = 1;
     for (int k = 0; k < N; ++k)
         for (int i = k + 1; i < N; ++i)
             if (lp[i][k])
@@ -550,7 +557,11 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         for (int qi = 0; qi < P; ++qi)
             for (const auto &kv : net_stoich(d, parts[qi].j))
                 if (kv.second != 0.0)
-                    eterms[lpos[t->iperm[kv.first]][t->iperm[parts[qi].s]]].push_back({qi, kv.second});
+                {
+                    // J entry (i = species changed, s = the partial's species); transposed: entry (s, i)
+                    const int ri = t->iperm[kv.first], cs = t->iperm[parts[qi].s];
+                    eterms[transpose ? lpos[cs][ri] : lpos[ri][cs]].push_back({qi, kv.second});
+                }
         std::vector<std::vector<Op16>> chains(nlu);
         for (int e = 0; e < nlu; ++e) {
             auto &tl = eterms[e];

@@ -72,6 +72,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_debug_emulate_cell": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_debug_schedule_info": ([vp, vp], ctypes.c_int),
         "mcc_debug_emulate_fj": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_debug_emulate_cell_adjoint": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
@@ -165,17 +166,19 @@ class Mechanism:
                  "fj_bytes", "f_bytes", "j_bytes"]
         return dict(zip(names, list(buf)[:7]))
 
-    def emulate_cell(self, k, y, c, b):
+    def emulate_cell(self, k, y, c, b, transposed: bool = False):
         """Host emulation of the solver phases for one cell (testing aid):
-        returns (f, x = (I - c J)^-1 b, violations)."""
+        returns (f, x = (I - c J)^-1 b, violations), or with transposed the
+        solve with (I - c J)^T by the reverse-mode tables."""
         k = np.ascontiguousarray(k, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
         b = np.ascontiguousarray(b, dtype=np.float64)
         f = np.zeros(self.n_species)
         x = np.zeros(self.n_species)
         v = ctypes.c_int32()
-        _check(library().mcc_debug_emulate_cell(self._h, k.ctypes.data, y.ctypes.data, float(c), b.ctypes.data,
-                                                f.ctypes.data, x.ctypes.data, ctypes.byref(v)))
+        fn = library().mcc_debug_emulate_cell_adjoint if transposed else library().mcc_debug_emulate_cell
+        _check(fn(self._h, k.ctypes.data, y.ctypes.data, float(c), b.ctypes.data, f.ctypes.data, x.ctypes.data,
+                  ctypes.byref(v)))
         return f, x, v.value
 
     def emulate_fj(self, k, y):

@@ -143,3 +143,24 @@ def test_dense_tail_configuration():
             mcchem.Mechanism(m, device=-1, dense_tail=bad)
     with pytest.raises(mcchem.MccError):
         mcchem.Mechanism(synth.mech_small(), device=-1, dense_tail=32)
+
+
+@pytest.mark.parametrize("mech_fn", [synth.mech_small_thermal, synth.mech_medium, synth.mech_large])
+@pytest.mark.parametrize("c", [1e-6, 10.0])
+def test_transposed_tables_solve_the_adjoint_system(oracle_mod, mech_fn, c):
+    """The reverse-mode tables (the solver compiled for I - c J^T: transposed
+    pattern, its own ordering and schedule) solve (I - c J)^T x = b."""
+    m = mech_fn()
+    h = mcchem.Mechanism(m, device=-1)
+    o = oracle_mod.Oracle(m)
+    cells = synth.make_cells(m, 2, seed=41)
+    k = o.rate_constants(cells.T, cells.jscale)
+    J_ref, _ = o.jac(k, cells.y0)
+    rng = np.random.default_rng(8)
+    for cell in range(2):
+        b = rng.normal(size=m.n_species)
+        _, x, viol = h.emulate_cell(k[:, cell], cells.y0[:, cell], c, b, transposed=True)
+        assert viol == 0
+        Mt = (np.eye(m.n_species) - c * J_ref[cell]).T
+        resid = np.abs(Mt @ x - b)
+        assert np.all(resid <= 1e-12 * (np.abs(Mt) @ np.abs(x) + np.abs(b)))
