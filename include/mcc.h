@@ -65,7 +65,9 @@ typedef enum {
     MCC_CELL_CONV_FAIL = 2,     /* Newton failures drove h below its minimum */
     MCC_CELL_ERR_FAIL = 3,      /* error-test failures drove h below its minimum */
     MCC_CELL_NONFINITE = 4,     /* non-finite state or derivative */
-    MCC_CELL_SINGULAR = 5       /* zero/non-finite pivot drove h below its minimum */
+    MCC_CELL_SINGULAR = 5,      /* zero/non-finite pivot drove h below its minimum
+                                   (mcc_adjoint_step: a singular transposed matrix) */
+    MCC_CELL_BAD_TAPE = 6       /* mcc_adjoint_step: the cell's tape is malformed */
 } mcc_cell_status;
 
 /* Reaction types. */
@@ -327,6 +329,30 @@ mcc_status mcc_solve_step(mcc_cells *cells, double *y, double dt, const mcc_solv
  * about 110 species). */
 mcc_status mcc_solve_step_multicell(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
                                     int32_t *cell_status, mcc_cell_stats *stats, void *stream);
+
+/* Reverse mode of one outer step (the discrete adjoint of the BDF step
+ * sequence of mcc_solve_step, Section 2 solver, with that sequence frozen):
+ * given lam = dL/dy(dt), overwrite lam with dL/dy0 and write (accumulate != 0:
+ * add) dL/d ln k_j to glnk, for every cell.  The step sequence of each cell
+ * is its tape: device doubles [n_cells][tape_stride], cell c using the first
+ * tape_len[c] (device int64 [n_cells]).  Entries are written in time order,
+ * each as a payload followed by three doubles (order, value, type):
+ *   type 0, start: value = the first step size h (D_0 = y0, D_1 = h f(y0));
+ *   type 1, re-sampling of the differences D_0..D_order to spacing value * h;
+ *   type 2, accepted step of order k with value c = h / gamma_k; payload:
+ *        the step's converged state z (n_species values, species order).
+ * Every tape starts with one type-0 entry.  For a step the transpose of
+ * I - c J(z) is factorised with the mechanism's transposed solver tables.
+ * y0 device [n_species][ld] (the state the tape starts from), lam device
+ * [n_species][ld] in/out, glnk device [n_reactions][ld], cell_status device
+ * int32 [n_cells] or NULL: MCC_CELL_OK, MCC_CELL_SINGULAR, or
+ * MCC_CELL_BAD_TAPE (that cell's outputs are NaN).  MCC_ERR_MECH when the
+ * mechanism has no reverse-mode kernel (the reason in mcc_last_error()):
+ * it is built for one or two species slots with no, a 32- or a 48-row dense
+ * tail, and at most 512 reactions. */
+mcc_status mcc_adjoint_step(const mcc_cells *cells, const double *y0, const double *tape, const int64_t *tape_len,
+                            int64_t tape_stride, double *lam, double *glnk, int32_t accumulate,
+                            int32_t *cell_status, void *stream);
 
 /* Wait for all work of this batch's device and report any asynchronous error. */
 mcc_status mcc_sync(mcc_cells *cells);

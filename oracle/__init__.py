@@ -74,6 +74,15 @@ class Tape:
     def __len__(self):
         return int(self.lib.orc_tape_size(self.h))
 
+    def values(self):
+        """A copy of the entries: type, order, value, then for a step the N
+        state values."""
+        n = len(self)
+        if n == 0:
+            return np.zeros(0)
+        ptr = ctypes.cast(self.lib.orc_tape_data(self.h), ctypes.POINTER(ctypes.c_double))
+        return np.ctypeslib.as_array(ptr, shape=(n,)).copy()
+
     def __del__(self):
         if getattr(self, "h", None):
             self.lib.orc_tape_free(self.h)
@@ -105,6 +114,8 @@ class Oracle:
         L.orc_tape_free.argtypes = [vp]
         L.orc_tape_size.argtypes = [vp]
         L.orc_tape_size.restype = i64
+        L.orc_tape_data.argtypes = [vp]
+        L.orc_tape_data.restype = vp
         L.orc_cell_solve_taped.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.orc_cell_solve_taped.restype = ctypes.c_int
         L.orc_cell_replay.argtypes = [vp, vp, vp, vp, vp, vp]

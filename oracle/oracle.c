@@ -682,6 +682,8 @@ void orc_tape_free(orc_tape *t)
     free(t);
 }
 int64_t orc_tape_size(const orc_tape *t) { return (int64_t)t->n; }
+/* The tape's entries: type, order, value, then (a step) the N state values. */
+const double *orc_tape_data(const orc_tape *t) { return t->v; }
 
 /* One outer step of one cell as cell_solve, recording the tape.  kc [R],
  * y [N] in/out. */

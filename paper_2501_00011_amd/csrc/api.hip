@@ -38,6 +38,17 @@ struct mcc_mech {
     std::string arch;
     hipModule_t fj_mod = nullptr;
     hipFunction_t fj_fn = nullptr, fj2_fn = nullptr, vjp_fn = nullptr, vjp2_fn = nullptr;
+    // reverse mode: the transposed solver tables on the device and their LDS layout
+    struct {
+        const int32_t *vspecies = nullptr, *rx_reac = nullptr, *part = nullptr;
+        const int32_t *nu_ptr = nullptr, *nu_vid = nullptr;
+        const double *nu_coef = nullptr;
+        const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
+        const uint64_t *lu_ops = nullptr;
+        const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
+        int32_t off_y = 0, off_k = 0, off_r = 0, off_lu = 0, off_tm = 0, off_w = 0, lds_doubles = 0;
+        std::string unavailable;  // empty: the reverse-mode kernel runs for this mechanism
+    } adj;
 };
 
 struct mcc_cells {
@@ -179,6 +190,23 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     m->off_lu = m->off_r + std::max(t.R, t.n_partials) + 1;
     m->off_tm = m->off_lu + t.lu_nnz + 2;
     m->lds_doubles = m->off_tm + (kMaxOrder + 1) * (kMaxOrder + 1);
+    {
+        // reverse mode: the same regions for the transposed tables, then R + 1 scratch values
+        const HostTables &a = m->ta;
+        auto &d = m->adj;
+        d.off_y = 0;
+        d.off_k = a.NV + 1;
+        d.off_r = d.off_k + a.R;
+        d.off_lu = d.off_r + std::max(a.R, a.n_partials) + 1;
+        d.off_tm = d.off_lu + a.lu_nnz + 2;
+        d.off_w = d.off_tm + (kMaxOrder + 1) * (kMaxOrder + 1);
+        d.lds_doubles = d.off_w + a.R + 1;
+        if (!adjoint_shape_supported(a.NS, a.M))
+            d.unavailable = "no reverse-mode kernel for " + std::to_string(a.NS) + " species slots with a dense tail of " +
+                            std::to_string(a.M);
+        else if (a.R > kAdjMaxR)
+            d.unavailable = "the reverse-mode kernel handles at most " + std::to_string(kAdjMaxR) + " reactions";
+    }
     if (device == -1) {  // host-only: validated and compiled, nothing uploaded
         *out = m;
         return ok();
@@ -225,6 +253,13 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
         delete m;
         return hip_error(e, "hipFuncSetAttribute");
     }
+    if (m->adj.unavailable.empty() && (size_t)m->adj.lds_doubles * sizeof(double) > (size_t)max_lds)
+        m->adj.unavailable = "the reverse-mode state of one cell needs " +
+                             std::to_string((size_t)m->adj.lds_doubles * sizeof(double)) + " bytes of LDS";
+    if (m->adj.unavailable.empty() && (e = prepare_adjoint_kernels(max_lds)) != hipSuccess) {
+        delete m;
+        return hip_error(e, "hipFuncSetAttribute");
+    }
 
     Packer pk;
     const size_t o_rxn = pk.add(t.rxn_type), o_A = pk.add(t.A), o_th = pk.add(t.theta);
@@ -235,6 +270,11 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
     const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
+    const HostTables &ta = m->ta;
+    const size_t oa_perm = pk.add(ta.vspecies), oa_rxr = pk.add(ta.rx_reac), oa_part = pk.add(ta.part);
+    const size_t oa_fg = pk.add(ta.fg_ops), oa_nm = pk.add(ta.nm_ops), oa_lu = pk.add(ta.lu_ops);
+    const size_t oa_fwd = pk.add(ta.fwd_map), oa_bwd = pk.add(ta.bwd_map);
+    const size_t oa_nup = pk.add(ta.nu_ptr), oa_nuv = pk.add(ta.nu_vid), oa_nuc = pk.add(ta.nu_coef);
     if ((e = hipMalloc(&m->dev_buf, pk.bytes.size())) != hipSuccess) {
         delete m;
         return hip_error(e, "hipMalloc (mechanism tables)");
@@ -265,6 +305,17 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     m->lu_ops = (const uint64_t *)(b + o_lu);
     m->fwd_map = (const uint16_t *)(b + o_fwd);
     m->bwd_map = (const uint16_t *)(b + o_bwd);
+    m->adj.vspecies = (const int32_t *)(b + oa_perm);
+    m->adj.rx_reac = (const int32_t *)(b + oa_rxr);
+    m->adj.part = (const int32_t *)(b + oa_part);
+    m->adj.fg_ops = (const Op16 *)(b + oa_fg);
+    m->adj.nm_ops = (const Op16 *)(b + oa_nm);
+    m->adj.lu_ops = (const uint64_t *)(b + oa_lu);
+    m->adj.fwd_map = (const uint16_t *)(b + oa_fwd);
+    m->adj.bwd_map = (const uint16_t *)(b + oa_bwd);
+    m->adj.nu_ptr = (const int32_t *)(b + oa_nup);
+    m->adj.nu_vid = (const int32_t *)(b + oa_nuv);
+    m->adj.nu_coef = (const double *)(b + oa_nuc);
     *out = m;
     return ok();
 }
@@ -715,6 +766,71 @@ static SolveParams solve_params(mcc_cells *c, double *y, double dt, const mcc_so
     p.dt = dt;
     p.opts = o;
     return p;
+}
+
+mcc_status mcc_adjoint_step(const mcc_cells *c, const double *y0, const double *tape, const int64_t *tape_len,
+                            int64_t tape_stride, double *lam, double *glnk, int32_t accumulate, int32_t *cell_status,
+                            void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "the batch has no rate constants yet");
+    const mcc_mech *m = c->mech;
+    if (!m->adj.unavailable.empty()) return set_error(MCC_ERR_MECH, m->adj.unavailable);
+    if (tape_stride < 0) return set_error(MCC_ERR_INVALID_ARG, "tape_stride < 0");
+    if (c->n_cells == 0) return ok();
+    if (!y0 || !tape_len || !lam || !glnk || (!tape && tape_stride > 0))
+        return set_error(MCC_ERR_INVALID_ARG, "y0, tape, tape_len, lam and glnk must not be null");
+    if (c->n_cells > 0x7fffffff) return set_error(MCC_ERR_INVALID_ARG, "too many cells");
+    const HostTables &t = m->ta;
+    SolveParams p{};
+    p.vspecies = m->adj.vspecies;
+    p.rx_reac = m->adj.rx_reac;
+    p.part = m->adj.part;
+    p.fg_ops = m->adj.fg_ops;
+    p.nm_ops = m->adj.nm_ops;
+    p.lu_ops = m->adj.lu_ops;
+    p.fwd_map = m->adj.fwd_map;
+    p.bwd_map = m->adj.bwd_map;
+    for (int q = 0; q < kMaxSlots; ++q) {
+        p.fg_blocks[q] = q < t.NS ? t.fg_blocks[q] : 0;
+        p.fg_base[q] = q < t.NS ? t.fg_base[q] : 0;
+        p.slot_cols[q] = q < t.NS ? t.slot_cols[q] : 0;
+    }
+    p.nm_blocks = t.nm_blocks;
+    p.lu_blocks = t.lu_blocks;
+    p.NV = t.NV;
+    p.tail_base = t.tail_base;
+    p.N = t.N;
+    p.R = t.R;
+    p.P = t.n_partials;
+    p.lu_nnz = t.lu_nnz;
+    p.off_y = m->adj.off_y;
+    p.off_k = m->adj.off_k;
+    p.off_r = m->adj.off_r;
+    p.off_p = m->adj.off_r;
+    p.off_lu = m->adj.off_lu;
+    p.off_tm = m->adj.off_tm;
+    p.lds_doubles = m->adj.lds_doubles;
+    p.k = c->k;
+    p.n_cells = c->n_cells;
+    p.ld = c->ld;
+    AdjointParams a{};
+    a.tape = tape;
+    a.len = tape_len;
+    a.stride = tape_stride;
+    a.y0 = y0;
+    a.lam = lam;
+    a.glnk = glnk;
+    a.status = cell_status;
+    a.nu_ptr = m->adj.nu_ptr;
+    a.nu_vid = m->adj.nu_vid;
+    a.nu_coef = m->adj.nu_coef;
+    a.off_w = m->adj.off_w;
+    a.accumulate = accumulate != 0;
+    DeviceGuard g(m->device);
+    hipError_t e = launch_adjoint(p, a, t.NS, t.M, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "reverse-mode kernel launch");
+    return ok();
 }
 
 mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,

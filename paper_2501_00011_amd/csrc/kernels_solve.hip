@@ -130,6 +130,28 @@ struct Cell {
     // f_v = sum nu r gathered per virtual index (lane per index).
     __device__ __forceinline__ void deriv(const double (&v)[NS], double (&f)[NS])
     {
+        rates(v);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            Prefetcher<Op16> st;
+            st.start(p.fg_ops + (size_t)p.fg_base[s] * kWave * kBlk, lane, p.fg_blocks[s]);
+            double acc = 0.0;
+            for (int b = 0; b < p.fg_blocks[s]; ++b) {
+                Op16 op[kBlk];
+                st.take(op);
+                double r[kBlk];
+#pragma unroll
+                for (int i = 0; i < kBlk; ++i) r[i] = rv[op[i].meta];
+#pragma unroll
+                for (int i = 0; i < kBlk; ++i) acc += op[i].coef * r[i];
+            }
+            f[s] = acc;
+        }
+    }
+
+    // Reaction rates at v into rv (lane per reaction); rv[R] = 0.
+    __device__ __forceinline__ void rates(const double (&v)[NS])
+    {
         put_y(v);
         const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
         for (int j0 = 0; j0 < p.R; j0 += 4 * kWave) {
@@ -152,26 +174,36 @@ struct Cell {
         }
         if (lane == 0) rv[p.R] = 0.0;  // the zero rate idle gather lanes read
         __syncthreads();
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            Prefetcher<Op16> st;
-            st.start(p.fg_ops + (size_t)p.fg_base[s] * kWave * kBlk, lane, p.fg_blocks[s]);
-            double acc = 0.0;
-            for (int b = 0; b < p.fg_blocks[s]; ++b) {
-                Op16 op[kBlk];
-                st.take(op);
-                double r[kBlk];
-#pragma unroll
-                for (int i = 0; i < kBlk; ++i) r[i] = rv[op[i].meta];
-#pragma unroll
-                for (int i = 0; i < kBlk; ++i) acc += op[i].coef * r[i];
-            }
-            f[s] = acc;
-        }
     }
 
     // Newton matrix M = I - c J(v) written over the LU storage (fill = 0).
     __device__ __forceinline__ void newton_matrix(const double (&v)[NS], double c)
+    {
+        partials(v);
+        Prefetcher<Op16> st;
+        st.start(p.nm_ops, lane, p.nm_blocks);
+        double acc = 0.0;
+        for (int b = 0; b < p.nm_blocks; ++b) {
+            Op16 op[kBlk];
+            st.take(op);
+            double x[kBlk];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) x[i] = pv[op[i].meta & kOffMask];
+#pragma unroll
+            for (int i = 0; i < kBlk; ++i) {
+                const uint32_t fl = op[i].meta >> 28;
+                acc = (fl & kFirst) ? op[i].coef * x[i] : acc + op[i].coef * x[i];
+                if (fl & kLast) {
+                    const double m = -c * acc;
+                    lu[off_at(op[i].meta, kOffBits)] = (fl & kDiag) ? 1.0 + m : m;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Rate partials d r_j / d y_s at v into pv (lane per partial); pv[P] = 0.
+    __device__ __forceinline__ void partials(const double (&v)[NS])
     {
         put_y(v);
         const int4 *pt = reinterpret_cast<const int4 *>(p.part);
@@ -193,26 +225,6 @@ struct Cell {
             }
         }
         if (lane == 0) pv[p.P] = 0.0;  // the zero partial of fill entries and idle lanes
-        __syncthreads();
-        Prefetcher<Op16> st;
-        st.start(p.nm_ops, lane, p.nm_blocks);
-        double acc = 0.0;
-        for (int b = 0; b < p.nm_blocks; ++b) {
-            Op16 op[kBlk];
-            st.take(op);
-            double x[kBlk];
-#pragma unroll
-            for (int i = 0; i < kBlk; ++i) x[i] = pv[op[i].meta & kOffMask];
-#pragma unroll
-            for (int i = 0; i < kBlk; ++i) {
-                const uint32_t fl = op[i].meta >> 28;
-                acc = (fl & kFirst) ? op[i].coef * x[i] : acc + op[i].coef * x[i];
-                if (fl & kLast) {
-                    const double m = -c * acc;
-                    lu[off_at(op[i].meta, kOffBits)] = (fl & kDiag) ? 1.0 + m : m;
-                }
-            }
-        }
         __syncthreads();
     }
 
@@ -466,6 +478,42 @@ __device__ __forceinline__ void rescale(double (&D)[kMaxOrder + 3][NS], int orde
 #pragma unroll
         for (int i = 0; i < M6; ++i)
             D[i][s] = i <= order ? out[i] : D[i][s];
+    }
+}
+
+// The transpose of rescale (reverse mode): L_j = sum_{i <= order} T_ij L'_i.
+template <int NS>
+__device__ __forceinline__ void rescale_transposed(double (&L)[kMaxOrder + 3][NS], int order, double rho, double *tm)
+{
+    constexpr int M6 = kMaxOrder + 1;
+    const int lane = (int)threadIdx.x;
+    __syncthreads();
+    if (lane < M6 * M6) {
+        const int i = lane / M6, j = lane % M6;
+        double acc = 0.0;
+        for (int l = 0; l <= order; ++l) {
+            double r = 1.0, u = 1.0;
+            for (int m = 1; m <= j; ++m) r *= ((m - 1) - rho * l) / m;
+            for (int m = 1; m <= l; ++m) u *= (double)((m - 1) - i) / m;
+            acc += r * u;
+        }
+        tm[lane] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        double out[M6];
+#pragma unroll
+        for (int j = 0; j < M6; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < M6; ++i)
+                if (i <= order) acc += tm[i * M6 + j] * L[i][s];
+            out[j] = acc;
+        }
+#pragma unroll
+        for (int j = 0; j < M6; ++j)
+            L[j][s] = j <= order ? out[j] : L[j][s];
     }
 }
 
@@ -834,6 +882,179 @@ __global__ void fill_i32_kernel(int32_t *q, int32_t v)
     if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = v;
 }
 
+// Reverse mode of one outer step (the discrete adjoint of its frozen step
+// sequence), one wavefront per cell, with the solver tables of the
+// transposed system I - c J^T.  The tape holds, per cell, entries written
+// payload first: [z (n_species, species order) for a step] order, value,
+// type; it is walked backwards.  For an accepted step of order k with
+// c = h / gamma_k at its converged state z: the difference update is
+// reversed, lam_d = lam_{k+1} + lam_{k+2}, mu = (I - c J(z))^-T lam_d (the
+// transposed matrix assembled, factorised and solved by the forward code),
+// then lam_ypred = c J^T mu = mu - lam_d and lam_psi = -mu go back onto the
+// differences, and d L / d ln k_j gains c r_j(z) sum_i nu_ij mu_i.  A
+// re-sampling of the differences is reversed with its transpose.  The start
+// D_0 = y0, D_1 = h f(y0) gives dL/dy0 = lam_0 + h J(y0)^T lam_1 and
+// d L / d ln k_j += h r_j(y0) sum_i nu_ij lam_1,i.
+constexpr int kAdjMaxRPass = kAdjMaxR / kWave;  // reactions per lane
+
+template <int NS, int M>
+__global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParams a)
+{
+    extern __shared__ double smem[];
+    const int64_t cell = blockIdx.x;
+    if (cell >= p.n_cells) return;
+    Cell<NS, M> C(p, smem);
+    double *wv = smem + a.off_w;
+    const int lane = C.lane, N = p.N;
+    for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
+    if (lane == 0) C.yv[p.NV] = 1.0;
+    if (lane == 0) {
+        C.lu[p.lu_nnz] = 0.0;
+        C.lu[p.lu_nnz + 1] = 0.0;
+    }
+    int sp[NS];
+    double L[kMaxOrder + 3][NS], z[NS], mu[NS], ld_[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sp[s] = C.valid(s) ? p.vspecies[s * kWave + lane] : 0;
+#pragma unroll
+        for (int j = 0; j < kMaxOrder + 3; ++j) L[j][s] = 0.0;
+        L[0][s] = C.valid(s) ? a.lam[(int64_t)sp[s] * p.ld + cell] : 0.0;
+    }
+    double g[kAdjMaxRPass];
+#pragma unroll
+    for (int u = 0; u < kAdjMaxRPass; ++u) g[u] = 0.0;
+    const int32_t *nu_ptr = a.nu_ptr, *nu_vid = a.nu_vid;
+    const double *nu_coef = a.nu_coef;
+    // d L / d ln k_j += cc * r_j * sum_i nu_ij yv_i (rv = the rates, yv = the multiplier)
+    auto add_lnk = [&](double cc) {
+#pragma unroll
+        for (int u = 0; u < kAdjMaxRPass; ++u) {
+            const int j = u * kWave + lane;
+            if (j < p.R) {
+                double w = 0.0;
+                for (int e = nu_ptr[j]; e < nu_ptr[j + 1]; ++e) w += nu_coef[e] * C.yv[nu_vid[e]];
+                g[u] += cc * C.rv[j] * w;
+            }
+        }
+    };
+    const double *tp = a.tape + cell * a.stride;
+    int64_t pos = a.len[cell];
+    int status = (pos >= 0 && pos <= a.stride) ? 0 : 1;
+    const bool empty = pos == 0;
+    bool started = false;
+    while (status == 0 && pos >= 3) {
+        const int type = (int)tp[pos - 1];
+        const double x = tp[pos - 2];
+        const int order = (int)tp[pos - 3];
+        pos -= 3;
+        if (type != 0 && (order < 1 || order > kMaxOrder)) {
+            status = 1;
+            break;
+        }
+        if (type == 1) {  // re-sampling of the differences
+            rescale_transposed<NS>(L, order, x, C.tm);
+        } else if (type == 2) {  // accepted step
+            if (pos < N) {
+                status = 1;
+                break;
+            }
+            pos -= N;
+            const int k = order;
+            const double c = x;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                z[s] = C.valid(s) ? tp[pos + sp[s]] : 0.0;
+                // D_j += D_{j+1} (j = k..0), reversed: lam_{j+1} += lam_j (j = 0..k)
+#pragma unroll
+                for (int j = 0; j <= kMaxOrder; ++j)
+                    if (j <= k) L[j + 1][s] += L[j][s];
+                double l1 = 0.0, l2 = 0.0;
+#pragma unroll
+                for (int j = 0; j < kMaxOrder + 3; ++j) {
+                    l1 = j == k + 1 ? L[j][s] : l1;
+                    l2 = j == k + 2 ? L[j][s] : l2;
+                }
+                ld_[s] = l1 + l2;  // lam_d
+                mu[s] = ld_[s];
+#pragma unroll
+                for (int j = 0; j < kMaxOrder + 3; ++j) {
+                    L[j][s] = j == k + 1 ? -l2 : L[j][s];
+                    L[j][s] = j == k + 2 ? 0.0 : L[j][s];
+                }
+            }
+            C.newton_matrix(z, c);  // assembles I - c J(z)^T (transposed tables)
+            if (C.factor()) {
+                status = 2;
+                break;
+            }
+            C.solve(mu);
+            const double gk = bdf_gamma(k);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const double lp = mu[s] - ld_[s];  // lam_ypred = c J^T mu
+#pragma unroll
+                for (int j = 0; j <= kMaxOrder; ++j) {
+                    if (j <= k) L[j][s] += lp;
+                    if (j >= 1 && j <= k) L[j][s] -= bdf_gamma(j) / gk * mu[s];
+                }
+            }
+            C.rates(z);
+            C.put_y(mu);
+            add_lnk(c);
+        } else if (type == 0) {  // start: D_0 = y0, D_1 = h f(y0)
+            const double h = x;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) z[s] = C.valid(s) ? a.y0[(int64_t)sp[s] * p.ld + cell] : 0.0;
+            C.rates(z);
+            C.put_y(L[1]);
+            // w_j = sum_i nu_ij lam_1,i (kept in wv), d L / d ln k_j += h r_j w_j, then
+            // (J^T lam_1)_s = sum over the partials taken with respect to s of partial * w_j
+#pragma unroll
+            for (int u = 0; u < kAdjMaxRPass; ++u) {
+                const int j = u * kWave + lane;
+                if (j < p.R) {
+                    double w = 0.0;
+                    for (int e = nu_ptr[j]; e < nu_ptr[j + 1]; ++e) w += nu_coef[e] * C.yv[nu_vid[e]];
+                    g[u] += h * C.rv[j] * w;
+                    wv[j] = w;
+                }
+            }
+            C.partials(z);
+            const int4 *pt = reinterpret_cast<const int4 *>(p.part);
+            double jt[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) jt[s] = 0.0;
+            for (int q = 0; q < p.P; ++q) {
+                const int4 e = pt[q];
+                const double v = C.pv[q] * wv[e.x];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) jt[s] += e.w == s * kWave + lane ? v : 0.0;
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) L[0][s] += h * jt[s];
+            if (pos != 0) status = 1;  // the start must be the first entry
+            started = true;
+            break;
+        } else {
+            status = 1;
+        }
+    }
+    if (status == 0 && !empty && !started) status = 1;  // no start entry, or a remainder shorter than an entry
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (C.valid(s)) a.lam[(int64_t)sp[s] * p.ld + cell] = status == 0 ? L[0][s] : NAN;
+#pragma unroll
+    for (int u = 0; u < kAdjMaxRPass; ++u) {
+        const int j = u * kWave + lane;
+        if (j < p.R) {
+            double *o = a.glnk + (int64_t)j * p.ld + cell;
+            *o = status != 0 ? NAN : (a.accumulate ? *o + g[u] : g[u]);
+        }
+    }
+    if (lane == 0 && a.status) a.status[cell] = status == 0 ? MCC_CELL_OK : (status == 2 ? MCC_CELL_SINGULAR : MCC_CELL_BAD_TAPE);
+}
+
 }  // namespace
 
 #define MCC_SOLVE_VARIANTS(X) \
@@ -880,6 +1101,46 @@ hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
     }
     MCC_SOLVE_VARIANTS(MCC_LAUNCH)
 #undef MCC_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+// Reverse-mode kernels for the shapes of small and 72-species class mechanisms.
+#define MCC_ADJOINT_VARIANTS(X) X(1, 0) X(2, 0) X(1, 32) X(2, 32) X(1, 48) X(2, 48)
+
+hipError_t prepare_adjoint_kernels(int max_lds_bytes)
+{
+    hipError_t e = hipSuccess;
+#define MCC_SET_LDS_ADJ(ns, m)                                                                           \
+    if (e == hipSuccess)                                                                                \
+        e = hipFuncSetAttribute((const void *)adjoint_kernel<ns, m>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                max_lds_bytes);
+    MCC_ADJOINT_VARIANTS(MCC_SET_LDS_ADJ)
+#undef MCC_SET_LDS_ADJ
+    return e;
+}
+
+bool adjoint_shape_supported(int NS, int M)
+{
+#define MCC_ADJ_OK(ns, m) \
+    if (NS == ns && M == m) return true;
+    MCC_ADJOINT_VARIANTS(MCC_ADJ_OK)
+#undef MCC_ADJ_OK
+    return false;
+}
+
+hipError_t launch_adjoint(const SolveParams &p, const AdjointParams &a, int NS, int M, hipStream_t s)
+{
+    if (p.n_cells == 0) return hipSuccess;
+    if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)p.n_cells), block(kWave);
+    const size_t lds = (size_t)p.lds_doubles * sizeof(double);
+#define MCC_LAUNCH_ADJ(ns, m)                                                 \
+    if (NS == ns && M == m) {                                                 \
+        hipLaunchKernelGGL((adjoint_kernel<ns, m>), grid, block, lds, s, p, a); \
+        return hipGetLastError();                                             \
+    }
+    MCC_ADJOINT_VARIANTS(MCC_LAUNCH_ADJ)
+#undef MCC_LAUNCH_ADJ
     return hipErrorInvalidValue;
 }
 

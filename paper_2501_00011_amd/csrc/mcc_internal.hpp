@@ -88,6 +88,7 @@ struct HostTables {
     std::vector<int32_t> rx_sp;       // [3 * R]
     std::vector<int32_t> nu_ptr, nu_sp;
     std::vector<double> nu_coef;
+    std::vector<int32_t> nu_vid;      // nu_sp as virtual indices of the solver's layout
     // the paper's Derivative kernel data (ablation): records and inverted
     std::vector<int32_t> paper_rec, paper_rec_inv;
     std::vector<double> paper_yld, paper_yld_inv;
@@ -105,7 +106,7 @@ struct HostTables {
     int tail_base = 0;                // LU offset of the column-major tail block
     std::vector<int32_t> slot_cols;   // [NS]: columns (lanes) in use per slot
     std::vector<int32_t> rx_reac;     // [4 * R]: virtual reactant ids (NV = one), pad
-    std::vector<int32_t> part;        // [4 * P]: j, o1, o2, pad (other slots, NV = one)
+    std::vector<int32_t> part;        // [4 * P]: j, o1, o2 (other slots, NV = one), own species
     // Op streams, laid out [block][lane][kBlk] so that a lane prefetches one
     // block (kBlk consecutive ops) with wide loads.
     // f gather: one stream per species slot (fg_blocks[s] blocks from block fg_base[s]).
@@ -190,6 +191,23 @@ struct SolveParams {
 };
 constexpr int kStateScalars = 16;
 
+// Reverse mode of one outer step (adjoint_kernel), with a SolveParams built
+// from the transposed solver tables.
+struct AdjointParams {
+    const double *tape;    // [n_cells][stride] entries, walked backwards
+    const int64_t *len;    // [n_cells] doubles of the tape in use
+    int64_t stride;
+    const double *y0;      // [N][ld] state at the start of the outer step
+    double *lam;           // [N][ld] in: dL/dy(end), out: dL/dy0
+    double *glnk;          // [R][ld] dL/d ln k (overwritten, or added to)
+    int32_t *status;       // [n_cells] or null
+    const int32_t *nu_ptr, *nu_vid;  // net stoichiometry per reaction, virtual indices
+    const double *nu_coef;
+    int32_t off_w;         // LDS offset (doubles) of R + 1 scratch values
+    int32_t accumulate;    // glnk += instead of =
+};
+constexpr int kAdjMaxR = 512;  // reactions per mechanism the reverse-mode kernel handles
+
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_rates(const RatesParams &p, hipStream_t s);
 hipError_t launch_fj(const FJParams &p, hipStream_t s);
@@ -210,6 +228,10 @@ bool compile_fj_source(const std::string &src, const std::string &arch, std::vec
 hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).
 hipError_t prepare_solve_kernels(int max_lds_bytes);
+// Reverse-mode kernels: shapes available, LDS limit, launch.
+bool adjoint_shape_supported(int NS, int M);
+hipError_t prepare_adjoint_kernels(int max_lds_bytes);
+hipError_t launch_adjoint(const SolveParams &p, const AdjointParams &a, int NS, int M, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);  // *p = v by a kernel (graph-safe)
 // Multi-cells solver: largest co-resident batch (0: no kernel for this shape), cooperative launch.
 hipError_t multicell_capacity(int NS, int M, size_t lds_bytes, int device, int64_t *max_cells);

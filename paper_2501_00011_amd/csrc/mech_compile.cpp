@@ -524,7 +524,10 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         t->part[4 * q + 0] = parts[q].j;
         t->part[4 * q + 1] = parts[q].o1 < N ? vid(parts[q].o1) : ONE;
         t->part[4 * q + 2] = parts[q].o2 < N ? vid(parts[q].o2) : ONE;
+        t->part[4 * q + 3] = vid(parts[q].s);  // the species the partial is taken with respect to
     }
+    t->nu_vid.resize(t->nu_sp.size());
+    for (size_t e = 0; e < t->nu_sp.size(); ++e) t->nu_vid[e] = vid(t->nu_sp[e]);
     const int P = (int)parts.size();
     if (P + 1 >= (1 << kOffBits)) {
         *err = "too many rate partials for the 14-bit offsets of the solver tables";

@@ -14,7 +14,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcchem.so")
 
-CELL_STATUS = {0: "OK", 1: "TOO_MUCH_WORK", 2: "CONV_FAIL", 3: "ERR_FAIL", 4: "NONFINITE", 5: "SINGULAR"}
+CELL_STATUS = {0: "OK", 1: "TOO_MUCH_WORK", 2: "CONV_FAIL", 3: "ERR_FAIL", 4: "NONFINITE", 5: "SINGULAR",
+               6: "BAD_TAPE"}
+CELL_OK, CELL_SINGULAR, CELL_BAD_TAPE = 0, 5, 6
 
 STATS_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_fails", np.int32),
                         ("newton_iters", np.int32), ("f_evals", np.int32), ("jac_evals", np.int32),
@@ -75,6 +77,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_debug_emulate_cell_adjoint": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_adjoint_step": ([vp, vp, vp, vp, i64, vp, vp, i32, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
@@ -333,6 +336,29 @@ class Cells:
             _dptr(glnk, "glnk", torch.float64, (self.mech.n_reactions, self.ld)) if glnk is not None else None,
             _stream_ptr(stream)))
         return gy, glnk
+
+    def adjoint_step(self, y0, tape, tape_len, lam, glnk=None, accumulate=False, status=None, stream=None):
+        """Reverse mode of one outer step: lam (dL/dy(dt), [N][ld]) is
+        overwritten with dL/dy0; dL/d ln k [R][ld] is written to (or, with
+        accumulate, added to) glnk.  tape: device float64 [n_cells][stride]
+        in the entry format of mcc_adjoint_step, tape_len: int64 [n_cells].
+        Returns (glnk, status)."""
+        import torch
+        if glnk is None:
+            glnk = torch.zeros((self.mech.n_reactions, self.ld), dtype=torch.float64, device=lam.device)
+        if status is None:
+            status = torch.empty(self.n_cells, dtype=torch.int32, device=lam.device)
+        if tape.dim() != 2 or tape.shape[0] != self.n_cells:
+            raise ValueError(f"tape must be [n_cells={self.n_cells}][stride]")
+        stride = int(tape.shape[1])
+        _check(library().mcc_adjoint_step(
+            self._h, _dptr(y0, "y0", torch.float64, self._yshape()),
+            _dptr(tape, "tape", torch.float64, (self.n_cells, stride)),
+            _dptr(tape_len, "tape_len", torch.int64, (self.n_cells,)), stride,
+            _dptr(lam, "lam", torch.float64, self._yshape()),
+            _dptr(glnk, "glnk", torch.float64, (self.mech.n_reactions, self.ld)), 1 if accumulate else 0,
+            _dptr(status, "status", torch.int32, (self.n_cells,)), _stream_ptr(stream)))
+        return glnk, status
 
     def set_rate_constants(self, k, stream=None):
         """Use caller rate constants k [R][ld] (device float64) instead of bind()'s."""

@@ -616,3 +616,95 @@ def test_vjp_pair_and_remainder(dev, oracle_mod, n, ld):
     assert np.all(np.abs(gy.cpu().numpy()[:, :n] - gy_ref) <= 1e-12 * by)
     assert np.all(np.abs(gk.cpu().numpy()[:, :n] - gk_ref) <= 1e-12 * bk)
     _check_fj(b, f.cpu().numpy()[:, :n], J.cpu().numpy()[:, :n], c.y0)
+
+
+def _device_tape(vals, N):
+    """An oracle tape (type, order, value[, z]) in the entry format of the
+    reverse-mode call ([z,] order, value, type)."""
+    out, p = [], 0
+    while p < len(vals):
+        typ, order, x = vals[p:p + 3]
+        n = N if int(typ) == 2 else 0
+        out.extend(vals[p + 3:p + 3 + n])
+        out.extend([order, x, typ])
+        p += 3 + n
+    return np.array(out)
+
+
+def _pack_tapes(tapes, pad=5):
+    stride = max(len(t) for t in tapes) + pad
+    buf = np.full((len(tapes), stride), np.nan)
+    for i, t in enumerate(tapes):
+        buf[i, :len(t)] = t
+    return buf, np.array([len(t) for t in tapes], dtype=np.int64)
+
+
+@pytest.mark.parametrize("name,n,ld", [("small10", 10, 13), ("medium10k", 40, 41)])
+def test_adjoint_step_parity(dev, oracle_mod, name, n, ld):
+    """Reverse mode of one outer step against the oracle's discrete adjoint,
+    both walking the same replayed (converged) step tapes."""
+    m, c, dt = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=ld, oracle_mod=oracle_mod)
+    N, R = m.n_species, m.n_reactions
+    k = b.o.rate_constants(c.T, c.jscale)
+    rng = np.random.default_rng(21)
+    W = np.zeros((N, n))
+    lam_ref, g_ref, tapes = np.zeros((N, n)), np.zeros((R, n)), []
+    for i in range(n):
+        y, s, _, tape = b.o.solve_taped(k[:, i], c.y0[:, i], dt)
+        assert s == 0
+        _, rt = b.o.replay(k[:, i], c.y0[:, i], tape)
+        W[:, i] = rng.normal(size=N) / np.maximum(np.abs(y), 1.0)
+        lam_ref[:, i], g_ref[:, i] = b.o.adjoint(k[:, i], c.y0[:, i], rt, W[:, i])
+        tapes.append(_device_tape(rt.values(), N))
+    buf, lens = _pack_tapes(tapes)
+    lam = _t(_padded(W, ld, 0.0), dev)
+    glnk, st = b.cells.adjoint_step(b.y_dev(), _t(buf, dev), _t(lens, dev), lam)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == mcchem.CELL_OK)
+    lam_g = lam.cpu().numpy()[:, :n]
+    g_g = glnk.cpu().numpy()[:, :n]
+    el = np.abs(lam_g - lam_ref) / np.abs(lam_ref).max(axis=0)
+    eg = np.abs(g_g - g_ref) / np.abs(g_ref).max(axis=0)
+    print(f"{name}: worst relative difference dL/dy0 {el.max():.3g}, dL/dlnk {eg.max():.3g}")
+    assert el.max() <= 1e-9 and eg.max() <= 1e-9
+
+
+def test_adjoint_step_accumulate_and_bad_tapes(dev, oracle_mod):
+    m, c, dt = synth.workload("small10", 4)
+    b = Batch(dev, m, c, ld=4, oracle_mod=oracle_mod)
+    N, R = m.n_species, m.n_reactions
+    k = b.o.rate_constants(c.T, c.jscale)
+    tapes = []
+    for i in range(4):
+        _, s, _, tape = b.o.solve_taped(k[:, i], c.y0[:, i], dt)
+        _, rt = b.o.replay(k[:, i], c.y0[:, i], tape)
+        tapes.append(_device_tape(rt.values(), N))
+    buf, lens = _pack_tapes(tapes)
+    W = np.ones((N, 4))
+    lam = _t(W, dev)
+    g1, st = b.cells.adjoint_step(b.y_dev(), _t(buf, dev), _t(lens, dev), lam)
+    lam1 = lam.clone()
+    lam2 = _t(W, dev)
+    g2 = torch.ones((R, 4), dtype=torch.float64, device=dev)
+    b.cells.adjoint_step(b.y_dev(), _t(buf, dev), _t(lens, dev), lam2, glnk=g2, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.equal(lam1, lam2) and torch.equal(g2, g1 + 1.0)
+    # cell 0: empty tape (lam unchanged, no k sensitivity); cell 1: length
+    # beyond the stride; cell 2: an entry of order 0; cell 3: no start
+    bad = buf.copy()
+    blen = lens.copy()
+    blen[0] = 0
+    blen[1] = buf.shape[1] + 1
+    assert int(bad[2, lens[2] - 1]) in (1, 2)  # the last entry is a step or a re-sampling
+    bad[2, lens[2] - 3] = 0.0  # ... of order 0
+    bad[3, 0:lens[3] - 3] = bad[3, 3:lens[3]]  # drop the start entry
+    blen[3] = lens[3] - 3
+    lam = _t(W, dev)
+    g, st = b.cells.adjoint_step(b.y_dev(), _t(bad, dev), _t(blen, dev), lam)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert list(st) == [mcchem.CELL_OK, mcchem.CELL_BAD_TAPE, mcchem.CELL_BAD_TAPE, mcchem.CELL_BAD_TAPE]
+    lam, g = lam.cpu().numpy(), g.cpu().numpy()
+    assert np.all(lam[:, 0] == 1.0) and np.all(g[:, 0] == 0.0)
+    assert np.all(np.isnan(lam[:, 1:])) and np.all(np.isnan(g[:, 1:]))
