@@ -313,6 +313,19 @@ mcc_status mcc_cells_set_rate_constants(mcc_cells *cells, const double *k, void 
 mcc_status mcc_solve_step(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
                           int32_t *cell_status, mcc_cell_stats *stats, void *stream);
 
+/* mcc_solve_step recording every cell's step tape for mcc_adjoint_step
+ * (the entry format described there): tape device doubles [n_cells]
+ * [tape_stride >= 3], tape_len device int64 [n_cells] receives the doubles
+ * written per cell, or -1 when the cell's tape did not fit in tape_stride
+ * (its solve is unaffected; mcc_adjoint_step then reports MCC_CELL_BAD_TAPE).
+ * A cell takes at most 3 + 6 * attempts + n_species * steps doubles (steps
+ * as in mcc_cell_stats; attempts = steps + rejects + newton_fails).
+ * The tape starts from the y passed in: keep a copy of it for the reverse
+ * pass.  Also in the per-launch form. */
+mcc_status mcc_solve_step_taped(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
+                                int32_t *cell_status, mcc_cell_stats *stats, double *tape, int64_t *tape_len,
+                                int64_t tape_stride, void *stream);
+
 /* The paper's Multi-cells mode (Section 3: the data of every cell grouped
  * into one structure and solved as one system; Section 5: the solver then
  * needs about as many iterations for all cells as for one): one outer step

@@ -74,6 +74,14 @@ class Tape:
     def __len__(self):
         return int(self.lib.orc_tape_size(self.h))
 
+    @classmethod
+    def from_values(cls, lib, values):
+        """A tape holding the given entries (recorded elsewhere)."""
+        t = cls(lib)
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        lib.orc_tape_assign(t.h, v.ctypes.data, len(v))
+        return t
+
     def values(self):
         """A copy of the entries: type, order, value, then for a step the N
         state values."""
@@ -116,6 +124,8 @@ class Oracle:
         L.orc_tape_size.restype = i64
         L.orc_tape_data.argtypes = [vp]
         L.orc_tape_data.restype = vp
+        L.orc_tape_assign.argtypes = [vp, vp, i64]
+        L.orc_tape_assign.restype = None
         L.orc_cell_solve_taped.argtypes = [vp, vp, vp, dbl, vp, vp, vp]
         L.orc_cell_solve_taped.restype = ctypes.c_int
         L.orc_cell_replay.argtypes = [vp, vp, vp, vp, vp, vp]

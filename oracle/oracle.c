@@ -684,6 +684,12 @@ void orc_tape_free(orc_tape *t)
 int64_t orc_tape_size(const orc_tape *t) { return (int64_t)t->n; }
 /* The tape's entries: type, order, value, then (a step) the N state values. */
 const double *orc_tape_data(const orc_tape *t) { return t->v; }
+/* Replace a tape's entries by n given values (a tape recorded elsewhere). */
+void orc_tape_assign(orc_tape *t, const double *v, int64_t n)
+{
+    t->n = 0;
+    for (int64_t i = 0; i < n; ++i) tape_push(t, v[i]);
+}
 
 /* One outer step of one cell as cell_solve, recording the tape.  kc [R],
  * y [N] in/out. */

@@ -1,4 +1,4 @@
-"""Reverse-mode differentiation of f through the library's kernels.
+"""Reverse-mode differentiation through the library's kernels.
 
 `deriv(cells, y, lnk)` returns f(y; k = exp(lnk)) for every cell of a batch,
 as a torch tensor that autograd can differentiate with respect to y and the
@@ -6,6 +6,12 @@ log rate constants: the backward pass is one launch of the library's VJP
 kernel (mcc_calc_vjp): dL/dy = J^T g and dL/d ln k_j = r_j sum_i nu_ij g_i for
 the incoming gradient g = dL/df.  The exp of the parameter is torch
 arithmetic on the parameter tensor; f and both products run in the library.
+
+`solve_step(cells, y0, lnk, dt)` is one outer step of the BDF solver,
+y(dt) for every cell, differentiable with respect to y0 and ln k: the
+forward pass records each cell's step tape (mcc_solve_step_taped) and the
+backward pass is the discrete adjoint of that step sequence
+(mcc_adjoint_step), both in the library.
 """
 from __future__ import annotations
 
@@ -37,3 +43,45 @@ class _Deriv(torch.autograd.Function):
 def deriv(cells: "mcchem.Cells", y: torch.Tensor, lnk: torch.Tensor) -> torch.Tensor:
     """f [N][ld] at y [N][ld] with rate constants exp(lnk) [R][ld]."""
     return _Deriv.apply(y, lnk, cells)
+
+
+class _SolveStep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y0, lnk, cells, dt, opts, stride):
+        k = torch.exp(lnk).contiguous()
+        cells.set_rate_constants(k)
+        y0 = y0.contiguous()
+        while True:
+            y = y0.clone()
+            tape = torch.empty((cells.n_cells, stride), dtype=torch.float64, device=y0.device)
+            tape_len = torch.empty(cells.n_cells, dtype=torch.int64, device=y0.device)
+            status, _ = cells.step_taped(y, dt, tape, tape_len, opts)
+            if cells.n_cells == 0 or int(tape_len.min()) >= 0:
+                break
+            stride *= 2  # a tape did not fit: the same step again with room for it
+        ctx.save_for_backward(y0, k, tape, tape_len)
+        ctx.cells = cells
+        ctx.status = status
+        return y
+
+    @staticmethod
+    def backward(ctx, g):
+        y0, k, tape, tape_len = ctx.saved_tensors
+        cells = ctx.cells
+        cells.set_rate_constants(k)
+        lam = g.contiguous().clone()
+        glnk, status = cells.adjoint_step(y0, tape, tape_len, lam)
+        if int((status != mcchem.CELL_OK).sum()) > 0:
+            raise mcchem.MccError("reverse-mode step failed for some cells: "
+                                  f"{torch.unique(status).tolist()}")
+        return lam, glnk, None, None, None, None
+
+
+def solve_step(cells: "mcchem.Cells", y0: torch.Tensor, lnk: torch.Tensor, dt: float,
+               opts: "mcchem.SolverOpts | None" = None, tape_stride: int | None = None) -> torch.Tensor:
+    """y(dt) [N][ld] from y0 [N][ld] with rate constants exp(lnk) [R][ld].
+    tape_stride: doubles of step tape per cell (default room for about 256
+    steps; doubled and the step redone when a tape does not fit)."""
+    N = cells.mech.n_species
+    stride = tape_stride or 3 + 256 * (N + 12)
+    return _SolveStep.apply(y0, lnk, cells, dt, opts, stride)

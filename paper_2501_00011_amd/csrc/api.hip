@@ -833,8 +833,30 @@ mcc_status mcc_adjoint_step(const mcc_cells *c, const double *y0, const double *
     return ok();
 }
 
+static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
+                             mcc_cell_stats *stats, double *tape, int64_t *tape_len, int64_t tape_stride, void *stream);
+
 mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
                           mcc_cell_stats *stats, void *stream)
+{
+    return solve_step(c, y, dt, opts, cell_status, stats, nullptr, nullptr, 0, stream);
+}
+
+mcc_status mcc_solve_step_taped(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
+                                mcc_cell_stats *stats, double *tape, int64_t *tape_len, int64_t tape_stride,
+                                void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (tape_stride < 3) return set_error(MCC_ERR_INVALID_ARG, "tape_stride must hold at least the start entry (3)");
+    if (c->n_cells > 0 && (!tape || !tape_len)) return set_error(MCC_ERR_INVALID_ARG, "tape and tape_len must not be null");
+    const mcc_mech *m = c->mech;
+    if (!m->adj.unavailable.empty()) return set_error(MCC_ERR_MECH, m->adj.unavailable);
+    if (!adjoint_shape_supported(m->t.NS, m->t.M)) return set_error(MCC_ERR_MECH, "no taping solver for this mechanism's shape");
+    return solve_step(c, y, dt, opts, cell_status, stats, tape, tape_len, tape_stride, stream);
+}
+
+static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,
+                             mcc_cell_stats *stats, double *tape, int64_t *tape_len, int64_t tape_stride, void *stream)
 {
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
     if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
@@ -851,6 +873,9 @@ mcc_status mcc_solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_o
     const mcc_mech *m = c->mech;
     DeviceGuard g(m->device);
     SolveParams p = solve_params(c, y, dt, o, cell_status, stats);
+    p.tape = tape;
+    p.tape_len = tape_len;
+    p.tape_stride = tape_stride;
     if (o.steps_per_launch <= 0) {  // the whole outer step in one launch
         hipError_t e = launch_solve(p, m->t.NS, m->t.M, (hipStream_t)stream);
         if (e != hipSuccess) return hip_error(e, "solver kernel launch");

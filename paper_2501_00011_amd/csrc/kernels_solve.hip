@@ -548,7 +548,8 @@ struct GridSum {
 template <int NS, int M>
 constexpr int kSolveWaves = (NS <= 2 && M <= 48) ? 2 : 1;
 
-template <int NS, int M, bool MC>
+// MC: Multi-cells (one system over all cells); TAPE: record the step tape.
+template <int NS, int M, bool MC, bool TAPE = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void bdf_kernel(SolveParams p)
 {
     extern __shared__ double smem[];
@@ -599,6 +600,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
     double h = 0.0, t = 0.0;
     int order = 1, n_equal = 0, attempts = 0;
     bool bad = false;
+    // step tape (reverse mode): start, re-samplings and accepted steps with
+    // their states, in time order; tpos = doubles written, -1 once one did not fit
+    double *tp = TAPE && !MC ? p.tape + cell * p.tape_stride : nullptr;
+    int64_t tpos = TAPE && resumed ? (int64_t)st_s[15] : 0;
+    auto record = [&](int type, int ord, double x, bool with_state) {
+        if (!TAPE || tpos < 0) return;
+        if (tpos + 3 + (with_state ? N : 0) > p.tape_stride) {
+            tpos = -1;
+            return;
+        }
+        if (with_state) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (C.valid(s)) tp[tpos + sp[s]] = D[0][s];
+            tpos += N;
+        }
+        if (lane == 0) {
+            tp[tpos] = ord;
+            tp[tpos + 1] = x;
+            tp[tpos + 2] = type;
+        }
+        tpos += 3;
+    };
     if (resumed) {
         t = st_s[2];
         h = st_s[3];
@@ -647,6 +671,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
         if (!bad) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) D[1][s] = h * f[s];
+            record(0, 0, h, false);
         }
     }
 
@@ -670,8 +695,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
                 attempts++;
                 landing = false;
                 if (h >= dt - t) {
-                    const double hn = dt - t;
-                    rescale<NS>(D, order, hn / h, C.tm);
+                    const double hn = dt - t, rho = hn / h;
+                    rescale<NS>(D, order, rho, C.tm);
+                    record(1, order, rho, false);
                     h = hn;
                     n_equal = 0;
                     landing = true;
@@ -728,6 +754,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
                 if (!converged) {
                     newton_fails++;
                     rescale<NS>(D, order, o.fac_newton_fail, C.tm);
+                    record(1, order, o.fac_newton_fail, false);
                     h *= o.fac_newton_fail;
                     n_equal = 0;
                     if (h < o.h_min_rel * dt || t + h == t) {
@@ -743,6 +770,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
                     double fac = o.safety * step_pow(err_norm, -1.0 / (order + 1));
                     if (fac < o.fac_min) fac = o.fac_min;
                     rescale<NS>(D, order, fac, C.tm);
+                    record(1, order, fac, false);
                     h *= fac;
                     n_equal = 0;
                     if (h < o.h_min_rel * dt || t + h == t) {
@@ -770,6 +798,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
                 for (int j = kMaxOrder; j >= 0; --j)
                     D[j][s] = j <= order ? D[j][s] + D[j + 1][s] : D[j][s];
             }
+            record(2, order, h / bdf_gamma(order), true);  // the step's state z = the new D_0
             n_equal++;
             if (t >= dt) break;
             if (n_equal < order + 1) continue;
@@ -808,6 +837,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
             if (fac > o.fac_max) fac = o.fac_max;
             order = new_order;
             rescale<NS>(D, order, fac, C.tm);
+            record(1, order, fac, false);
             h *= fac;
             n_equal = 0;
         }
@@ -834,6 +864,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
             st_s[12] = jac_evals;
             st_s[13] = lu_count;
             st_s[14] = status;
+            if (TAPE) st_s[15] = (double)tpos;
             atomicAdd(p.pending, 1);
         }
         return;
@@ -856,6 +887,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
     }
     if (lane == 0) {
         p.status[cell] = status;
+        if (TAPE) p.tape_len[cell] = tpos;
         if (p.stats) {
             mcc_cell_stats st;
             st.steps = steps;
@@ -1064,6 +1096,10 @@ __global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParam
 // Multi-cells instantiations (small and 72-species class mechanisms).
 #define MCC_MULTICELL_VARIANTS(X) X(1, 0) X(2, 0) X(2, 48)
 
+// Reverse mode (the taping forward solver and the adjoint kernel), for the
+// shapes of small and 72-species class mechanisms.
+#define MCC_ADJOINT_VARIANTS(X) X(1, 0) X(2, 0) X(1, 32) X(2, 32) X(1, 48) X(2, 48)
+
 hipError_t prepare_solve_kernels(int max_lds_bytes)
 {
     hipError_t e = hipSuccess;
@@ -1079,6 +1115,12 @@ hipError_t prepare_solve_kernels(int max_lds_bytes)
                                 max_lds_bytes);
     MCC_MULTICELL_VARIANTS(MCC_SET_LDS_MC)
 #undef MCC_SET_LDS_MC
+#define MCC_SET_LDS_TAPE(ns, m)                                                                                     \
+    if (e == hipSuccess)                                                                                           \
+        e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                max_lds_bytes);
+    MCC_ADJOINT_VARIANTS(MCC_SET_LDS_TAPE)
+#undef MCC_SET_LDS_TAPE
     return e;
 }
 
@@ -1094,6 +1136,16 @@ hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
     if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)p.n_cells), block(kWave);
     const size_t lds = (size_t)p.lds_doubles * sizeof(double);
+    if (p.tape) {
+#define MCC_LAUNCH_TAPE(ns, m)                                                          \
+    if (NS == ns && M == m) {                                                           \
+        hipLaunchKernelGGL((bdf_kernel<ns, m, false, true>), grid, block, lds, s, p); \
+        return hipGetLastError();                                                       \
+    }
+        MCC_ADJOINT_VARIANTS(MCC_LAUNCH_TAPE)
+#undef MCC_LAUNCH_TAPE
+        return hipErrorInvalidValue;
+    }
 #define MCC_LAUNCH(ns, m)                                                         \
     if (NS == ns && M == m) {                                                     \
         hipLaunchKernelGGL((bdf_kernel<ns, m, false>), grid, block, lds, s, p); \
@@ -1103,9 +1155,6 @@ hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
 #undef MCC_LAUNCH
     return hipErrorInvalidValue;
 }
-
-// Reverse-mode kernels for the shapes of small and 72-species class mechanisms.
-#define MCC_ADJOINT_VARIANTS(X) X(1, 0) X(2, 0) X(1, 32) X(2, 32) X(1, 48) X(2, 48)
 
 hipError_t prepare_adjoint_kernels(int max_lds_bytes)
 {

@@ -188,6 +188,12 @@ struct SolveParams {
     int32_t call_id;   // the outer step this launch belongs to
     // Multi-cells (one system over all cells): [2][n_cells] reduction slots
     double *mc_slots;
+    // step tape for reverse mode (null: none): [n_cells][tape_stride]
+    // doubles in the entry format of AdjointParams, doubles used per cell in
+    // tape_len (-1: the tape did not fit)
+    double *tape;
+    int64_t *tape_len;
+    int64_t tape_stride;
 };
 constexpr int kStateScalars = 16;
 

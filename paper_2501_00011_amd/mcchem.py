@@ -78,6 +78,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_adjoint_step": ([vp, vp, vp, vp, i64, vp, vp, i32, vp, vp], ctypes.c_int),
+        "mcc_solve_step_taped": ([vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
@@ -380,6 +381,25 @@ class Cells:
         _check(library().mcc_solve_step(self._h, _dptr(y, "y", torch.float64, self._yshape()), float(dt), op,
                                         _dptr(status, "status", torch.int32, (self.n_cells,)), sp,
                                         _stream_ptr(stream)))
+        return status, stats
+
+    def step_taped(self, y, dt, tape, tape_len, opts: SolverOpts | None = None, status=None, stats=None,
+                   stream=None):
+        """step() recording each cell's step tape for adjoint_step: tape
+        float64 [n_cells][stride], tape_len int64 [n_cells] (-1: did not fit)."""
+        import torch
+        if status is None:
+            status = torch.empty(self.n_cells, dtype=torch.int32, device=y.device)
+        if tape.dim() != 2 or tape.shape[0] != self.n_cells:
+            raise ValueError(f"tape must be [n_cells={self.n_cells}][stride]")
+        stride = int(tape.shape[1])
+        op = ctypes.addressof(opts) if opts is not None else None
+        sp = _dptr(stats, "stats", torch.uint8, (self.n_cells, STATS_DTYPE.itemsize)) if stats is not None else None
+        _check(library().mcc_solve_step_taped(
+            self._h, _dptr(y, "y", torch.float64, self._yshape()), float(dt), op,
+            _dptr(status, "status", torch.int32, (self.n_cells,)), sp,
+            _dptr(tape, "tape", torch.float64, (self.n_cells, stride)),
+            _dptr(tape_len, "tape_len", torch.int64, (self.n_cells,)), stride, _stream_ptr(stream)))
         return status, stats
 
     def step_multicell(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, stream=None):

@@ -17,6 +17,8 @@ torch = pytest.importorskip("torch")
 
 from paper_2501_00011_amd import mcchem, synth  # noqa: E402
 
+import tape_format  # noqa: E402
+
 EPS = np.finfo(np.float64).eps
 
 
@@ -618,27 +620,6 @@ def test_vjp_pair_and_remainder(dev, oracle_mod, n, ld):
     _check_fj(b, f.cpu().numpy()[:, :n], J.cpu().numpy()[:, :n], c.y0)
 
 
-def _device_tape(vals, N):
-    """An oracle tape (type, order, value[, z]) in the entry format of the
-    reverse-mode call ([z,] order, value, type)."""
-    out, p = [], 0
-    while p < len(vals):
-        typ, order, x = vals[p:p + 3]
-        n = N if int(typ) == 2 else 0
-        out.extend(vals[p + 3:p + 3 + n])
-        out.extend([order, x, typ])
-        p += 3 + n
-    return np.array(out)
-
-
-def _pack_tapes(tapes, pad=5):
-    stride = max(len(t) for t in tapes) + pad
-    buf = np.full((len(tapes), stride), np.nan)
-    for i, t in enumerate(tapes):
-        buf[i, :len(t)] = t
-    return buf, np.array([len(t) for t in tapes], dtype=np.int64)
-
-
 @pytest.mark.parametrize("name,n,ld", [("small10", 10, 13), ("medium10k", 40, 41)])
 def test_adjoint_step_parity(dev, oracle_mod, name, n, ld):
     """Reverse mode of one outer step against the oracle's discrete adjoint,
@@ -656,8 +637,8 @@ def test_adjoint_step_parity(dev, oracle_mod, name, n, ld):
         _, rt = b.o.replay(k[:, i], c.y0[:, i], tape)
         W[:, i] = rng.normal(size=N) / np.maximum(np.abs(y), 1.0)
         lam_ref[:, i], g_ref[:, i] = b.o.adjoint(k[:, i], c.y0[:, i], rt, W[:, i])
-        tapes.append(_device_tape(rt.values(), N))
-    buf, lens = _pack_tapes(tapes)
+        tapes.append(tape_format.to_device(rt.values(), N))
+    buf, lens = tape_format.pack(tapes)
     lam = _t(_padded(W, ld, 0.0), dev)
     glnk, st = b.cells.adjoint_step(b.y_dev(), _t(buf, dev), _t(lens, dev), lam)
     torch.cuda.synchronize()
@@ -679,8 +660,8 @@ def test_adjoint_step_accumulate_and_bad_tapes(dev, oracle_mod):
     for i in range(4):
         _, s, _, tape = b.o.solve_taped(k[:, i], c.y0[:, i], dt)
         _, rt = b.o.replay(k[:, i], c.y0[:, i], tape)
-        tapes.append(_device_tape(rt.values(), N))
-    buf, lens = _pack_tapes(tapes)
+        tapes.append(tape_format.to_device(rt.values(), N))
+    buf, lens = tape_format.pack(tapes)
     W = np.ones((N, 4))
     lam = _t(W, dev)
     g1, st = b.cells.adjoint_step(b.y_dev(), _t(buf, dev), _t(lens, dev), lam)
@@ -708,3 +689,109 @@ def test_adjoint_step_accumulate_and_bad_tapes(dev, oracle_mod):
     lam, g = lam.cpu().numpy(), g.cpu().numpy()
     assert np.all(lam[:, 0] == 1.0) and np.all(g[:, 0] == 0.0)
     assert np.all(np.isnan(lam[:, 1:])) and np.all(np.isnan(g[:, 1:]))
+
+
+@pytest.mark.parametrize("name,n,K", [("small10", 10, 0), ("medium10k", 48, 0), ("medium10k", 48, 5)])
+def test_taped_solve_and_gpu_adjoint(dev, oracle_mod, name, n, K):
+    """The taping solver gives the same y as the plain one (bit for bit); its
+    tapes hold the steps the stats count; the oracle's adjoint on those tapes
+    agrees with the GPU reverse mode (same states z), and, after the oracle
+    replays each tape to convergence, to the Newton tolerance."""
+    m, c, dt = synth.workload(name, n)
+    b = Batch(dev, m, c, ld=n + 1, oracle_mod=oracle_mod)
+    N = m.n_species
+    opts = mcchem.default_opts(steps_per_launch=K)
+    y_plain = b.y_dev()
+    st_plain, stats_plain = b.cells.step(y_plain, dt, opts)
+    y0 = b.y_dev()
+    y = y0.clone()
+    sp = mcchem.stats_numpy(stats_plain)
+    attempts = sp["steps"] + sp["rejects"] + sp["newton_fails"]
+    stride = int((3 + 6 * attempts + N * sp["steps"]).max())  # the documented bound
+    tape = torch.full((n, stride), float("nan"), dtype=torch.float64, device=dev)
+    tlen = torch.empty(n, dtype=torch.int64, device=dev)
+    stats = torch.empty_like(stats_plain)
+    st, _ = b.cells.step_taped(y, dt, tape, tlen, opts, stats=stats)
+    torch.cuda.synchronize()
+    assert np.all(tlen.cpu().numpy() >= 0)
+    assert torch.equal(y[:, :n], y_plain[:, :n]) and torch.equal(st, st_plain) and torch.equal(stats, stats_plain)
+    assert np.all(st.cpu().numpy() == 0)
+    stn = mcchem.stats_numpy(stats)
+    tv, tl = tape.cpu().numpy(), tlen.cpu().numpy()
+    k = b.o.rate_constants(c.T, c.jscale)
+    rng = np.random.default_rng(5)
+    W = rng.normal(size=(N, n)) / np.maximum(np.abs(y.cpu().numpy()[:, :n]), 1.0)
+    lam = _t(_padded(W, n + 1, 0.0), dev)
+    glnk, ast = b.cells.adjoint_step(y0, tape, tlen, lam)
+    torch.cuda.synchronize()
+    assert np.all(ast.cpu().numpy() == 0)
+    lam_g, g_g = lam.cpu().numpy()[:, :n], glnk.cpu().numpy()[:, :n]
+    worst_same, worst_replay = 0.0, 0.0
+    for i in range(n):
+        ov = tape_format.to_oracle(tv[i, :tl[i]], N)
+        assert tape_format.count_steps(ov, N) == stn["steps"][i]  # a step entry per accepted step
+        t = oracle_mod.Tape.from_values(b.o.lib, ov)
+        lr, gr = b.o.adjoint(k[:, i], c.y0[:, i], t, W[:, i])
+        worst_same = max(worst_same, np.abs(lam_g[:, i] - lr).max() / np.abs(lr).max(),
+                         np.abs(g_g[:, i] - gr).max() / np.abs(gr).max())
+        _, rt = b.o.replay(k[:, i], c.y0[:, i], t)
+        lr2, gr2 = b.o.adjoint(k[:, i], c.y0[:, i], rt, W[:, i])
+        worst_replay = max(worst_replay, np.abs(lam_g[:, i] - lr2).max() / np.abs(lr2).max(),
+                           np.abs(g_g[:, i] - gr2).max() / np.abs(gr2).max())
+    print(f"{name} K={K}: worst relative difference, same tape {worst_same:.3g}, replayed {worst_replay:.3g}")
+    assert worst_same <= 1e-9
+    assert worst_replay <= 1e-4
+
+
+def test_taped_solve_overflow_marks_tape(dev, oracle_mod):
+    m, c, dt = synth.workload("small10", 3)
+    b = Batch(dev, m, c)
+    y = b.y_dev()
+    tape = torch.zeros((3, 20), dtype=torch.float64, device=dev)
+    tlen = torch.zeros(3, dtype=torch.int64, device=dev)
+    st, _ = b.cells.step_taped(y, dt, tape, tlen)
+    y_plain = b.y_dev()
+    b.cells.step(y_plain, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_plain) and np.all(st.cpu().numpy() == 0)
+    assert np.all(tlen.cpu().numpy() == -1)
+    lam = torch.ones_like(y)
+    _, ast = b.cells.adjoint_step(b.y_dev(), tape, tlen, lam)
+    torch.cuda.synchronize()
+    assert np.all(ast.cpu().numpy() == mcchem.CELL_BAD_TAPE)
+
+
+def test_autograd_solve_step(dev, oracle_mod):
+    """torch autograd through one outer step (taped forward, reverse-mode
+    backward in the library) against the oracle's adjoint of the same tapes,
+    for the log loss of the adjoint workload summed over cells."""
+    from paper_2501_00011_amd import autograd
+    m, c, dt = synth.workload("medium10k", 16)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    N = m.n_species
+    k_gpu = b.cells.rate_constants().clone()
+    lnk = torch.log(k_gpu).requires_grad_(True)
+    y0 = b.y_dev().requires_grad_(True)
+    y = autograd.solve_step(b.cells, y0, lnk, dt, tape_stride=50)  # forces the regrow path
+    atol = 1.0
+    target = torch.from_numpy(c.y0).to(dev) * 0.5 + 10.0
+    loss = ((torch.log(y + atol) - torch.log(target + atol)) ** 2).sum()
+    loss.backward()
+    gl = lnk.grad.cpu().numpy()
+    gy = y0.grad.cpu().numpy()
+    # the oracle on the tapes the forward pass recorded (the Function keeps them)
+    yd = y.detach().cpu().numpy()
+    W = 2 * (np.log(yd + atol) - np.log(target.cpu().numpy() + atol)) / (yd + atol)
+    k = k_gpu.cpu().numpy()
+    tape = torch.empty((16, 3 + 2000 * (N + 6)), dtype=torch.float64, device=dev)
+    tlen = torch.empty(16, dtype=torch.int64, device=dev)
+    yy = b.y_dev()
+    b.cells.step_taped(yy, dt, tape, tlen)
+    torch.cuda.synchronize()
+    assert torch.equal(yy, y.detach())
+    tv, tl = tape.cpu().numpy(), tlen.cpu().numpy()
+    for i in range(16):
+        t = oracle_mod.Tape.from_values(b.o.lib, tape_format.to_oracle(tv[i, :tl[i]], N))
+        lr, gr = b.o.adjoint(k[:, i], c.y0[:, i], t, W[:, i])
+        assert np.abs(gy[:, i] - lr).max() <= 1e-9 * np.abs(lr).max()
+        assert np.abs(gl[:, i] - gr).max() <= 1e-9 * np.abs(gr).max()
