@@ -75,6 +75,12 @@ def parse():
                     help="time the paper's Derivative kernel (thread per reaction, atomic adds; record and "
                          "inverted reaction data; with and without per-call host-device copies) beside "
                          "this library's f kernel, and exit")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="reverse mode of the outer step: taped forward solve + adjoint kernel (one JSON line "
+                         "with their times beside the plain solve)")
+    ap.add_argument("--gradient", action="store_true",
+                    help="gradient of the log loss with respect to log A over 10 x 60 s outer steps "
+                         "(checkpointed forward + reverse mode; one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -261,6 +267,174 @@ def bench_ablation(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Forward outer step with its step tape, then the reverse pass
+    (mcc_adjoint_step) for dL/dy0 and dL/d ln k, each timed with events on
+    the launch stream; the plain forward step beside them."""
+    import numpy as np
+    import torch
+
+    from paper_2501_00011_amd import mcchem, synth
+    m, c, dt = synth.workload(args.workload, args.cells)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mech = mcchem.Mechanism(m, device=0)
+    C, N, R = c.n_cells, m.n_species, m.n_reactions
+    cells = mcchem.Cells(mech, C)
+    cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
+    y0 = torch.from_numpy(c.y0).to(dev)
+    y = torch.empty_like(y0)
+    status = torch.empty(C, dtype=torch.int32, device=dev)
+    stats = torch.empty((C, mcchem.STATS_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    opts = mcchem.default_opts()
+    y.copy_(y0)
+    cells.step(y, dt, opts, status, stats, stream=stream)
+    sn = mcchem.stats_numpy(stats)
+    attempts = sn["steps"] + sn["rejects"] + sn["newton_fails"]
+    stride = int((3 + 6 * attempts + N * sn["steps"]).max())
+    tape = torch.empty((C, stride), dtype=torch.float64, device=dev)
+    tlen = torch.empty(C, dtype=torch.int64, device=dev)
+    lam = torch.empty_like(y0)
+    w = torch.ones_like(y0)
+    glnk = torch.empty((R, C), dtype=torch.float64, device=dev)
+    ast = torch.empty(C, dtype=torch.int32, device=dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            ts.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ts]))  # ms
+
+    def plain():
+        y.copy_(y0)
+        cells.step(y, dt, opts, status, stats, stream=stream)
+
+    def taped():
+        y.copy_(y0)
+        cells.step_taped(y, dt, tape, tlen, opts, status, stats, stream=stream)
+
+    def reverse():
+        lam.copy_(w)
+        cells.adjoint_step(y0, tape, tlen, lam, glnk, status=ast, stream=stream)
+
+    reps = max(args.steps, 1)
+    t_plain = timed(plain, reps)
+    t_taped = timed(taped, reps)
+    t_rev = timed(reverse, reps)
+    tl = tlen.cpu().numpy()
+    ok = int(((ast.cpu().numpy() == 0) & (status.cpu().numpy() == 0)).sum())
+    oc = mech.op_counts()
+    steps = sn["steps"].astype(np.int64)
+    # reverse pass per accepted step: Newton matrix, factorisation, one
+    # solve, the rates twice (Jacobian partials and rates) -- counted as
+    # the forward kernel's per-operation flops
+    rev_flops = float(np.sum(steps * (oc["newton_matrix_flops"] + oc["lu_flops"] + oc["solve_flops"]
+                                      + oc["deriv_flops"])))
+    out = {"metric": "reverse mode of one outer step (ms per launch, mean)",
+           "workload": f"{N} species / {R} reactions, {C} cells, one {dt:g} s BDF step",
+           "plain_forward_ms": round(t_plain, 3), "taped_forward_ms": round(t_taped, 3),
+           "reverse_ms": round(t_rev, 3), "taping_overhead": t_taped / t_plain - 1.0,
+           "reverse_over_forward": t_rev / t_plain,
+           "forward_plus_reverse_cell_steps_per_s": C / ((t_taped + t_rev) / 1e3),
+           "tape_bytes_mean_per_cell": float(tl.mean() * 8), "tape_stride": stride,
+           "cells_ok": ok, "steps_mean": float(steps.mean()),
+           "reverse_tflops": rev_flops / (t_rev / 1e3) / 1e12}
+    if not args.no_cpu:
+        import oracle
+        o = oracle.Oracle(m)
+        k = o.rate_constants(c.T, c.jscale)
+        t0 = time.perf_counter()
+        n = 0
+        while n < C and (n < 2 or time.perf_counter() - t0 < args.cpu_seconds):
+            _, _, _, tp = o.solve_taped(k[:, n], c.y0[:, n], dt)
+            o.adjoint(k[:, n], c.y0[:, n], tp, np.ones(N))
+            n += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n / el, "unit": "cells/s (taped forward + adjoint)", "cores": 1,
+                               "kind": "oracle", "sample": f"first {n} cells, one thread"}
+        out["gpu_cells_per_s"] = C / ((t_taped + t_rev) / 1e3)
+    print(json.dumps(out), flush=True)
+
+
+def bench_gradient(args):
+    """d L / d log A for L = sum over cells and species of
+    (ln(y + atol) - ln(y_target + atol))^2 after 10 outer steps of 60 s, the
+    target being the forward result with log A perturbed by N(0, 0.1^2)
+    (seed 5005): forward with checkpoints, then the reverse sweep (each
+    outer step re-run with its tape and reversed), timed on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2501_00011_amd import autograd, mcchem, synth
+    m, c, dt = synth.workload("adjoint10k" if args.workload == "medium10k" else args.workload, args.cells)
+    n_out = 10
+    dev = torch.device("cuda:0")
+    mech = mcchem.Mechanism(m, device=0)
+    C, N, R = c.n_cells, m.n_species, m.n_reactions
+    cells = mcchem.Cells(mech, C)
+    cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
+    k = cells.rate_constants().clone()
+    y0 = torch.from_numpy(c.y0).to(dev)
+    atol = mcchem.default_opts().atol
+    with torch.no_grad():
+        pert = torch.from_numpy(np.random.default_rng(5005).normal(0.0, 0.1, R)).to(dev)
+        target = autograd.integrate(cells, y0, torch.log(k) + pert[:, None], dt, n_out)
+
+    def run():
+        lnk = torch.log(k).requires_grad_(True)
+        y = autograd.integrate(cells, y0, lnk, dt, n_out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = ((torch.log(y + atol) - torch.log(target + atol)) ** 2).sum()
+        loss.backward()
+        gA = lnk.grad.sum(dim=1)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1, gA, float(loss.detach())
+
+    for _ in range(args.warmup):
+        run()
+    ts = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        t_bwd, gA, loss = run()
+        ts.append((time.perf_counter() - t0, t_bwd))
+    tot = float(np.mean([a for a, _ in ts]))
+    bwd = float(np.mean([b for _, b in ts]))
+    out = {"metric": "gradient of the log loss wrt log A, 10 x 60 s forward + reverse (s per gradient)",
+           "workload": f"{N} species / {R} reactions, {C} cells, 10 outer steps of {dt:g} s",
+           "value": tot, "unit": "s", "higher_is_better": False,
+           "forward_s": tot - bwd, "reverse_s": bwd, "reverse_over_forward": bwd / (tot - bwd),
+           "cell_gradients_per_s": C / tot, "loss": loss,
+           "grad_logA_norm": float(gA.norm()), "grad_logA_first4": [float(v) for v in gA[:4]]}
+    if not args.no_cpu:
+        import oracle
+        o = oracle.Oracle(m)
+        kc = o.rate_constants(c.T, c.jscale)
+        t0 = time.perf_counter()
+        n = 0
+        while n < C and (n < 1 or time.perf_counter() - t0 < args.cpu_seconds):
+            y, tapes = c.y0[:, n].copy(), []
+            for _ in range(n_out):
+                ys = y.copy()
+                y, _, _, tp = o.solve_taped(kc[:, n], ys, dt)
+                tapes.append((ys, tp))
+            lam = np.ones(N)
+            for ys, tp in reversed(tapes):
+                lam, _ = o.adjoint(kc[:, n], ys, tp, lam)
+            n += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n / el, "unit": "cell gradients/s (10 x 60 s forward + adjoint)",
+                               "cores": 1, "kind": "oracle", "sample": f"first {n} cells, one thread"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -275,6 +449,12 @@ def main():
         return
     if args.workload == "mixed100k":
         bench_mixed(args)
+        return
+    if args.adjoint:
+        bench_adjoint(args)
+        return
+    if args.gradient:
+        bench_gradient(args)
         return
     import numpy as np
     import torch

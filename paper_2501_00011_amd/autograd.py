@@ -85,3 +85,61 @@ def solve_step(cells: "mcchem.Cells", y0: torch.Tensor, lnk: torch.Tensor, dt: f
     N = cells.mech.n_species
     stride = tape_stride or 3 + 256 * (N + 12)
     return _SolveStep.apply(y0, lnk, cells, dt, opts, stride)
+
+
+def _tape_bound(stats, n_species: int) -> int:
+    """Doubles of step tape the largest cell of an outer step needs (the
+    bound of mcc_solve_step_taped: 3 + 6 attempts + n_species steps)."""
+    sn = mcchem.stats_numpy(stats)
+    attempts = sn["steps"].astype("int64") + sn["rejects"] + sn["newton_fails"]
+    return int((3 + 6 * attempts + n_species * sn["steps"].astype("int64")).max()) if len(sn) else 3
+
+
+class _Integrate(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y0, lnk, cells, dt, n_steps, opts):
+        k = torch.exp(lnk).contiguous()
+        cells.set_rate_constants(k)
+        N = cells.mech.n_species
+        y = y0.contiguous().clone()
+        checkpoints, stride = [], 3
+        stats = None
+        for _ in range(n_steps):
+            checkpoints.append(y.clone())  # the state each outer step starts from
+            status, stats = cells.step(y, dt, opts, stats=stats)
+            stride = max(stride, _tape_bound(stats, N))
+        ctx.save_for_backward(k, *checkpoints)
+        ctx.cells, ctx.dt, ctx.opts, ctx.stride = cells, dt, opts, stride
+        ctx.status = status
+        return y
+
+    @staticmethod
+    def backward(ctx, g):
+        k, *checkpoints = ctx.saved_tensors
+        cells = ctx.cells
+        cells.set_rate_constants(k)
+        C = cells.n_cells
+        lam = g.contiguous().clone()
+        glnk = torch.zeros((cells.mech.n_reactions, cells.ld), dtype=torch.float64, device=g.device)
+        tape = torch.empty((C, ctx.stride), dtype=torch.float64, device=g.device)
+        tlen = torch.empty(C, dtype=torch.int64, device=g.device)
+        status = torch.empty(C, dtype=torch.int32, device=g.device)
+        for y_start in reversed(checkpoints):
+            # recompute the outer step's tape from its checkpoint (the solver is
+            # deterministic: the same steps as the forward pass), then reverse it
+            y = y_start.clone()
+            cells.step_taped(y, ctx.dt, tape, tlen, ctx.opts)
+            cells.adjoint_step(y_start, tape, tlen, lam, glnk, accumulate=True, status=status)
+            if int((status != mcchem.CELL_OK).sum()) > 0:
+                raise mcchem.MccError(f"reverse-mode step failed for some cells: {torch.unique(status).tolist()}")
+        return lam, glnk, None, None, None, None
+
+
+def integrate(cells: "mcchem.Cells", y0: torch.Tensor, lnk: torch.Tensor, dt: float, n_steps: int,
+              opts: "mcchem.SolverOpts | None" = None) -> torch.Tensor:
+    """y after n_steps outer steps of length dt, differentiable with respect
+    to y0 [N][ld] and ln k [R][ld].  The forward pass keeps only the state at
+    the start of every outer step (checkpoints); the backward pass re-runs
+    each outer step from its checkpoint with its step tape and reverses it,
+    last step first, accumulating d L / d ln k."""
+    return _Integrate.apply(y0, lnk, cells, dt, n_steps, opts)
