@@ -121,9 +121,22 @@ def cpu_baseline(m, c, dt, target_s):
         failed += int((st != 0).sum())
         n += len(sel)
         start += len(sel)
+    # the same oracle on one thread (the paper's single-thread baseline), a
+    # shorter sample of the next cells
+    n1, wall1 = 0, 0.0
+    while wall1 < target_s / 4 and start < c.n_cells:
+        sel = np.arange(start, min(c.n_cells, start + 4))
+        k = o.rate_constants(c.T[sel], c.jscale[sel])
+        t0 = time.perf_counter()
+        o.solve(k, c.y0[:, sel], dt, n_threads=1)
+        wall1 += time.perf_counter() - t0
+        n1 += len(sel)
+        start += len(sel)
     return {"value": n / wall, "unit": "cell-timesteps/s", "cores": threads, "kind": "oracle",
             "sample": f"cells {warm}..{warm + n - 1} of {c.n_cells}, one {dt:g} s step each, "
-                      f"{wall:.1f} s wall on {threads} OpenMP threads ({failed} failed)"}
+                      f"{wall:.1f} s wall on {threads} OpenMP threads ({failed} failed)",
+            "value_1_thread": n1 / wall1 if wall1 > 0 else None,
+            "sample_1_thread": f"the next {n1} cells, {wall1:.1f} s wall on one thread"}
 
 
 def bench_mixed(args):
@@ -548,6 +561,27 @@ def main():
     vj_bytes = 8 * (3 * m.n_species + 2 * m.n_reactions)  # read y, v, k; write gy, glnk
     vj_gbs = vj_bytes * C / vj_s / 1e9
 
+    # the same f+J launches captured in a HIP graph (launch gaps amortised)
+    fj_graph_us = None
+    try:
+        cap = torch.cuda.Stream(device=dev)
+        cap.wait_stream(stream)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cap):
+            for _ in range(20):
+                cells.deriv_jac(y0, f, J, stream=cap)
+        g.replay()
+        torch.cuda.synchronize()
+        ge = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ge[0].record()
+        for _ in range(5):
+            g.replay()
+        ge[1].record()
+        torch.cuda.synchronize()
+        fj_graph_us = ge[0].elapsed_time(ge[1]) * 1e3 / 100
+    except RuntimeError as e:  # capture refused: reported, not fatal
+        print(f"f+J graph capture failed: {e}", file=sys.stderr)
+
     result = {
         "metric": "cell-timesteps/s (FP64, 1e-6 rel vs oracle); f+J evals/s as % HBM peak",
         "value": C * args.steps / wall,
@@ -576,7 +610,8 @@ def main():
         "fj_roofline": {"kernel": FJ_KERNEL + " (calc_deriv_jac, generated for this mechanism)", "bound": "hbm",
                         "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
                         "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
-                        "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"]},
+                        "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"],
+                        "launch_us_in_graph": fj_graph_us},
         "vjp_roofline": {"kernel": "mcc_vjp_generated2 (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
                          "achieved": vj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vj_gbs / HBM_PEAK_GBS,
                          "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes},

@@ -142,3 +142,13 @@ def test_null_arguments_are_rejected():
     assert lib.mcc_cells_destroy(None) == 0
     assert lib.mcc_solve_step(None, None, 1.0, None, None, None, None) == 1
     assert ctypes.string_at(lib.mcc_last_error()) != b""
+
+
+def test_reverse_mode_entry_points_reject_null_handles():
+    """The taping solver and the reverse-mode call validate their arguments
+    before touching a device."""
+    lib = mcchem.library()
+    assert lib.mcc_adjoint_step(None, None, None, None, 0, None, None, 0, None, None) == 1
+    assert b"cells is null" in lib.mcc_last_error()
+    assert lib.mcc_solve_step_taped(None, None, 60.0, None, None, None, None, None, 3, None) == 1
+    assert b"cells is null" in lib.mcc_last_error()
