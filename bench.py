@@ -304,7 +304,7 @@ def bench_adjoint(args):
     cells.step(y, dt, opts, status, stats, stream=stream)
     sn = mcchem.stats_numpy(stats)
     attempts = sn["steps"] + sn["rejects"] + sn["newton_fails"]
-    stride = int((3 + 6 * attempts + N * sn["steps"]).max())
+    stride = int((4 + 8 * attempts + N * sn["steps"]).max())
     tape = torch.empty((C, stride), dtype=torch.float64, device=dev)
     tlen = torch.empty(C, dtype=torch.int64, device=dev)
     lam = torch.empty_like(y0)

@@ -313,12 +313,28 @@ mcc_status mcc_cells_set_rate_constants(mcc_cells *cells, const double *k, void 
 mcc_status mcc_solve_step(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
                           int32_t *cell_status, mcc_cell_stats *stats, void *stream);
 
+/* The step sequence of each cell's tape (format of mcc_adjoint_step) run
+ * again from y0 with the batch's current rate constants: the map whose
+ * derivative mcc_adjoint_step computes, for checking it by finite
+ * differences (Section 2 solver with its steps frozen).  The start and the
+ * re-samplings are applied as taped; each accepted step solves its implicit
+ * equation by Newton with a fresh Newton matrix at every iterate, starting
+ * from the taped state, until the largest correction relative to its
+ * component is at most tol, or for max_newton iterations.  y0, y device
+ * [n_species][ld] (y receives the end state; NaN for a failed cell).
+ * cell_status as mcc_adjoint_step (MCC_CELL_SINGULAR: a Newton matrix was
+ * singular).  An empty tape maps y0 to itself.  Mechanism shapes as
+ * mcc_adjoint_step. */
+mcc_status mcc_replay_step(const mcc_cells *cells, const double *y0, const double *tape, const int64_t *tape_len,
+                           int64_t tape_stride, double *y, int32_t max_newton, double tol, int32_t *cell_status,
+                           void *stream);
+
 /* mcc_solve_step recording every cell's step tape for mcc_adjoint_step
  * (the entry format described there): tape device doubles [n_cells]
- * [tape_stride >= 3], tape_len device int64 [n_cells] receives the doubles
+ * [tape_stride >= 4], tape_len device int64 [n_cells] receives the doubles
  * written per cell, or -1 when the cell's tape did not fit in tape_stride
  * (its solve is unaffected; mcc_adjoint_step then reports MCC_CELL_BAD_TAPE).
- * A cell takes at most 3 + 6 * attempts + n_species * steps doubles (steps
+ * A cell takes at most 4 + 8 * attempts + n_species * steps doubles (steps
  * as in mcc_cell_stats; attempts = steps + rejects + newton_fails).
  * The tape starts from the y passed in: keep a copy of it for the reverse
  * pass.  Also in the per-launch form. */
@@ -349,12 +365,13 @@ mcc_status mcc_solve_step_multicell(mcc_cells *cells, double *y, double dt, cons
  * add) dL/d ln k_j to glnk, for every cell.  The step sequence of each cell
  * is its tape: device doubles [n_cells][tape_stride], cell c using the first
  * tape_len[c] (device int64 [n_cells]).  Entries are written in time order,
- * each as a payload followed by three doubles (order, value, type):
+ * each as [type, payload, order, value, type] (the type at both ends, so a
+ * tape can be walked either way):
  *   type 0, start: value = the first step size h (D_0 = y0, D_1 = h f(y0));
  *   type 1, re-sampling of the differences D_0..D_order to spacing value * h;
  *   type 2, accepted step of order k with value c = h / gamma_k; payload:
  *        the step's converged state z (n_species values, species order).
- * Every tape starts with one type-0 entry.  For a step the transpose of
+ * Other entries have no payload.  Every tape starts with one type-0 entry.  For a step the transpose of
  * I - c J(z) is factorised with the mechanism's transposed solver tables.
  * y0 device [n_species][ld] (the state the tape starts from), lam device
  * [n_species][ld] in/out, glnk device [n_reactions][ld], cell_status device

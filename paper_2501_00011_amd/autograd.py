@@ -83,16 +83,16 @@ def solve_step(cells: "mcchem.Cells", y0: torch.Tensor, lnk: torch.Tensor, dt: f
     tape_stride: doubles of step tape per cell (default room for about 256
     steps; doubled and the step redone when a tape does not fit)."""
     N = cells.mech.n_species
-    stride = tape_stride or 3 + 256 * (N + 12)
+    stride = tape_stride or 4 + 256 * (N + 16)
     return _SolveStep.apply(y0, lnk, cells, dt, opts, stride)
 
 
 def _tape_bound(stats, n_species: int) -> int:
     """Doubles of step tape the largest cell of an outer step needs (the
-    bound of mcc_solve_step_taped: 3 + 6 attempts + n_species steps)."""
+    bound of mcc_solve_step_taped: 4 + 8 attempts + n_species steps)."""
     sn = mcchem.stats_numpy(stats)
     attempts = sn["steps"].astype("int64") + sn["rejects"] + sn["newton_fails"]
-    return int((3 + 6 * attempts + n_species * sn["steps"].astype("int64")).max()) if len(sn) else 3
+    return int((4 + 8 * attempts + n_species * sn["steps"].astype("int64")).max()) if len(sn) else 4
 
 
 class _Integrate(torch.autograd.Function):
@@ -102,7 +102,7 @@ class _Integrate(torch.autograd.Function):
         cells.set_rate_constants(k)
         N = cells.mech.n_species
         y = y0.contiguous().clone()
-        checkpoints, stride = [], 3
+        checkpoints, stride = [], 4
         stats = None
         for _ in range(n_steps):
             checkpoints.append(y.clone())  # the state each outer step starts from

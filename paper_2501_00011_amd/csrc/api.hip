@@ -847,12 +847,44 @@ mcc_status mcc_solve_step_taped(mcc_cells *c, double *y, double dt, const mcc_so
                                 void *stream)
 {
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
-    if (tape_stride < 3) return set_error(MCC_ERR_INVALID_ARG, "tape_stride must hold at least the start entry (3)");
+    if (tape_stride < kTapeScalars)
+        return set_error(MCC_ERR_INVALID_ARG, "tape_stride must hold at least the start entry (4 doubles)");
     if (c->n_cells > 0 && (!tape || !tape_len)) return set_error(MCC_ERR_INVALID_ARG, "tape and tape_len must not be null");
     const mcc_mech *m = c->mech;
     if (!m->adj.unavailable.empty()) return set_error(MCC_ERR_MECH, m->adj.unavailable);
     if (!adjoint_shape_supported(m->t.NS, m->t.M)) return set_error(MCC_ERR_MECH, "no taping solver for this mechanism's shape");
     return solve_step(c, y, dt, opts, cell_status, stats, tape, tape_len, tape_stride, stream);
+}
+
+mcc_status mcc_replay_step(const mcc_cells *c, const double *y0, const double *tape, const int64_t *tape_len,
+                           int64_t tape_stride, double *y, int32_t max_newton, double tol, int32_t *cell_status,
+                           void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (!c->bound) return set_error(MCC_ERR_STATE, "the batch has no rate constants yet");
+    const mcc_mech *m = c->mech;
+    if (!adjoint_shape_supported(m->t.NS, m->t.M)) return set_error(MCC_ERR_MECH, "no replay kernel for this mechanism's shape");
+    if (tape_stride < 0) return set_error(MCC_ERR_INVALID_ARG, "tape_stride < 0");
+    if (max_newton < 1 || !(tol >= 0.0)) return set_error(MCC_ERR_INVALID_ARG, "need max_newton >= 1 and tol >= 0");
+    if (c->n_cells == 0) return ok();
+    if (!y0 || !y || !tape_len || (!tape && tape_stride > 0))
+        return set_error(MCC_ERR_INVALID_ARG, "y0, tape, tape_len and y must not be null");
+    DeviceGuard g(m->device);
+    mcc_solver_opts o;
+    mcc_solver_opts_default(&o);
+    SolveParams p = solve_params(const_cast<mcc_cells *>(c), y, 1.0, o, cell_status, nullptr);
+    ReplayParams r{};
+    r.tape = tape;
+    r.len = tape_len;
+    r.stride = tape_stride;
+    r.y0 = y0;
+    r.y = y;
+    r.status = cell_status;
+    r.max_newton = max_newton;
+    r.tol = tol;
+    hipError_t e = launch_replay(p, r, m->t.NS, m->t.M, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "replay kernel launch");
+    return ok();
 }
 
 static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts, int32_t *cell_status,

@@ -606,10 +606,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
     int64_t tpos = TAPE && resumed ? (int64_t)st_s[15] : 0;
     auto record = [&](int type, int ord, double x, bool with_state) {
         if (!TAPE || tpos < 0) return;
-        if (tpos + 3 + (with_state ? N : 0) > p.tape_stride) {
+        if (tpos + kTapeScalars + (with_state ? N : 0) > p.tape_stride) {
             tpos = -1;
             return;
         }
+        if (lane == 0) tp[tpos] = type;
+        tpos += 1;
         if (with_state) {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
@@ -975,28 +977,28 @@ __global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParam
     int status = (pos >= 0 && pos <= a.stride) ? 0 : 1;
     const bool empty = pos == 0;
     bool started = false;
-    while (status == 0 && pos >= 3) {
+    while (status == 0 && pos >= kTapeScalars) {
         const int type = (int)tp[pos - 1];
         const double x = tp[pos - 2];
         const int order = (int)tp[pos - 3];
+        const int64_t n_state = type == 2 ? N : 0;
         pos -= 3;
-        if (type != 0 && (order < 1 || order > kMaxOrder)) {
+        // the entry's leading copy of its type
+        if (pos < n_state + 1 || (type != 0 && (order < 1 || order > kMaxOrder)) ||
+            tp[pos - n_state - 1] != (double)type) {
             status = 1;
             break;
         }
+        const double *pl = tp + pos - n_state;  // the step's state
+        pos -= n_state + 1;
         if (type == 1) {  // re-sampling of the differences
             rescale_transposed<NS>(L, order, x, C.tm);
         } else if (type == 2) {  // accepted step
-            if (pos < N) {
-                status = 1;
-                break;
-            }
-            pos -= N;
             const int k = order;
             const double c = x;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                z[s] = C.valid(s) ? tp[pos + sp[s]] : 0.0;
+                z[s] = C.valid(s) ? pl[sp[s]] : 0.0;
                 // D_j += D_{j+1} (j = k..0), reversed: lam_{j+1} += lam_j (j = 0..k)
 #pragma unroll
                 for (int j = 0; j <= kMaxOrder; ++j)
@@ -1087,6 +1089,127 @@ __global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParam
     if (lane == 0 && a.status) a.status[cell] = status == 0 ? MCC_CELL_OK : (status == 2 ? MCC_CELL_SINGULAR : MCC_CELL_BAD_TAPE);
 }
 
+// The step sequence of a tape run again from y0 with the batch's rate
+// constants (the frozen-sequence map that the reverse pass differentiates):
+// the start and every re-sampling as taped; every accepted step of order k
+// and c = h / gamma_k solves d - c f(ypred + d) + psi = 0 by Newton with a
+// fresh Newton matrix at every iterate, from the taped state, until the
+// largest correction relative to its component is at most tol (or
+// max_newton iterations), then updates the differences as the solver does.
+template <int NS, int M>
+__global__ __launch_bounds__(64) void replay_kernel(SolveParams p, ReplayParams r)
+{
+    extern __shared__ double smem[];
+    const int64_t cell = blockIdx.x;
+    if (cell >= p.n_cells) return;
+    Cell<NS, M> C(p, smem);
+    const int lane = C.lane, N = p.N;
+    for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
+    if (lane == 0) C.yv[p.NV] = 1.0;
+    if (lane == 0) {
+        C.lu[p.lu_nnz] = 0.0;
+        C.lu[p.lu_nnz + 1] = 0.0;
+    }
+    int sp[NS];
+    double D[kMaxOrder + 3][NS], f[NS], ypred[NS], psi[NS], d[NS], tmp[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        sp[s] = C.valid(s) ? p.vspecies[s * kWave + lane] : 0;
+#pragma unroll
+        for (int j = 0; j < kMaxOrder + 3; ++j) D[j][s] = 0.0;
+        D[0][s] = C.valid(s) ? r.y0[(int64_t)sp[s] * p.ld + cell] : 0.0;
+    }
+    const double *tp = r.tape + cell * r.stride;
+    const int64_t len = r.len[cell];
+    int status = (len >= 0 && len <= r.stride) ? 0 : 1;  // 1: malformed tape, 2: singular matrix
+    bool started = false;
+    int64_t pos = 0;
+    while (status == 0 && pos < len) {
+        if (len - pos < kTapeScalars) {
+            status = 1;
+            break;
+        }
+        const int type = (int)tp[pos];
+        const int64_t n_state = type == 2 ? N : 0;
+        if (len - pos < kTapeScalars + n_state) {
+            status = 1;
+            break;
+        }
+        const double *pl = tp + pos + 1;
+        const int order = (int)tp[pos + 1 + n_state];
+        const double x = tp[pos + 2 + n_state];
+        // the trailing copy of the type matches; the start comes first and once
+        if (tp[pos + 3 + n_state] != (double)type || (type != 0 && (order < 1 || order > kMaxOrder)) ||
+            (type == 0) == started || type < 0 || type > 2) {
+            status = 1;
+            break;
+        }
+        pos += kTapeScalars + n_state;
+        if (type == 0) {  // D_0 = y0, D_1 = h f(y0)
+            started = true;
+            C.deriv(D[0], f);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) D[1][s] = x * f[s];
+        } else if (type == 1) {
+            rescale<NS>(D, order, x, C.tm);
+        } else {
+            const int k = order;
+            const double c = x, gk = bdf_gamma(k);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                double yp = 0.0, ps = 0.0;
+#pragma unroll
+                for (int j = 0; j <= kMaxOrder; ++j) yp += j <= k ? D[j][s] : 0.0;
+#pragma unroll
+                for (int j = 1; j <= kMaxOrder; ++j) ps += j <= k ? bdf_gamma(j) * D[j][s] : 0.0;
+                ypred[s] = yp;
+                psi[s] = ps / gk;
+                d[s] = C.valid(s) ? pl[sp[s]] - yp : 0.0;  // from the taped state
+            }
+            for (int it = 0; it < r.max_newton; ++it) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) tmp[s] = ypred[s] + d[s];
+                C.deriv(tmp, f);
+                C.newton_matrix(tmp, c);
+                if (C.factor()) {
+                    status = 2;
+                    break;
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) tmp[s] = c * f[s] - psi[s] - d[s];
+                C.solve(tmp);
+                double nr = 0.0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (C.valid(s)) {
+                        d[s] += tmp[s];
+                        nr = fmax(nr, fabs(tmp[s]) / (fabs(ypred[s] + d[s]) + 1e-300));
+                    }
+                if (-wave_min(-nr) <= r.tol) break;
+            }
+            if (status != 0) break;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                for (int j = 3; j < kMaxOrder + 3; ++j)
+                    D[j][s] = j == k + 2 ? d[s] - D[j - 1][s] : D[j][s];
+#pragma unroll
+                for (int j = 2; j < kMaxOrder + 2; ++j)
+                    D[j][s] = j == k + 1 ? d[s] : D[j][s];
+#pragma unroll
+                for (int j = kMaxOrder; j >= 0; --j)
+                    D[j][s] = j <= k ? D[j][s] + D[j + 1][s] : D[j][s];
+            }
+        }
+    }
+    if (status == 0 && len > 0 && !started) status = 1;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (C.valid(s)) r.y[(int64_t)sp[s] * p.ld + cell] = status == 0 ? D[0][s] : NAN;
+    if (lane == 0 && r.status)
+        r.status[cell] = status == 0 ? MCC_CELL_OK : (status == 2 ? MCC_CELL_SINGULAR : MCC_CELL_BAD_TAPE);
+}
+
 }  // namespace
 
 #define MCC_SOLVE_VARIANTS(X) \
@@ -1165,7 +1288,29 @@ hipError_t prepare_adjoint_kernels(int max_lds_bytes)
                                 max_lds_bytes);
     MCC_ADJOINT_VARIANTS(MCC_SET_LDS_ADJ)
 #undef MCC_SET_LDS_ADJ
+#define MCC_SET_LDS_REPLAY(ns, m)                                                                       \
+    if (e == hipSuccess)                                                                               \
+        e = hipFuncSetAttribute((const void *)replay_kernel<ns, m>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                max_lds_bytes);
+    MCC_ADJOINT_VARIANTS(MCC_SET_LDS_REPLAY)
+#undef MCC_SET_LDS_REPLAY
     return e;
+}
+
+hipError_t launch_replay(const SolveParams &p, const ReplayParams &r, int NS, int M, hipStream_t s)
+{
+    if (p.n_cells == 0) return hipSuccess;
+    if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)p.n_cells), block(kWave);
+    const size_t lds = (size_t)p.lds_doubles * sizeof(double);
+#define MCC_LAUNCH_REPLAY(ns, m)                                              \
+    if (NS == ns && M == m) {                                                 \
+        hipLaunchKernelGGL((replay_kernel<ns, m>), grid, block, lds, s, p, r); \
+        return hipGetLastError();                                             \
+    }
+    MCC_ADJOINT_VARIANTS(MCC_LAUNCH_REPLAY)
+#undef MCC_LAUNCH_REPLAY
+    return hipErrorInvalidValue;
 }
 
 bool adjoint_shape_supported(int NS, int M)

@@ -197,6 +197,12 @@ struct SolveParams {
 };
 constexpr int kStateScalars = 16;
 
+// Step tapes: per cell, entries in time order, each [type, state (n_species
+// doubles, accepted steps only), order, value, type]; types 0 start (value:
+// first h), 1 re-sampling (value: factor), 2 accepted step (value:
+// h / gamma_order).  kTapeScalars: the doubles of an entry besides the state.
+constexpr int kTapeScalars = 4;
+
 // Reverse mode of one outer step (adjoint_kernel), with a SolveParams built
 // from the transposed solver tables.
 struct AdjointParams {
@@ -213,6 +219,18 @@ struct AdjointParams {
     int32_t accumulate;    // glnk += instead of =
 };
 constexpr int kAdjMaxR = 512;  // reactions per mechanism the reverse-mode kernel handles
+
+// Replay of a tape's frozen step sequence (replay_kernel), forward solver tables.
+struct ReplayParams {
+    const double *tape;
+    const int64_t *len;
+    int64_t stride;
+    const double *y0;  // [N][ld]
+    double *y;         // [N][ld] out
+    int32_t *status;   // [n_cells] or null
+    int32_t max_newton;
+    double tol;        // largest Newton correction relative to its component
+};
 
 // Launchers (enqueue only; return the launch error).
 hipError_t launch_rates(const RatesParams &p, hipStream_t s);
@@ -238,6 +256,7 @@ hipError_t prepare_solve_kernels(int max_lds_bytes);
 bool adjoint_shape_supported(int NS, int M);
 hipError_t prepare_adjoint_kernels(int max_lds_bytes);
 hipError_t launch_adjoint(const SolveParams &p, const AdjointParams &a, int NS, int M, hipStream_t s);
+hipError_t launch_replay(const SolveParams &p, const ReplayParams &r, int NS, int M, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);  // *p = v by a kernel (graph-safe)
 // Multi-cells solver: largest co-resident batch (0: no kernel for this shape), cooperative launch.
 hipError_t multicell_capacity(int NS, int M, size_t lds_bytes, int device, int64_t *max_cells);

@@ -79,6 +79,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_adjoint_step": ([vp, vp, vp, vp, i64, vp, vp, i32, vp, vp], ctypes.c_int),
         "mcc_solve_step_taped": ([vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp], ctypes.c_int),
+        "mcc_replay_step": ([vp, vp, vp, vp, i64, vp, i32, dbl, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
@@ -360,6 +361,26 @@ class Cells:
             _dptr(glnk, "glnk", torch.float64, (self.mech.n_reactions, self.ld)), 1 if accumulate else 0,
             _dptr(status, "status", torch.int32, (self.n_cells,)), _stream_ptr(stream)))
         return glnk, status
+
+    def replay_step(self, y0, tape, tape_len, y=None, max_newton=50, tol=1e-15, status=None, stream=None):
+        """The tapes' frozen step sequences run again from y0 with the
+        current rate constants (Newton to convergence at every step).
+        Returns (y, status)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(y0)
+        if status is None:
+            status = torch.empty(self.n_cells, dtype=torch.int32, device=y0.device)
+        if tape.dim() != 2 or tape.shape[0] != self.n_cells:
+            raise ValueError(f"tape must be [n_cells={self.n_cells}][stride]")
+        stride = int(tape.shape[1])
+        _check(library().mcc_replay_step(
+            self._h, _dptr(y0, "y0", torch.float64, self._yshape()),
+            _dptr(tape, "tape", torch.float64, (self.n_cells, stride)),
+            _dptr(tape_len, "tape_len", torch.int64, (self.n_cells,)), stride,
+            _dptr(y, "y", torch.float64, self._yshape()), int(max_newton), float(tol),
+            _dptr(status, "status", torch.int32, (self.n_cells,)), _stream_ptr(stream)))
+        return y, status
 
     def set_rate_constants(self, k, stream=None):
         """Use caller rate constants k [R][ld] (device float64) instead of bind()'s."""

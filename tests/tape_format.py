@@ -1,16 +1,19 @@
 """Conversions between the oracle's step tape order (type, order, value,
-then for a step the n_species state values) and the reverse-mode kernel's
-entry format (the state first, then order, value, type), so that tapes
-written by either side can be walked by the other."""
+then for a step the n_species state values) and the library's entry format
+([type, state of a step, order, value, type]), so that tapes written by
+either side can be walked by the other."""
 import numpy as np
+
+SCALARS = 4  # doubles of a library tape entry besides the state
 
 
 def to_device(vals, N):
-    """An oracle tape in the reverse-mode entry format."""
+    """An oracle tape in the library's entry format."""
     out, p = [], 0
     while p < len(vals):
         typ, order, x = vals[p:p + 3]
         n = N if int(typ) == 2 else 0
+        out.append(typ)
         out.extend(vals[p + 3:p + 3 + n])
         out.extend([order, x, typ])
         p += 3 + n
@@ -18,15 +21,16 @@ def to_device(vals, N):
 
 
 def to_oracle(dev_vals, N):
-    """A tape in the reverse-mode entry format back in the oracle's order
-    (parsed from the end, as the kernel walks it)."""
-    entries, p = [], len(dev_vals)
-    while p > 0:
-        typ, x, order = dev_vals[p - 1], dev_vals[p - 2], dev_vals[p - 3]
+    """A library tape back in the oracle's order (parsed from the start)."""
+    entries, p = [], 0
+    while p < len(dev_vals):
+        typ = dev_vals[p]
         n = N if int(typ) == 2 else 0
-        entries.append(np.concatenate([[typ, order, x], dev_vals[p - 3 - n:p - 3]]))
-        p -= 3 + n
-    return np.concatenate(entries[::-1]) if entries else np.zeros(0)
+        order, x, typ2 = dev_vals[p + 1 + n:p + 4 + n]
+        assert typ2 == typ, "malformed tape"
+        entries.append(np.concatenate([[typ, order, x], dev_vals[p + 1:p + 1 + n]]))
+        p += SCALARS + n
+    return np.concatenate(entries) if entries else np.zeros(0)
 
 
 def pack(tapes, pad=5):
@@ -46,3 +50,12 @@ def count_steps(vals, N):
         n += int(vals[p]) == 2
         p += 3 + (N if int(vals[p]) == 2 else 0)
     return n
+
+
+def entry_offsets(dev_vals, N):
+    """Start offsets of the entries of a library tape."""
+    out, p = [], 0
+    while p < len(dev_vals):
+        out.append(p)
+        p += SCALARS + (N if int(dev_vals[p]) == 2 else 0)
+    return out

@@ -679,8 +679,9 @@ def test_adjoint_step_accumulate_and_bad_tapes(dev, oracle_mod):
     blen[1] = buf.shape[1] + 1
     assert int(bad[2, lens[2] - 1]) in (1, 2)  # the last entry is a step or a re-sampling
     bad[2, lens[2] - 3] = 0.0  # ... of order 0
-    bad[3, 0:lens[3] - 3] = bad[3, 3:lens[3]]  # drop the start entry
-    blen[3] = lens[3] - 3
+    S = tape_format.SCALARS
+    bad[3, 0:lens[3] - S] = bad[3, S:lens[3]]  # drop the start entry
+    blen[3] = lens[3] - S
     lam = _t(W, dev)
     g, st = b.cells.adjoint_step(b.y_dev(), _t(bad, dev), _t(blen, dev), lam)
     torch.cuda.synchronize()
@@ -707,7 +708,7 @@ def test_taped_solve_and_gpu_adjoint(dev, oracle_mod, name, n, K):
     y = y0.clone()
     sp = mcchem.stats_numpy(stats_plain)
     attempts = sp["steps"] + sp["rejects"] + sp["newton_fails"]
-    stride = int((3 + 6 * attempts + N * sp["steps"]).max())  # the documented bound
+    stride = int((4 + 8 * attempts + N * sp["steps"]).max())  # the documented bound
     tape = torch.full((n, stride), float("nan"), dtype=torch.float64, device=dev)
     tlen = torch.empty(n, dtype=torch.int64, device=dev)
     stats = torch.empty_like(stats_plain)
@@ -783,7 +784,7 @@ def test_autograd_solve_step(dev, oracle_mod):
     yd = y.detach().cpu().numpy()
     W = 2 * (np.log(yd + atol) - np.log(target.cpu().numpy() + atol)) / (yd + atol)
     k = k_gpu.cpu().numpy()
-    tape = torch.empty((16, 3 + 2000 * (N + 6)), dtype=torch.float64, device=dev)
+    tape = torch.empty((16, 4 + 2000 * (N + 8)), dtype=torch.float64, device=dev)
     tlen = torch.empty(16, dtype=torch.int64, device=dev)
     yy = b.y_dev()
     b.cells.step_taped(yy, dt, tape, tlen)
@@ -822,7 +823,7 @@ def test_autograd_integrate_checkpointed(dev, oracle_mod):
     yy = b.y_dev()
     for _ in range(n_out):
         ys.append(yy.cpu().numpy())
-        tape = torch.empty((8, 3 + 3000 * (N + 6)), dtype=torch.float64, device=dev)
+        tape = torch.empty((8, 4 + 3000 * (N + 8)), dtype=torch.float64, device=dev)
         tlen = torch.empty(8, dtype=torch.int64, device=dev)
         b.cells.step_taped(yy, dt, tape, tlen)
         torch.cuda.synchronize()
@@ -872,7 +873,7 @@ def test_gradient_full_size_sampled(dev, oracle_mod):
     ys, tapes = [], []
     for _ in range(n_out):
         ys.append(yy.cpu().numpy())
-        tape = torch.empty((3, 3 + 3000 * (N + 6)), dtype=torch.float64, device=dev)
+        tape = torch.empty((3, 4 + 3000 * (N + 8)), dtype=torch.float64, device=dev)
         tlen = torch.empty(3, dtype=torch.int64, device=dev)
         bs.cells.step_taped(yy, dt, tape, tlen)
         torch.cuda.synchronize()
@@ -887,3 +888,97 @@ def test_gradient_full_size_sampled(dev, oracle_mod):
             g += gs
         assert np.abs(gy[:, i] - lam).max() <= 1e-9 * np.abs(lam).max()
         assert np.abs(gl[:, i] - g).max() <= 1e-9 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("name,n", [("small10", 10), ("medium10k", 24)])
+def test_replay_step_parity(dev, oracle_mod, name, n):
+    """The GPU replay of GPU-recorded tapes against the oracle's replay of
+    the same tapes (both solve every step to convergence), and against the
+    forward solve it replays (to the forward's Newton tolerance)."""
+    m, c, dt = synth.workload(name, n)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    N = m.n_species
+    y0 = b.y_dev()
+    y = y0.clone()
+    tape = torch.empty((n, 4 + 2000 * (N + 8)), dtype=torch.float64, device=dev)
+    tlen = torch.empty(n, dtype=torch.int64, device=dev)
+    st, _ = b.cells.step_taped(y, dt, tape, tlen)
+    yr, rst = b.cells.replay_step(y0, tape, tlen)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0) and np.all(rst.cpu().numpy() == 0)
+    yr, yf = yr.cpu().numpy(), y.cpu().numpy()
+    assert np.all(np.abs(yr - yf) <= 1e-6 * np.abs(yf) + 1e2)  # the step bar
+    k = b.cells.rate_constants().cpu().numpy()
+    tv, tl = tape.cpu().numpy(), tlen.cpu().numpy()
+    worst = 0.0
+    for i in range(n):
+        t = oracle_mod.Tape.from_values(b.o.lib, tape_format.to_oracle(tv[i, :tl[i]], N))
+        yo, _ = b.o.replay(k[:, i], c.y0[:, i], t)
+        worst = max(worst, float(np.max(np.abs(yr[:, i] - yo) / (np.abs(yo) + 1.0))))
+    print(f"{name}: GPU replay vs oracle replay, worst relative difference {worst:.3g}")
+    assert worst <= 1e-10
+
+
+def test_replay_rejects_bad_tapes(dev):
+    m, c, dt = synth.workload("small10", 3)
+    b = Batch(dev, m, c)
+    N = m.n_species
+    y0 = b.y_dev()
+    y = y0.clone()
+    tape = torch.empty((3, 4 + 2000 * (N + 8)), dtype=torch.float64, device=dev)
+    tlen = torch.empty(3, dtype=torch.int64, device=dev)
+    b.cells.step_taped(y, dt, tape, tlen)
+    torch.cuda.synchronize()
+    bad_len = tlen.clone()
+    bad_len[0] = 0                  # empty: y = y0
+    bad_len[1] = tape.shape[1] + 4  # beyond the stride
+    bad_len[2] = tlen[2] - 1        # the last entry cut short
+    yr, rst = b.cells.replay_step(y0, tape, bad_len)
+    torch.cuda.synchronize()
+    assert rst.cpu().tolist() == [mcchem.CELL_OK, mcchem.CELL_BAD_TAPE, mcchem.CELL_BAD_TAPE]
+    assert torch.equal(yr[:, 0], y0[:, 0]) and torch.isnan(yr[:, 1:]).all()
+
+
+def test_gradient_against_central_differences_of_the_replay(dev):
+    """d L / d log A for 64 cells over 10 x 60 s (the adjoint workload's log
+    loss and perturbed target) against central differences, h = 1e-6, of
+    the frozen step sequences replayed on the GPU, for six parameters."""
+    from paper_2501_00011_amd import autograd
+    m, c, dt = synth.workload("adjoint10k", 64)
+    C, N, R, n_out, eps = 64, m.n_species, m.n_reactions, 10, 1e-6
+    b = Batch(dev, m, c)
+    k = b.cells.rate_constants().clone()
+    y0 = b.y_dev()
+    with torch.no_grad():
+        pert = torch.from_numpy(np.random.default_rng(5005).normal(0.0, 0.1, R)).to(dev)
+        target = autograd.integrate(b.cells, y0, torch.log(k) + pert[:, None], dt, n_out)
+    lnk = torch.log(k).requires_grad_(True)
+    y = autograd.integrate(b.cells, y0, lnk, dt, n_out)
+    loss = ((torch.log(y + 1.0) - torch.log(target + 1.0)) ** 2).sum()
+    loss.backward()
+    gA = lnk.grad.sum(dim=1).cpu().numpy()
+    # the forward's tapes, then the loss of the replayed chain at perturbed log A
+    b.cells.set_rate_constants(k)
+    tapes, yy = [], y0.clone()
+    for _ in range(n_out):
+        tape = torch.empty((C, 4 + 3000 * (N + 8)), dtype=torch.float64, device=dev)
+        tlen = torch.empty(C, dtype=torch.int64, device=dev)
+        b.cells.step_taped(yy, dt, tape, tlen)
+        tapes.append((tape, tlen))
+
+    def replayed_loss(j, sign):
+        kp = k.clone()
+        kp[j] *= math.exp(sign * eps)
+        b.cells.set_rate_constants(kp)
+        ys = y0
+        for tape, tlen in tapes:
+            ys, st = b.cells.replay_step(ys, tape, tlen)
+            assert int((st != 0).sum()) == 0
+        return float(((torch.log(ys + 1.0) - torch.log(target + 1.0)) ** 2).sum())
+
+    sel = list(np.argsort(-np.abs(gA))[:3]) + list(np.random.default_rng(3).choice(R, 3, replace=False))
+    for j in sel:
+        fd = (replayed_loss(j, 1) - replayed_loss(j, -1)) / (2 * eps)
+        print(f"log A_{j}: adjoint {gA[j]:.9g}, central difference {fd:.9g}")
+        assert abs(fd - gA[j]) <= 1e-5 * abs(gA[j]) + 1e-7 * float(loss), (j, fd, gA[j])
+    b.cells.set_rate_constants(k)

@@ -136,12 +136,13 @@ def test_tape_formats_round_trip_and_assign(oracle_mod):
     assert s == 0
     v = tape.values()
     dv = tape_format.to_device(v, m.n_species)
-    assert len(dv) == len(v)
+    offs = tape_format.entry_offsets(dv, m.n_species)
+    assert len(dv) == len(v) + len(offs)  # one leading type per entry
     assert np.array_equal(tape_format.to_oracle(dv, m.n_species), v)
     assert tape_format.count_steps(v, m.n_species) == st["steps"]
     w = np.random.default_rng(1).normal(size=m.n_species)
     lam1, g1 = o.adjoint(k, y0, tape, w)
     lam2, g2 = o.adjoint(k, y0, oracle_mod.Tape.from_values(o.lib, v), w)
     assert np.array_equal(lam1, lam2) and np.array_equal(g1, g2)
-    buf, lens = tape_format.pack([dv, dv[:3]])
-    assert lens.tolist() == [len(dv), 3] and np.isnan(buf[1, 3:]).all()
+    buf, lens = tape_format.pack([dv, dv[:4]])
+    assert lens.tolist() == [len(dv), 4] and np.isnan(buf[1, 4:]).all()
