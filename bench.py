@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--gradient", action="store_true",
                     help="gradient of the log loss with respect to log A over 10 x 60 s outer steps "
                          "(checkpointed forward + reverse mode; one JSON line)")
+    ap.add_argument("--fd-params", type=int, default=4,
+                    help="with --gradient: parameters checked against central differences (h = 1e-6) of the "
+                         "frozen step sequences replayed on the GPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -426,6 +429,42 @@ def bench_gradient(args):
            "forward_s": tot - bwd, "reverse_s": bwd, "reverse_over_forward": bwd / (tot - bwd),
            "cell_gradients_per_s": C / tot, "loss": loss,
            "grad_logA_norm": float(gA.norm()), "grad_logA_first4": [float(v) for v in gA[:4]]}
+    if args.fd_params > 0:
+        # the forward's step tapes, one buffer per outer step, then the loss
+        # of the replayed chain at log A_j +- h for the largest components
+        cells.set_rate_constants(k)
+        tapes, yy, stats = [], y0.clone(), None
+        for _ in range(n_out):
+            probe = yy.clone()
+            _, stats = cells.step(probe, dt, stats=stats)
+            tape = torch.empty((C, autograd._tape_bound(stats, N)), dtype=torch.float64, device=dev)
+            tlen = torch.empty(C, dtype=torch.int64, device=dev)
+            cells.step_taped(yy, dt, tape, tlen)
+            tapes.append((tape, tlen))
+        eps = 1e-6
+
+        def replayed_loss(j, sign):
+            kp = k.clone()
+            kp[j] *= float(np.exp(sign * eps))
+            cells.set_rate_constants(kp)
+            ys = y0
+            for tape, tlen in tapes:
+                ys, st = cells.replay_step(ys, tape, tlen)
+            bad = int((st != 0).sum())
+            return float(((torch.log(ys + atol) - torch.log(target + atol)) ** 2).sum()), bad
+
+        g = gA.cpu().numpy()
+        sel = [int(j) for j in np.argsort(-np.abs(g))[:args.fd_params]]
+        rel, failed = [], 0
+        t0 = time.perf_counter()
+        for j in sel:
+            (lp, bp), (lm, bm) = replayed_loss(j, 1), replayed_loss(j, -1)
+            failed += bp + bm
+            rel.append(abs((lp - lm) / (2 * eps) - g[j]) / abs(g[j]))
+        t_fd = time.perf_counter() - t0
+        cells.set_rate_constants(k)
+        out["fd_check"] = {"params": sel, "h": eps, "max_rel_diff": max(rel), "replay_failed_cells": failed,
+                           "replayed_chains": 2 * len(sel), "s_per_chain": t_fd / (2 * len(sel))}
     if not args.no_cpu:
         import oracle
         o = oracle.Oracle(m)
