@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--fd-params", type=int, default=4,
                     help="with --gradient: parameters checked against central differences (h = 1e-6) of the "
                          "frozen step sequences replayed on the GPU")
+    ap.add_argument("--no-balance", action="store_true",
+                    help="keep the identity cell schedule (no longest-first ordering from the previous step)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -552,6 +554,16 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # cell schedule: the solver takes the cells longest first by the step
+    # attempts they needed in the previous outer step (its counters); the
+    # identity schedule's solve time is reported beside it
+    unbalanced_ms = None
+    if not args.multicell and not args.no_balance:
+        ev0 = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        step(ev0)
+        torch.cuda.synchronize()
+        unbalanced_ms = ev0[0].elapsed_time(ev0[1])
+        cells.balance(stats)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -640,6 +652,9 @@ def main():
                    "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch,
                    "step_control": "multi-cells (shared)" if args.multicell else "per cell",
                    "dense_tail": mech.schedule_info()["dense_tail"],
+                   "cell_schedule": "identity" if unbalanced_ms is None else
+                   "longest first by the previous outer step's attempts",
+                   "solve_ms_identity_schedule": unbalanced_ms,
                    "autotune_ms": {str(k): round(v, 2) for k, v in tuned.items()} if tuned else None},
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",

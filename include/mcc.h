@@ -384,6 +384,18 @@ mcc_status mcc_adjoint_step(const mcc_cells *cells, const double *y0, const doub
                             int64_t tape_stride, double *lam, double *glnk, int32_t accumulate,
                             int32_t *cell_status, void *stream);
 
+/* Cell schedule of the per-cell solver kernels (mcc_solve_step and its
+ * per-launch and taped forms, mcc_adjoint_step, mcc_replay_step): workgroup i
+ * integrates cell order[i], so cells listed first start first.  Cells whose
+ * integrations take many steps listed first shorten the tail of a launch
+ * (longest-processing-time-first); the per-cell counters of the previous
+ * outer step (mcc_cell_stats) predict them.  order: host int32 [n_cells], a
+ * permutation of 0..n_cells-1 (MCC_ERR_INVALID_ARG otherwise), copied by the
+ * call; NULL restores the identity.  Results do not depend on the schedule
+ * (every cell's integration is independent of the others).  Synchronises
+ * the device.  The Multi-cells solver ignores it. */
+mcc_status mcc_cells_set_schedule(mcc_cells *cells, const int32_t *order);
+
 /* Wait for all work of this batch's device and report any asynchronous error. */
 mcc_status mcc_sync(mcc_cells *cells);
 

@@ -65,6 +65,7 @@ struct mcc_cells {
     int32_t call_id = 0;
     double *mc_slots = nullptr;  // Multi-cells reduction slots [2][mc_cells]
     int64_t mc_cells = 0;
+    int32_t *order = nullptr;    // the solver's cell schedule (device [n_cells]), or null
 };
 
 namespace {
@@ -757,6 +758,7 @@ static SolveParams solve_params(mcc_cells *c, double *y, double dt, const mcc_so
     p.off_lu = m->off_lu;
     p.off_tm = m->off_tm;
     p.lds_doubles = m->lds_doubles;
+    p.order = c->order;
     p.k = c->k;
     p.y = y;
     p.status = cell_status;
@@ -811,6 +813,7 @@ mcc_status mcc_adjoint_step(const mcc_cells *c, const double *y0, const double *
     p.off_lu = m->adj.off_lu;
     p.off_tm = m->adj.off_tm;
     p.lds_doubles = m->adj.lds_doubles;
+    p.order = c->order;
     p.k = c->k;
     p.n_cells = c->n_cells;
     p.ld = c->ld;
@@ -985,9 +988,41 @@ mcc_status mcc_solve_step_multicell(mcc_cells *c, double *y, double dt, const mc
         c->mc_cells = c->n_cells;
     }
     SolveParams p = solve_params(c, y, dt, o, cell_status, stats);
+    p.order = nullptr;  // the grid-wide sums are taken in workgroup order: keep it the cell order
     p.mc_slots = c->mc_slots;
     e = launch_solve_multicell(p, m->t.NS, m->t.M, (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "Multi-cells solver launch");
+    return ok();
+}
+
+mcc_status mcc_cells_set_schedule(mcc_cells *c, const int32_t *order)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    DeviceGuard g(c->mech->device);
+    if (!order) {
+        if (c->order) {
+            hipError_t e = hipDeviceSynchronize();  // no launch may still read it
+            if (e == hipSuccess) e = hipFree(c->order);
+            c->order = nullptr;
+            if (e != hipSuccess) return hip_error(e, "releasing the cell schedule");
+        }
+        return ok();
+    }
+    const int64_t n = c->n_cells;
+    std::vector<char> seen((size_t)n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t v = order[i];
+        if (v < 0 || v >= n || seen[(size_t)v])
+            return set_error(MCC_ERR_INVALID_ARG, "order is not a permutation of the cells (entry " +
+                                                      std::to_string(i) + ")");
+        seen[(size_t)v] = 1;
+    }
+    if (n == 0) return ok();
+    hipError_t e = hipSuccess;
+    if (!c->order) e = hipMalloc(&c->order, (size_t)n * sizeof(int32_t));
+    else e = hipDeviceSynchronize();  // earlier launches may still read the old schedule
+    if (e == hipSuccess) e = hipMemcpy(c->order, order, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "uploading the cell schedule");
     return ok();
 }
 
@@ -1005,7 +1040,8 @@ mcc_status mcc_cells_destroy(mcc_cells *c)
     if (!c) return ok();
     DeviceGuard g(c->mech->device);
     hipError_t e = hipDeviceSynchronize();
-    for (void *buf : {(void *)c->k, (void *)c->ones, (void *)c->state, (void *)c->pending, (void *)c->mc_slots})
+    for (void *buf : {(void *)c->k, (void *)c->ones, (void *)c->state, (void *)c->pending, (void *)c->mc_slots,
+                      (void *)c->order})
         if (buf) {
             hipError_t e2 = hipFree(buf);
             if (e == hipSuccess) e = e2;

@@ -553,8 +553,8 @@ template <int NS, int M, bool MC, bool TAPE = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void bdf_kernel(SolveParams p)
 {
     extern __shared__ double smem[];
-    const int64_t cell = blockIdx.x;
-    if (cell >= p.n_cells) return;
+    if ((int64_t)blockIdx.x >= p.n_cells) return;
+    const int64_t cell = p.order ? p.order[blockIdx.x] : blockIdx.x;  // the batch's cell schedule
     // per-launch form: where this cell's state lives between launches
     const int K = p.opts.steps_per_launch;
     double *st_d = K > 0 ? p.state + cell * p.state_stride : nullptr;
@@ -935,8 +935,8 @@ template <int NS, int M>
 __global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParams a)
 {
     extern __shared__ double smem[];
-    const int64_t cell = blockIdx.x;
-    if (cell >= p.n_cells) return;
+    if ((int64_t)blockIdx.x >= p.n_cells) return;
+    const int64_t cell = p.order ? p.order[blockIdx.x] : blockIdx.x;  // the batch's cell schedule
     Cell<NS, M> C(p, smem);
     double *wv = smem + a.off_w;
     const int lane = C.lane, N = p.N;
@@ -1100,8 +1100,8 @@ template <int NS, int M>
 __global__ __launch_bounds__(64) void replay_kernel(SolveParams p, ReplayParams r)
 {
     extern __shared__ double smem[];
-    const int64_t cell = blockIdx.x;
-    if (cell >= p.n_cells) return;
+    if ((int64_t)blockIdx.x >= p.n_cells) return;
+    const int64_t cell = p.order ? p.order[blockIdx.x] : blockIdx.x;  // the batch's cell schedule
     Cell<NS, M> C(p, smem);
     const int lane = C.lane, N = p.N;
     for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];

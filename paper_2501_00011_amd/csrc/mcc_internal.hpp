@@ -172,6 +172,7 @@ struct SolveParams {
     // LDS layout (offsets in doubles)
     int32_t off_y, off_k, off_r, off_p, off_lu, off_tm, lds_doubles;
     // batch
+    const int32_t *order;  // workgroup -> cell (a permutation of the cells), or null: the identity
     const double *k;
     double *y;
     int32_t *status;

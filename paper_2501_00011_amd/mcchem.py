@@ -80,6 +80,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_adjoint_step": ([vp, vp, vp, vp, i64, vp, vp, i32, vp, vp], ctypes.c_int),
         "mcc_solve_step_taped": ([vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp], ctypes.c_int),
         "mcc_replay_step": ([vp, vp, vp, vp, i64, vp, i32, dbl, vp, vp], ctypes.c_int),
+        "mcc_cells_set_schedule": ([vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
@@ -381,6 +382,26 @@ class Cells:
             _dptr(y, "y", torch.float64, self._yshape()), int(max_newton), float(tol),
             _dptr(status, "status", torch.int32, (self.n_cells,)), _stream_ptr(stream)))
         return y, status
+
+    def set_schedule(self, order=None):
+        """Workgroup i of the per-cell solver kernels integrates cell
+        order[i] (host int32 permutation of the cells); None: the identity."""
+        if order is None:
+            _check(library().mcc_cells_set_schedule(self._h, None))
+            return
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        if o.shape != (self.n_cells,):
+            raise MccError(f"order must have shape ({self.n_cells},)")
+        _check(library().mcc_cells_set_schedule(self._h, o.ctypes.data))
+
+    def balance(self, stats):
+        """Schedule the cells longest first by their step attempts in stats
+        (the counters of a previous outer step).  Returns the order."""
+        sn = stats_numpy(stats)
+        attempts = sn["steps"].astype(np.int64) + sn["rejects"] + sn["newton_fails"]
+        order = np.argsort(-attempts, kind="stable").astype(np.int32)
+        self.set_schedule(order)
+        return order
 
     def set_rate_constants(self, k, stream=None):
         """Use caller rate constants k [R][ld] (device float64) instead of bind()'s."""

@@ -982,3 +982,56 @@ def test_gradient_against_central_differences_of_the_replay(dev):
         print(f"log A_{j}: adjoint {gA[j]:.9g}, central difference {fd:.9g}")
         assert abs(fd - gA[j]) <= 1e-5 * abs(gA[j]) + 1e-7 * float(loss), (j, fd, gA[j])
     b.cells.set_rate_constants(k)
+
+
+@pytest.mark.parametrize("K", [0, 3])
+def test_cell_schedule_leaves_results_unchanged(dev, K):
+    """Any cell schedule (here longest first by the previous step's
+    attempts, and a random one) gives every cell the same bits, in one
+    launch and in the per-launch form, and the same step tapes and
+    reverse-mode results."""
+    m, c, dt = synth.workload("medium10k", 300)
+    b = Batch(dev, m, c)
+    N = m.n_species
+    opts = mcchem.default_opts(steps_per_launch=K)
+    y0 = b.y_dev()
+
+    def run():
+        y = y0.clone()
+        st, stats = b.cells.step(y, dt, opts)
+        tape = torch.empty((300, 4 + 1500 * (N + 8)), dtype=torch.float64, device=dev)
+        tlen = torch.empty(300, dtype=torch.int64, device=dev)
+        yt = y0.clone()
+        b.cells.step_taped(yt, dt, tape, tlen, opts)
+        lam = torch.ones_like(y0)
+        glnk, ast = b.cells.adjoint_step(y0, tape, tlen, lam)
+        torch.cuda.synchronize()
+        return y, st, stats, tape, tlen, lam, glnk
+
+    ref = run()
+    order = b.cells.balance(ref[2])
+    assert sorted(order.tolist()) == list(range(300))
+    att = mcchem.stats_numpy(ref[2])
+    a = (att["steps"] + att["rejects"] + att["newton_fails"])[order]
+    assert np.all(np.diff(a) <= 0)  # longest first
+    for sched in (order, np.random.default_rng(1).permutation(300).astype(np.int32)):
+        b.cells.set_schedule(sched)
+        got = run()
+        for x, y in zip(ref, got):
+            if x.dtype == torch.float64 and x.dim() == 2 and x.shape[0] == 300:  # tapes: up to each length
+                for i in range(300):
+                    assert torch.equal(x[i, :int(ref[4][i])], y[i, :int(ref[4][i])])
+            else:
+                assert torch.equal(x, y)
+    b.cells.set_schedule(None)
+    assert torch.equal(run()[0], ref[0])
+
+
+def test_cell_schedule_rejects_non_permutations(dev):
+    m, c, _ = synth.workload("small10", 4)
+    b = Batch(dev, m, c)
+    for bad in ([0, 1, 2, 2], [0, 1, 2, 4], [-1, 0, 1, 2]):
+        with pytest.raises(mcchem.MccError, match="permutation"):
+            b.cells.set_schedule(np.array(bad, dtype=np.int32))
+    with pytest.raises(mcchem.MccError):
+        b.cells.set_schedule(np.arange(3, dtype=np.int32))
