@@ -68,9 +68,9 @@ def parse():
     ap.add_argument("--multicell", action="store_true",
                     help="the paper's Multi-cells mode: all cells one system with a shared step size "
                          "(the batch must fit on the device at once)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="choose the solver's dense-tail size by timing each choice on the first 2,048 cells "
-                         "(untimed, before the warm-up)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the compiler's dense-tail choice instead of timing each choice on the first "
+                         "8,192 cells (untimed, before the warm-up)")
     ap.add_argument("--ablation", action="store_true",
                     help="time the paper's Derivative kernel (thread per reaction, atomic adds; record and "
                          "inverted reaction data; with and without per-call host-device copies) beside "
@@ -231,13 +231,7 @@ def bench_ablation(args):
     m, c, dt = synth.workload(args.workload, args.cells)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    tuned = None
-    if args.autotune:
-        n = min(2048, c.n_cells)
-        sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
-        mech, tuned = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts())
-    else:
-        mech = mcchem.Mechanism(m, device=0)
+    mech = mcchem.Mechanism(m, device=0)  # f only: the solver's dense tail plays no part
     C = c.n_cells
     cells = mcchem.Cells(mech, C)
     cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
@@ -518,8 +512,8 @@ def main():
     m, c, dt = synth.workload(args.workload, args.cells)
     dev = torch.device("cuda:0")
     tuned = None
-    if args.autotune:
-        n = min(2048, c.n_cells)
+    if args.autotune and not args.multicell:  # Multi-cells is built for fewer tail sizes
+        n = min(8192, c.n_cells)
         sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
         mech, tuned = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts())
     else:

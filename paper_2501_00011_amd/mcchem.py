@@ -502,9 +502,12 @@ def autotune_solver(mech, cells, dt: float, opts: SolverOpts | None = None, devi
                     candidates=(0, 32, 48, 64), reps: int = 2):
     """Pick the solver's dense-tail size for `mech` by measurement: every
     candidate the mechanism admits is compiled, and one outer step of the
-    sample `cells` (a synth.Cells; a few thousand cells fill the device) is
-    timed with HIP events, best of `reps` after one warm-up.  Returns
-    (Mechanism compiled with the fastest choice, {choice: ms})."""
+    sample `cells` (a synth.Cells) is timed with HIP events, best of `reps`
+    after one warm-up step whose counters schedule the cells longest first
+    (Cells.balance).  The choice changes how many cells a compute unit holds
+    (LDS per cell), so the sample should fill the device several times over
+    (several thousand cells).  Returns (Mechanism compiled with the fastest
+    choice, {choice: ms})."""
     import torch
     dev = torch.device(f"cuda:{device}")
     T = torch.from_numpy(np.ascontiguousarray(cells.T)).to(dev)
@@ -527,10 +530,12 @@ def autotune_solver(mech, cells, dt: float, opts: SolverOpts | None = None, devi
             y.copy_(y0)
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
-            c.step(y, dt, opts, want_stats=False)
+            _, stats = c.step(y, dt, opts)
             b.record()
             torch.cuda.synchronize()
-            if r > 0:
+            if r == 0:
+                c.balance(stats)
+            else:
                 ts.append(a.elapsed_time(b))
         times[m_tail] = min(ts)
         c.close()
