@@ -183,24 +183,27 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     HostTables &t = m->t;
     m->device = device;
 
-    // LDS layout of one solver cell (doubles).
+    // LDS layout of one solver cell (doubles): the compact state (N + 1),
+    // k, one scratch region for the rates (f), the rate partials (Newton
+    // matrix) and the re-sampling matrix -- never live together -- and the LU.
+    constexpr int kTm = (kMaxOrder + 1) * (kMaxOrder + 1);
     m->off_y = 0;
-    m->off_k = t.NV + 1;
+    m->off_k = t.N + 1;
     m->off_r = m->off_k + t.R;
-    m->off_p = m->off_r;  // rates (f) and rate partials (Newton matrix) are never live together
-    m->off_lu = m->off_r + std::max(t.R, t.n_partials) + 1;
-    m->off_tm = m->off_lu + t.lu_nnz + 2;
-    m->lds_doubles = m->off_tm + (kMaxOrder + 1) * (kMaxOrder + 1);
+    m->off_p = m->off_r;
+    m->off_tm = m->off_r;
+    m->off_lu = m->off_r + std::max({t.R + 1, t.n_partials + 1, kTm});
+    m->lds_doubles = m->off_lu + t.lu_nnz + 2;
     {
         // reverse mode: the same regions for the transposed tables, then R + 1 scratch values
         const HostTables &a = m->ta;
         auto &d = m->adj;
         d.off_y = 0;
-        d.off_k = a.NV + 1;
+        d.off_k = a.N + 1;
         d.off_r = d.off_k + a.R;
-        d.off_lu = d.off_r + std::max(a.R, a.n_partials) + 1;
-        d.off_tm = d.off_lu + a.lu_nnz + 2;
-        d.off_w = d.off_tm + (kMaxOrder + 1) * (kMaxOrder + 1);
+        d.off_tm = d.off_r;
+        d.off_lu = d.off_r + std::max({a.R + 1, a.n_partials + 1, kTm});
+        d.off_w = d.off_lu + a.lu_nnz + 2;
         d.lds_doubles = d.off_w + a.R + 1;
         if (!adjoint_shape_supported(a.NS, a.M))
             d.unavailable = "no reverse-mode kernel for " + std::to_string(a.NS) + " species slots with a dense tail of " +
@@ -738,10 +741,12 @@ static SolveParams solve_params(mcc_cells *c, double *y, double dt, const mcc_so
     p.lu_ops = m->lu_ops;
     p.fwd_map = m->fwd_map;
     p.bwd_map = m->bwd_map;
-    for (int q = 0; q < kMaxSlots; ++q) {
+    for (int q = 0, base = 0; q < kMaxSlots; ++q) {
         p.fg_blocks[q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
         p.fg_base[q] = q < m->t.NS ? m->t.fg_base[q] : 0;
         p.slot_cols[q] = q < m->t.NS ? m->t.slot_cols[q] : 0;
+        p.ybase[q] = base;
+        base += p.slot_cols[q];
     }
     p.nm_blocks = m->t.nm_blocks;
     p.lu_blocks = m->t.lu_blocks;
@@ -793,10 +798,12 @@ mcc_status mcc_adjoint_step(const mcc_cells *c, const double *y0, const double *
     p.lu_ops = m->adj.lu_ops;
     p.fwd_map = m->adj.fwd_map;
     p.bwd_map = m->adj.bwd_map;
-    for (int q = 0; q < kMaxSlots; ++q) {
+    for (int q = 0, base = 0; q < kMaxSlots; ++q) {
         p.fg_blocks[q] = q < t.NS ? t.fg_blocks[q] : 0;
         p.fg_base[q] = q < t.NS ? t.fg_base[q] : 0;
         p.slot_cols[q] = q < t.NS ? t.slot_cols[q] : 0;
+        p.ybase[q] = base;
+        base += p.slot_cols[q];
     }
     p.nm_blocks = t.nm_blocks;
     p.lu_blocks = t.lu_blocks;

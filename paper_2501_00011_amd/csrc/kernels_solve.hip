@@ -122,7 +122,8 @@ struct Cell {
     {
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < NS; ++s) yv[s * kWave + lane] = v[s];
+        for (int s = 0; s < NS; ++s)
+            if (lane < p.slot_cols[s]) yv[p.ybase[s] + lane] = v[s];
         __syncthreads();
     }
 
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
     const int maxord = o.max_order < 1 ? 1 : (o.max_order > kMaxOrder ? kMaxOrder : o.max_order);
 
     for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
-    if (lane == 0) C.yv[p.NV] = 1.0;
+    if (lane == 0) C.yv[p.N] = 1.0;
     if (lane == 0) {
         C.lu[p.lu_nnz] = 0.0;
         C.lu[p.lu_nnz + 1] = 0.0;
@@ -941,7 +942,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParam
     double *wv = smem + a.off_w;
     const int lane = C.lane, N = p.N;
     for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
-    if (lane == 0) C.yv[p.NV] = 1.0;
+    if (lane == 0) C.yv[p.N] = 1.0;
     if (lane == 0) {
         C.lu[p.lu_nnz] = 0.0;
         C.lu[p.lu_nnz + 1] = 0.0;
@@ -1105,7 +1106,7 @@ __global__ __launch_bounds__(64) void replay_kernel(SolveParams p, ReplayParams 
     Cell<NS, M> C(p, smem);
     const int lane = C.lane, N = p.N;
     for (int j = lane; j < p.R; j += kWave) C.kv[j] = p.k[(int64_t)j * p.ld + cell];
-    if (lane == 0) C.yv[p.NV] = 1.0;
+    if (lane == 0) C.yv[p.N] = 1.0;
     if (lane == 0) {
         C.lu[p.lu_nnz] = 0.0;
         C.lu[p.lu_nnz + 1] = 0.0;

@@ -88,7 +88,7 @@ struct HostTables {
     std::vector<int32_t> rx_sp;       // [3 * R]
     std::vector<int32_t> nu_ptr, nu_sp;
     std::vector<double> nu_coef;
-    std::vector<int32_t> nu_vid;      // nu_sp as virtual indices of the solver's layout
+    std::vector<int32_t> nu_vid;      // nu_sp as indices of the solver's compact LDS state vector
     // the paper's Derivative kernel data (ablation): records and inverted
     std::vector<int32_t> paper_rec, paper_rec_inv;
     std::vector<double> paper_yld, paper_yld_inv;
@@ -105,8 +105,11 @@ struct HostTables {
     int M = 0, F = 0;                 // dense tail size and front size (F = N - M)
     int tail_base = 0;                // LU offset of the column-major tail block
     std::vector<int32_t> slot_cols;   // [NS]: columns (lanes) in use per slot
-    std::vector<int32_t> rx_reac;     // [4 * R]: virtual reactant ids (NV = one), pad
-    std::vector<int32_t> part;        // [4 * P]: j, o1, o2 (other slots, NV = one), own species
+    // The solver's LDS copy of the state is compact: virtual index (slot s,
+    // lane l) at ybase[s] + l, with ybase[s] the lanes in use of the slots
+    // before s (slot_cols); index N holds the constant 1.
+    std::vector<int32_t> rx_reac;     // [4 * R]: compact reactant ids (N = one), pad
+    std::vector<int32_t> part;        // [4 * P]: j, o1, o2 (other slots, compact ids, N = one), own species (virtual)
     // Op streams, laid out [block][lane][kBlk] so that a lane prefetches one
     // block (kBlk consecutive ops) with wide loads.
     // f gather: one stream per species slot (fg_blocks[s] blocks from block fg_base[s]).
@@ -167,6 +170,7 @@ struct SolveParams {
     const uint64_t *lu_ops;
     const uint16_t *fwd_map, *bwd_map;
     int32_t fg_blocks[kMaxSlots], fg_base[kMaxSlots], slot_cols[kMaxSlots];
+    int32_t ybase[kMaxSlots];  // compact LDS state vector: slot s at ybase[s] + lane
     int32_t nm_blocks, lu_blocks, NV, tail_base;
     int32_t N, R, P, lu_nnz;
     // LDS layout (offsets in doubles)

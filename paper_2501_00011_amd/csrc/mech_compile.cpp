@@ -493,7 +493,21 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
     for (int p = 0; p < N; ++p) t->vspecies[vpos[p]] = t->perm[p];
     t->vpos.assign(vpos.begin(), vpos.end());
     auto vid = [&](int species) { return vpos[t->iperm[species]]; };
-    const int ONE = t->NV;  // yv[NV] holds the constant 1
+    // The LDS copy of the state is compact: slot s keeps lanes 0..cols_s-1
+    // (the lanes in use are contiguous) at ybase[s] + lane, so the N values
+    // take N places and yv[N] holds the constant 1.
+    std::vector<int> cols(t->NS, 0), ybase(t->NS, 0);
+    for (int p = 0; p < N; ++p) cols[vpos[p] / kWave] = std::max(cols[vpos[p] / kWave], vpos[p] % kWave + 1);
+    for (int s = 1; s < t->NS; ++s) ybase[s] = ybase[s - 1] + cols[s - 1];
+    if (ybase[t->NS - 1] + cols[t->NS - 1] != N) {
+        *err = "internal: the solver's lanes in use are not contiguous";
+        return MCC_ERR_MECH;
+    }
+    auto yid = [&](int species) {
+        const int v = vid(species);
+        return ybase[v / kWave] + v % kWave;
+    };
+    const int ONE = N;
 
     // ---- LU storage: front entries row by row, then the tail column-major --
     std::vector<std::vector<int>> lpos(N, std::vector<int>(N, -1));
@@ -516,18 +530,18 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
     t->rx_reac.assign(4 * (size_t)R, ONE);
     for (int j = 0; j < R; ++j) {
         const int b = d->reac_ptr[j], e = d->reac_ptr[j + 1];
-        for (int q = b; q < e; ++q) t->rx_reac[4 * j + (q - b)] = vid(d->reac_idx[q]);
+        for (int q = b; q < e; ++q) t->rx_reac[4 * j + (q - b)] = yid(d->reac_idx[q]);
         t->rx_reac[4 * j + 3] = 0;
     }
     t->part.assign(4 * parts.size(), 0);
     for (size_t q = 0; q < parts.size(); ++q) {
         t->part[4 * q + 0] = parts[q].j;
-        t->part[4 * q + 1] = parts[q].o1 < N ? vid(parts[q].o1) : ONE;
-        t->part[4 * q + 2] = parts[q].o2 < N ? vid(parts[q].o2) : ONE;
-        t->part[4 * q + 3] = vid(parts[q].s);  // the species the partial is taken with respect to
+        t->part[4 * q + 1] = parts[q].o1 < N ? yid(parts[q].o1) : ONE;
+        t->part[4 * q + 2] = parts[q].o2 < N ? yid(parts[q].o2) : ONE;
+        t->part[4 * q + 3] = vid(parts[q].s);  // the species the partial is taken with respect to (virtual index)
     }
     t->nu_vid.resize(t->nu_sp.size());
-    for (size_t e = 0; e < t->nu_sp.size(); ++e) t->nu_vid[e] = vid(t->nu_sp[e]);
+    for (size_t e = 0; e < t->nu_sp.size(); ++e) t->nu_vid[e] = yid(t->nu_sp[e]);
     const int P = (int)parts.size();
     if (P + 1 >= (1 << kOffBits)) {
         *err = "too many rate partials for the 14-bit offsets of the solver tables";

@@ -22,20 +22,26 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
     const int N = t.N, R = t.R, P = t.n_partials, NS = t.NS, NV = t.NV, M = t.M;
     const int ZERO = t.lu_nnz, TRASH = t.lu_nnz + 1;
     int bad = 0;
-    std::vector<double> yv(NV + 1, 0.0), rv(R + 1, 0.0), pv(P + 1, 0.0), lu(t.lu_nnz + 2, 0.0);
-    for (int v = 0; v < NV; ++v)
-        if (t.vspecies[v] >= 0) yv[v] = y_species[t.vspecies[v]];
-    yv[NV] = 1.0;
+    std::vector<double> yv(N + 1, 0.0), rv(R + 1, 0.0), pv(P + 1, 0.0), lu(t.lu_nnz + 2, 0.0);
     auto chk = [&](long v, long n) {
         if (v < 0 || v >= n) bad++;
         return v < 0 || v >= n ? 0 : v;
     };
+    {  // the compact state vector: slot s, lane l at (lanes in use of earlier slots) + l
+        int base = 0;
+        for (int s = 0; s < NS; ++s) {
+            for (int l = 0; l < t.slot_cols[s]; ++l)
+                if (t.vspecies[s * 64 + l] >= 0) yv[chk(base + l, N)] = y_species[t.vspecies[s * 64 + l]];
+            base += t.slot_cols[s];
+        }
+    }
+    yv[N] = 1.0;
 
     // deriv: rates then the per-slot gathers
     for (int j = 0; j < R; ++j) {
-        double r = k[j] * yv[chk(t.rx_reac[4 * j], NV + 1)];
-        r *= yv[chk(t.rx_reac[4 * j + 1], NV + 1)];
-        r *= yv[chk(t.rx_reac[4 * j + 2], NV + 1)];
+        double r = k[j] * yv[chk(t.rx_reac[4 * j], N + 1)];
+        r *= yv[chk(t.rx_reac[4 * j + 1], N + 1)];
+        r *= yv[chk(t.rx_reac[4 * j + 2], N + 1)];
         rv[j] = r;
     }
     for (int s = 0; s < NS; ++s)
@@ -52,8 +58,8 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
 
     // Newton matrix
     for (int q = 0; q < P; ++q) {
-        double d = k[chk(t.part[4 * q], R)] * yv[chk(t.part[4 * q + 1], NV + 1)];
-        d *= yv[chk(t.part[4 * q + 2], NV + 1)];
+        double d = k[chk(t.part[4 * q], R)] * yv[chk(t.part[4 * q + 1], N + 1)];
+        d *= yv[chk(t.part[4 * q + 2], N + 1)];
         pv[q] = d;
     }
     std::vector<int> written(t.lu_nnz + 2, 0);

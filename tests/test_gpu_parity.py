@@ -980,7 +980,7 @@ def test_gradient_against_central_differences_of_the_replay(dev):
     for j in sel:
         fd = (replayed_loss(j, 1) - replayed_loss(j, -1)) / (2 * eps)
         print(f"log A_{j}: adjoint {gA[j]:.9g}, central difference {fd:.9g}")
-        assert abs(fd - gA[j]) <= 1e-5 * abs(gA[j]) + 1e-7 * float(loss), (j, fd, gA[j])
+        assert abs(fd - gA[j]) <= 1e-5 * abs(gA[j]) + 1e-7 * float(loss.detach()), (j, fd, gA[j])
     b.cells.set_rate_constants(k)
 
 
