@@ -289,6 +289,21 @@ def bench_ablation(args):
     print(json.dumps(out), flush=True)
 
 
+def _solver_mechanism(args, m, c, dt):
+    """The mechanism compiled with --dense-tail, or with the tail size the
+    autotuner measures fastest on (up to) the first 8,192 cells."""
+    from paper_2501_00011_amd import mcchem, synth
+    if args.dense_tail is not None:
+        return mcchem.Mechanism(m, device=0, dense_tail=args.dense_tail)
+    if not args.autotune:
+        return mcchem.Mechanism(m, device=0)
+    n = min(8192, c.n_cells)
+    sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
+    # the reverse-mode kernels are built for tails of 0, 32 and 48 rows
+    mech, _ = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts(), candidates=(0, 32, 48))
+    return mech
+
+
 def bench_adjoint(args):
     """Forward outer step with its step tape, then the reverse pass
     (mcc_adjoint_step) for dL/dy0 and dL/d ln k, each timed with events on
@@ -300,7 +315,7 @@ def bench_adjoint(args):
     m, c, dt = synth.workload(args.workload, args.cells)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    mech = mcchem.Mechanism(m, device=0)
+    mech = _solver_mechanism(args, m, c, dt)
     C, N, R = c.n_cells, m.n_species, m.n_reactions
     cells = mcchem.Cells(mech, C)
     cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
@@ -311,6 +326,7 @@ def bench_adjoint(args):
     opts = mcchem.default_opts()
     y.copy_(y0)
     cells.step(y, dt, opts, status, stats, stream=stream)
+    cells.balance(stats)  # the cells longest first, for all three launches
     sn = mcchem.stats_numpy(stats)
     attempts = sn["steps"] + sn["rejects"] + sn["newton_fails"]
     stride = int((4 + 8 * attempts + N * sn["steps"]).max())
@@ -361,6 +377,7 @@ def bench_adjoint(args):
                                       + oc["deriv_flops"])))
     out = {"metric": "reverse mode of one outer step (ms per launch, mean)",
            "workload": f"{N} species / {R} reactions, {C} cells, one {dt:g} s BDF step",
+           "dense_tail": mech.schedule_info()["dense_tail"], "cell_schedule": "longest first",
            "plain_forward_ms": round(t_plain, 3), "taped_forward_ms": round(t_taped, 3),
            "reverse_ms": round(t_rev, 3), "taping_overhead": t_taped / t_plain - 1.0,
            "reverse_over_forward": t_rev / t_plain,
@@ -398,12 +415,14 @@ def bench_gradient(args):
     m, c, dt = synth.workload("adjoint10k" if args.workload == "medium10k" else args.workload, args.cells)
     n_out = 10
     dev = torch.device("cuda:0")
-    mech = mcchem.Mechanism(m, device=0)
+    mech = _solver_mechanism(args, m, c, dt)
     C, N, R = c.n_cells, m.n_species, m.n_reactions
     cells = mcchem.Cells(mech, C)
     cells.bind(torch.from_numpy(c.T).to(dev), torch.from_numpy(c.P).to(dev), torch.from_numpy(c.jscale).to(dev))
     k = cells.rate_constants().clone()
     y0 = torch.from_numpy(c.y0).to(dev)
+    _, first = cells.step(y0.clone(), dt)
+    cells.balance(first)  # the cells longest first by their first outer step
     atol = mcchem.default_opts().atol
     with torch.no_grad():
         pert = torch.from_numpy(np.random.default_rng(5005).normal(0.0, 0.1, R)).to(dev)
@@ -430,6 +449,7 @@ def bench_gradient(args):
     tot = float(np.mean([a for a, _ in ts]))
     bwd = float(np.mean([b for _, b in ts]))
     out = {"metric": "gradient of the log loss wrt log A, 10 x 60 s forward + reverse (s per gradient)",
+           "dense_tail": mech.schedule_info()["dense_tail"], "cell_schedule": "longest first by the first step",
            "workload": f"{N} species / {R} reactions, {C} cells, 10 outer steps of {dt:g} s",
            "value": tot, "unit": "s", "higher_is_better": False,
            "forward_s": tot - bwd, "reverse_s": bwd, "reverse_over_forward": bwd / (tot - bwd),
