@@ -203,8 +203,10 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
         d.off_r = d.off_k + a.R;
         d.off_tm = d.off_r;
         d.off_lu = d.off_r + std::max({a.R + 1, a.n_partials + 1, kTm});
-        d.off_w = d.off_lu + a.lu_nnz + 2;
-        d.lds_doubles = d.off_w + a.R + 1;
+        // the R + 1 scratch values of the start entry, the last one reversed:
+        // no factorisation follows, so they may take the LU storage
+        d.off_w = a.lu_nnz + 2 >= a.R + 1 ? d.off_lu : d.off_lu + a.lu_nnz + 2;
+        d.lds_doubles = std::max(d.off_lu + a.lu_nnz + 2, d.off_w + a.R + 1);
         if (!adjoint_shape_supported(a.NS, a.M))
             d.unavailable = "no reverse-mode kernel for " + std::to_string(a.NS) + " species slots with a dense tail of " +
                             std::to_string(a.M);

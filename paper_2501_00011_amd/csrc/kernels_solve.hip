@@ -933,7 +933,8 @@ __global__ void fill_i32_kernel(int32_t *q, int32_t v)
 constexpr int kAdjMaxRPass = kAdjMaxR / kWave;  // reactions per lane
 
 template <int NS, int M>
-__global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParams a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void adjoint_kernel(
+    SolveParams p, AdjointParams a)
 {
     extern __shared__ double smem[];
     if ((int64_t)blockIdx.x >= p.n_cells) return;
@@ -1098,7 +1099,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(SolveParams p, AdjointParam
 // largest correction relative to its component is at most tol (or
 // max_newton iterations), then updates the differences as the solver does.
 template <int NS, int M>
-__global__ __launch_bounds__(64) void replay_kernel(SolveParams p, ReplayParams r)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void replay_kernel(
+    SolveParams p, ReplayParams r)
 {
     extern __shared__ double smem[];
     if ((int64_t)blockIdx.x >= p.n_cells) return;

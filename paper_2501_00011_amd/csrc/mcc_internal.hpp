@@ -220,7 +220,7 @@ struct AdjointParams {
     int32_t *status;       // [n_cells] or null
     const int32_t *nu_ptr, *nu_vid;  // net stoichiometry per reaction, virtual indices
     const double *nu_coef;
-    int32_t off_w;         // LDS offset (doubles) of R + 1 scratch values
+    int32_t off_w;         // LDS offset (doubles) of R + 1 scratch values (used after the last factorisation)
     int32_t accumulate;    // glnk += instead of =
 };
 constexpr int kAdjMaxR = 512;  // reactions per mechanism the reverse-mode kernel handles
