@@ -139,9 +139,16 @@ def cpu_baseline(m, c, dt, target_s):
         wall1 += time.perf_counter() - t0
         n1 += len(sel)
         start += len(sel)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / wall, "unit": "cell-timesteps/s", "cores": threads, "kind": "oracle",
             "sample": f"cells {warm}..{warm + n - 1} of {c.n_cells}, one {dt:g} s step each, "
                       f"{wall:.1f} s wall on {threads} OpenMP threads ({failed} failed)",
+            "host_cpu": model,
             "value_1_thread": n1 / wall1 if wall1 > 0 else None,
             "sample_1_thread": f"the next {n1} cells, {wall1:.1f} s wall on one thread"}
 
