@@ -378,8 +378,9 @@ mcc_status mcc_solve_step_multicell(mcc_cells *cells, double *y, double dt, cons
  * int32 [n_cells] or NULL: MCC_CELL_OK, MCC_CELL_SINGULAR, or
  * MCC_CELL_BAD_TAPE (that cell's outputs are NaN).  MCC_ERR_MECH when the
  * mechanism has no reverse-mode kernel (the reason in mcc_last_error()):
- * it is built for one or two species slots with no, a 32- or a 48-row dense
- * tail, and at most 512 reactions. */
+ * it is built for one or two species slots with no, a 32-, 48- or 64-row
+ * dense tail, three slots with a 64-row tail (up to about 190 species), and
+ * at most 512 reactions. */
 mcc_status mcc_adjoint_step(const mcc_cells *cells, const double *y0, const double *tape, const int64_t *tape_len,
                             int64_t tape_stride, double *lam, double *glnk, int32_t accumulate,
                             int32_t *cell_status, void *stream);

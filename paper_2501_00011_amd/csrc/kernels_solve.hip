@@ -1222,9 +1222,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
 // Multi-cells instantiations (small and 72-species class mechanisms).
 #define MCC_MULTICELL_VARIANTS(X) X(1, 0) X(2, 0) X(2, 48)
 
-// Reverse mode (the taping forward solver and the adjoint kernel), for the
-// shapes of small and 72-species class mechanisms.
-#define MCC_ADJOINT_VARIANTS(X) X(1, 0) X(2, 0) X(1, 32) X(2, 32) X(1, 48) X(2, 48)
+// Reverse mode (the taping forward solver, the adjoint and the replay
+// kernels), for the shapes of small, 72- and 150-species class mechanisms.
+#define MCC_ADJOINT_VARIANTS(X) X(1, 0) X(2, 0) X(1, 32) X(2, 32) X(1, 48) X(2, 48) X(1, 64) X(2, 64) X(3, 64)
 
 hipError_t prepare_solve_kernels(int max_lds_bytes)
 {

@@ -1035,3 +1035,45 @@ def test_cell_schedule_rejects_non_permutations(dev):
             b.cells.set_schedule(np.array(bad, dtype=np.int32))
     with pytest.raises(mcchem.MccError):
         b.cells.set_schedule(np.arange(3, dtype=np.int32))
+
+
+def test_reverse_mode_large_mechanism(dev, oracle_mod):
+    """The 150-species mechanism (three register slots, 64-row dense tail):
+    taped solve equal to the plain one, reverse pass and replay against the
+    oracle's adjoint and replay of the same tapes."""
+    m = synth.mech_large()
+    n, dt = 6, 60.0
+    c = synth.make_cells(m, n, seed=516)
+    b = Batch(dev, m, c, oracle_mod=oracle_mod)
+    N = m.n_species
+    info = b.h.schedule_info()
+    assert info["dense_tail"] == 64
+    y0 = b.y_dev()
+    y_plain = y0.clone()
+    st_plain, stats = b.cells.step(y_plain, dt)
+    sn = mcchem.stats_numpy(stats)
+    stride = int((4 + 8 * (sn["steps"] + sn["rejects"] + sn["newton_fails"]) + N * sn["steps"]).max())
+    tape = torch.empty((n, stride), dtype=torch.float64, device=dev)
+    tlen = torch.empty(n, dtype=torch.int64, device=dev)
+    y = y0.clone()
+    st, _ = b.cells.step_taped(y, dt, tape, tlen)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_plain) and np.all(st.cpu().numpy() == 0) and np.all(tlen.cpu().numpy() > 0)
+    rng = np.random.default_rng(17)
+    yd = y.cpu().numpy()
+    W = rng.normal(size=(N, n)) / np.maximum(np.abs(yd), 1.0)
+    lam = _t(W, dev)
+    glnk, ast = b.cells.adjoint_step(y0, tape, tlen, lam)
+    yr, rst = b.cells.replay_step(y0, tape, tlen)
+    torch.cuda.synchronize()
+    assert np.all(ast.cpu().numpy() == 0) and np.all(rst.cpu().numpy() == 0)
+    lam_g, g_g, yr = lam.cpu().numpy(), glnk.cpu().numpy(), yr.cpu().numpy()
+    k = b.cells.rate_constants().cpu().numpy()
+    tv, tl = tape.cpu().numpy(), tlen.cpu().numpy()
+    for i in range(n):
+        t = oracle_mod.Tape.from_values(b.o.lib, tape_format.to_oracle(tv[i, :tl[i]], N))
+        lr, gr = b.o.adjoint(k[:, i], c.y0[:, i], t, W[:, i])
+        assert np.abs(lam_g[:, i] - lr).max() <= 1e-9 * np.abs(lr).max()
+        assert np.abs(g_g[:, i] - gr).max() <= 1e-9 * np.abs(gr).max()
+        yo, _ = b.o.replay(k[:, i], c.y0[:, i], t)
+        assert np.abs(yr[:, i] - yo).max() <= 1e-10 * (np.abs(yo).max() + 1.0)
