@@ -942,7 +942,8 @@ def test_replay_rejects_bad_tapes(dev):
 def test_gradient_against_central_differences_of_the_replay(dev):
     """d L / d log A for 64 cells over 10 x 60 s (the adjoint workload's log
     loss and perturbed target) against central differences, h = 1e-6, of
-    the frozen step sequences replayed on the GPU, for six parameters."""
+    the frozen step sequences replayed on the GPU, for six parameters, and
+    d L / d y0 along one direction."""
     from paper_2501_00011_amd import autograd
     m, c, dt = synth.workload("adjoint10k", 64)
     C, N, R, n_out, eps = 64, m.n_species, m.n_reactions, 10, 1e-6
@@ -966,11 +967,12 @@ def test_gradient_against_central_differences_of_the_replay(dev):
         b.cells.step_taped(yy, dt, tape, tlen)
         tapes.append((tape, tlen))
 
-    def replayed_loss(j, sign):
+    def replayed_loss(j, sign, y_start=None):
         kp = k.clone()
-        kp[j] *= math.exp(sign * eps)
+        if j is not None:
+            kp[j] *= math.exp(sign * eps)
         b.cells.set_rate_constants(kp)
-        ys = y0
+        ys = y0 if y_start is None else y_start
         for tape, tlen in tapes:
             ys, st = b.cells.replay_step(ys, tape, tlen)
             assert int((st != 0).sum()) == 0
@@ -981,6 +983,16 @@ def test_gradient_against_central_differences_of_the_replay(dev):
         fd = (replayed_loss(j, 1) - replayed_loss(j, -1)) / (2 * eps)
         print(f"log A_{j}: adjoint {gA[j]:.9g}, central difference {fd:.9g}")
         assert abs(fd - gA[j]) <= 1e-5 * abs(gA[j]) + 1e-7 * float(loss.detach()), (j, fd, gA[j])
+    # d L / d y0 along a direction u (relative perturbations of every cell's state)
+    u = torch.from_numpy(np.random.default_rng(4).normal(size=tuple(y0.shape))).to(dev) * y0
+    y0g = y0.clone().requires_grad_(True)
+    lnk2 = torch.log(k)
+    yy2 = autograd.integrate(b.cells, y0g, lnk2, dt, n_out)
+    ((torch.log(yy2 + 1.0) - torch.log(target + 1.0)) ** 2).sum().backward()
+    adj = float((y0g.grad * u).sum())
+    fd = (replayed_loss(None, 0, y0 + eps * u) - replayed_loss(None, 0, y0 - eps * u)) / (2 * eps)
+    print(f"d L / d y0 along u: adjoint {adj:.9g}, central difference {fd:.9g}")
+    assert abs(fd - adj) <= 1e-5 * abs(adj) + 1e-7 * float(loss.detach())
     b.cells.set_rate_constants(k)
 
 
