@@ -26,6 +26,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+# vector-issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one 64-wide instruction per SIMD every 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wavefront-instructions/s
 
 
 SOLVE_SOURCES = ["paper_2501_00011_amd/csrc/kernels_solve.hip", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
@@ -36,9 +38,10 @@ FJ_KERNEL = "mcc_fj_generated2"  # the two-cell variant (even leading dimension)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_medium10k.txt")
 
 
-def measured_traffic(kernel, sources):
-    """HBM bytes per launch measured with rocprofv3 counters for this workload,
-    or None when the kernel's sources changed since the measurement."""
+def measured_counter(kernel, sources, key="traffic_bytes"):
+    """A per-launch figure measured with rocprofv3 counters for this workload
+    (HBM bytes, or the solver's vector instructions), or None when the
+    kernel's sources changed since the measurement."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -49,7 +52,32 @@ def measured_traffic(kernel, sources):
     for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return rec["traffic_bytes"] if h.hexdigest()[:16] == rec["source_sha256_16"] else None
+    return rec.get(key) if h.hexdigest()[:16] == rec["source_sha256_16"] else None
+
+
+def measured_traffic(kernel, sources):
+    return measured_counter(kernel, sources, "traffic_bytes")
+
+
+def solver_counter(key, n_cells, dense_tail):
+    """A counter figure of the solver launch, only for the configuration it
+    was measured in (10,000 cells, the recorded dense-tail size)."""
+    if n_cells != 10000 or measured_counter("bdf_kernel", SOLVE_SOURCES, "dense_tail") != dense_tail:
+        return None
+    return measured_counter("bdf_kernel", SOLVE_SOURCES, key)
+
+
+def issue_roofline(launch_s, n_cells, dense_tail):
+    """The solver launch against the vector-issue peak: its vector
+    instructions (SQ_INSTS_VALU, measured for this workload with the
+    scheduled build) per launch time, or None when not measured for the
+    current sources or this configuration."""
+    insts = solver_counter("valu_instructions", n_cells, dense_tail)
+    if insts is None:
+        return None
+    achieved = insts / launch_s
+    return {"achieved": achieved, "peak": VALU_ISSUE_PEAK, "unit": "wavefront-instructions/s",
+            "frac": achieved / VALU_ISSUE_PEAK, "instructions_per_launch": insts}
 
 
 def parse():
@@ -666,6 +694,9 @@ def main():
     except RuntimeError as e:  # capture refused: reported, not fatal
         print(f"f+J graph capture failed: {e}", file=sys.stderr)
 
+    # counter figures were taken for one scheduled launch per outer step
+    plain = args.steps_per_launch == 0 and not args.multicell and unbalanced_ms is not None
+    tail_measured = mech.schedule_info()["dense_tail"] if plain else None
     result = {
         "metric": "cell-timesteps/s (FP64, 1e-6 rel vs oracle); f+J evals/s as % HBM peak",
         "value": C * args.steps / wall,
@@ -692,8 +723,9 @@ def main():
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": measured_traffic("bdf_kernel", SOLVE_SOURCES) if C == 10000 else None,
-                     "launch_ms": solve_s * 1e3, "flops_per_launch": flops},
+                     "traffic": solver_counter("traffic_bytes", C, tail_measured),
+                     "launch_ms": solve_s * 1e3, "flops_per_launch": flops,
+                     "issue": issue_roofline(solve_s, C, tail_measured)},
         "fj_roofline": {"kernel": FJ_KERNEL + " (calc_deriv_jac, generated for this mechanism)", "bound": "hbm",
                         "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
                         "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
