@@ -17,12 +17,16 @@
 //               backward differences D[0..7], the Newton correction, ...;
 //               during the factorisation also the dense tail of the LU
 //               (lane = row).
-//   LDS       : the evaluation point y by virtual index (+ the constant 1),
-//               the cell's rate constants, reaction rates, rate partials, the
-//               LU factors (1/U_kk in place of U_kk; the tail block
-//               column-major; + a zero cell and a write-only cell), and the
-//               6 x 6 transform of a step-size change.
-//   HBM       : only y in/out, k in, status and stats out.
+//   LDS       : the evaluation point y, compact (slot s, lane l at the
+//               lanes in use of the earlier slots + l; then the constant 1),
+//               the cell's rate constants, one scratch region for the
+//               reaction rates, the rate partials or the 6 x 6 transform of a
+//               step-size change (never live together), and the LU factors
+//               (1/U_kk in place of U_kk; the tail block column-major; + a
+//               zero cell and a write-only cell).
+//   HBM       : y in/out, k in, status and stats out; in the per-launch form
+//               the solver state between launches; when taping, the step
+//               tape.
 #include <hip/hip_cooperative_groups.h>
 
 #include "mcc_internal.hpp"
@@ -541,11 +545,12 @@ struct GridSum {
     }
 };
 
-// Wavefronts per SIMD the kernel is compiled for: two for one or two register
-// slots (up to 128 species) with a dense tail of at most 48 rows, where the
-// second wavefront hides more latency than the few registers it spills cost
-// (measured: 387 -> 295 ms for 10,000 cells of 72 species); one for the
-// larger shapes, whose registers would spill heavily.
+// Wavefronts per SIMD the solver, reverse-mode and replay kernels are
+// compiled for: two for one or two register slots (up to 128 species) with a
+// dense tail of at most 48 rows, where the second wavefront hides more
+// latency than the few registers it spills cost (measured: 387 -> 295 ms for
+// 10,000 cells of 72 species); one for the larger shapes, whose registers
+// would spill heavily.
 template <int NS, int M>
 constexpr int kSolveWaves = (NS <= 2 && M <= 48) ? 2 : 1;
 
@@ -919,9 +924,9 @@ __global__ void fill_i32_kernel(int32_t *q, int32_t v)
 
 // Reverse mode of one outer step (the discrete adjoint of its frozen step
 // sequence), one wavefront per cell, with the solver tables of the
-// transposed system I - c J^T.  The tape holds, per cell, entries written
-// payload first: [z (n_species, species order) for a step] order, value,
-// type; it is walked backwards.  For an accepted step of order k with
+// transposed system I - c J^T.  The tape holds, per cell, entries [type,
+// z (n_species, species order; accepted steps only), order, value, type];
+// it is walked backwards.  For an accepted step of order k with
 // c = h / gamma_k at its converged state z: the difference update is
 // reversed, lam_d = lam_{k+1} + lam_{k+2}, mu = (I - c J(z))^-T lam_d (the
 // transposed matrix assembled, factorised and solved by the forward code),
