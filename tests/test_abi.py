@@ -150,5 +150,9 @@ def test_reverse_mode_entry_points_reject_null_handles():
     lib = mcchem.library()
     assert lib.mcc_adjoint_step(None, None, None, None, 0, None, None, 0, None, None) == 1
     assert b"cells is null" in lib.mcc_last_error()
-    assert lib.mcc_solve_step_taped(None, None, 60.0, None, None, None, None, None, 3, None) == 1
+    assert lib.mcc_solve_step_taped(None, None, 60.0, None, None, None, None, None, 4, None) == 1
+    assert b"cells is null" in lib.mcc_last_error()
+    assert lib.mcc_replay_step(None, None, None, None, 0, None, 50, 1e-15, None, None) == 1
+    assert b"cells is null" in lib.mcc_last_error()
+    assert lib.mcc_cells_set_schedule(None, None) == 1
     assert b"cells is null" in lib.mcc_last_error()
