@@ -36,6 +36,30 @@ def test_emulated_solver_phases_match_oracle(oracle_mod, mech_fn, c):
         assert np.max(np.abs(x - x_ref)) <= 1e-13 * cond * np.max(np.abs(x_ref))
 
 
+@pytest.mark.parametrize("tail", [0, 32, 48, 64])
+def test_emulated_solver_every_dense_tail(oracle_mod, tail):
+    """The 72-species mechanism compiled with every dense-tail size (the
+    autotuner's choices): f and the Newton solve from the tables, with the
+    compact state layout each size implies."""
+    m = synth.mech_medium()
+    h = mcchem.Mechanism(m, device=-1, dense_tail=tail)
+    assert h.schedule_info()["dense_tail"] == tail
+    o = oracle_mod.Oracle(m)
+    cells = synth.make_cells(m, 2, seed=37)
+    k = o.rate_constants(cells.T, cells.jscale)
+    f_ref, fs = o.deriv(k, cells.y0)
+    J_ref, _ = o.jac(k, cells.y0)
+    rng = np.random.default_rng(tail)
+    for cell in range(2):
+        b = rng.normal(size=m.n_species) * cells.y0[:, cell]
+        f, x, viol = h.emulate_cell(k[:, cell], cells.y0[:, cell], 1e-3, b)
+        assert viol == 0
+        assert np.all(np.abs(f - f_ref[:, cell]) <= 1e-12 * fs[:, cell])
+        M = np.eye(m.n_species) - 1e-3 * J_ref[cell]
+        resid = np.abs(M @ x - b)
+        assert np.all(resid <= 1e-12 * (np.abs(M) @ np.abs(x) + np.abs(b)))
+
+
 def test_emulator_handles_tiny_mechanisms():
     for rx in ([([0], [(1, 1.0)], 0.5, 0.0, 0)],
                [([0, 0, 0], [(1, 1.0)], 0.25, 0.0, 0)],
