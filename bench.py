@@ -80,6 +80,22 @@ def issue_roofline(launch_s, n_cells, dense_tail):
             "frac": achieved / VALU_ISSUE_PEAK, "instructions_per_launch": insts}
 
 
+def per_launch_state(sn, K, n_species, mech):
+    """HBM bytes the per-launch form moves for the solver state in one outer
+    step: a cell takes part in about L = ceil(steps / K) launches, writes
+    its state (backward differences [8][NS x 64] and 16 scalars, doubles)
+    at the end of all but the last and reads it at the start of all but the
+    first.  None for one launch."""
+    if K <= 0:
+        return None
+    import numpy as np
+    ns = len([b for b in mech.schedule_info()["fg_blocks"] if b > 0]) or 1
+    state_bytes = 8 * (8 * ns * 64 + 16)
+    launches = np.ceil(sn["steps"].astype(np.float64) / K)
+    return {"state_bytes_per_cell": state_bytes, "launches_max": int(launches.max()),
+            "bytes_per_outer_step": float(2 * state_bytes * np.maximum(launches - 1, 0).sum())}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -734,6 +750,7 @@ def main():
         "vjp_roofline": {"kernel": "mcc_vjp_generated2 (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
                          "achieved": vj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vj_gbs / HBM_PEAK_GBS,
                          "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes},
+        "per_launch_state": per_launch_state(sn, args.steps_per_launch, m.n_species, mech),
         "solver": {"failed_cells": int((st != 0).sum()),
                    "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),
                    "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),
