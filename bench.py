@@ -753,6 +753,7 @@ def main():
         "per_launch_state": per_launch_state(sn, args.steps_per_launch, m.n_species, mech),
         "solver": {"failed_cells": int((st != 0).sum()),
                    "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),
+                   "steps_percentiles": {str(q): float(np.percentile(sn["steps"], q)) for q in (1, 10, 50, 90, 99)},
                    "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),
                    "newton_per_attempt": float(sn["newton_iters"].sum() / max(sn["lu_count"].sum(), 1))},
     }
