@@ -397,6 +397,13 @@ mcc_status mcc_adjoint_step(const mcc_cells *cells, const double *y0, const doub
  * the device.  The Multi-cells solver ignores it. */
 mcc_status mcc_cells_set_schedule(mcc_cells *cells, const int32_t *order);
 
+/* mcc_cells_set_schedule with the cells ordered longest first by the step
+ * attempts (steps + rejects + newton_fails) of a previous outer step:
+ * stats device mcc_cell_stats [n_cells] as mcc_solve_step wrote them
+ * (copied to the host; synchronous).  Equal counts keep their cell order.
+ * order_out: host int32 [n_cells] receiving the schedule, or NULL. */
+mcc_status mcc_cells_schedule_from_stats(mcc_cells *cells, const mcc_cell_stats *stats, int32_t *order_out);
+
 /* Wait for all work of this batch's device and report any asynchronous error. */
 mcc_status mcc_sync(mcc_cells *cells);
 

@@ -1035,6 +1035,29 @@ mcc_status mcc_cells_set_schedule(mcc_cells *c, const int32_t *order)
     return ok();
 }
 
+mcc_status mcc_cells_schedule_from_stats(mcc_cells *c, const mcc_cell_stats *stats, int32_t *order_out)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    const int64_t n = c->n_cells;
+    if (n == 0) return ok();
+    if (!stats) return set_error(MCC_ERR_INVALID_ARG, "stats is null");
+    DeviceGuard g(c->mech->device);
+    std::vector<mcc_cell_stats> st((size_t)n);
+    hipError_t e = hipMemcpy(st.data(), stats, (size_t)n * sizeof(mcc_cell_stats), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_error(e, "copying the counters to the host");
+    // longest first: attempts = accepted steps + rejections + Newton failures
+    std::vector<int32_t> order((size_t)n);
+    for (int64_t i = 0; i < n; ++i) order[(size_t)i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const int64_t wa = (int64_t)st[a].steps + st[a].rejects + st[a].newton_fails;
+        const int64_t wb = (int64_t)st[b].steps + st[b].rejects + st[b].newton_fails;
+        return wa > wb;
+    });
+    const mcc_status r = mcc_cells_set_schedule(c, order.data());
+    if (r == MCC_OK && order_out) std::memcpy(order_out, order.data(), (size_t)n * sizeof(int32_t));
+    return r;
+}
+
 mcc_status mcc_sync(mcc_cells *c)
 {
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");

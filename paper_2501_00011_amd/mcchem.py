@@ -81,6 +81,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_solve_step_taped": ([vp, vp, dbl, vp, vp, vp, vp, vp, i64, vp], ctypes.c_int),
         "mcc_replay_step": ([vp, vp, vp, vp, i64, vp, i32, dbl, vp, vp], ctypes.c_int),
         "mcc_cells_set_schedule": ([vp, vp], ctypes.c_int),
+        "mcc_cells_schedule_from_stats": ([vp, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
@@ -396,11 +397,13 @@ class Cells:
 
     def balance(self, stats):
         """Schedule the cells longest first by their step attempts in stats
-        (the counters of a previous outer step).  Returns the order."""
-        sn = stats_numpy(stats)
-        attempts = sn["steps"].astype(np.int64) + sn["rejects"] + sn["newton_fails"]
-        order = np.argsort(-attempts, kind="stable").astype(np.int32)
-        self.set_schedule(order)
+        (device counters of a previous outer step; mcc_cells_schedule_from_stats).
+        Returns the order."""
+        import torch
+        order = np.empty(self.n_cells, dtype=np.int32)
+        _check(library().mcc_cells_schedule_from_stats(
+            self._h, _dptr(stats, "stats", torch.uint8, (self.n_cells, STATS_DTYPE.itemsize)),
+            order.ctypes.data))
         return order
 
     def set_rate_constants(self, k, stream=None):

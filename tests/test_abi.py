@@ -156,3 +156,5 @@ def test_reverse_mode_entry_points_reject_null_handles():
     assert b"cells is null" in lib.mcc_last_error()
     assert lib.mcc_cells_set_schedule(None, None) == 1
     assert b"cells is null" in lib.mcc_last_error()
+    assert lib.mcc_cells_schedule_from_stats(None, None, None) == 1
+    assert b"cells is null" in lib.mcc_last_error()

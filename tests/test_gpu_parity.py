@@ -1024,8 +1024,9 @@ def test_cell_schedule_leaves_results_unchanged(dev, K):
     order = b.cells.balance(ref[2])
     assert sorted(order.tolist()) == list(range(300))
     att = mcchem.stats_numpy(ref[2])
-    a = (att["steps"] + att["rejects"] + att["newton_fails"])[order]
-    assert np.all(np.diff(a) <= 0)  # longest first
+    attempts = (att["steps"] + att["rejects"] + att["newton_fails"]).astype(np.int64)
+    assert np.all(np.diff(attempts[order]) <= 0)  # longest first
+    assert np.array_equal(order, np.argsort(-attempts, kind="stable"))  # ties keep the cell order
     for sched in (order, np.random.default_rng(1).permutation(300).astype(np.int32)):
         b.cells.set_schedule(sched)
         got = run()
