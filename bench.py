@@ -570,8 +570,8 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the cells of this workload are independent and this "
-              "build measures one GPU's share; use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the cells of this workload are independent, so one GPU's "
+              "share is what it measures (sharding is by contiguous cell ranges); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.ablation:
         bench_ablation(args)
