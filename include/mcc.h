@@ -30,9 +30,11 @@
  *             device; the library never frees them and keeps no pointer past
  *             the call.  "host" pointers are ordinary host memory.
  *   Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
- *             stream).  Calls that take a stream only enqueue work and return;
- *             errors inside kernels surface at mcc_sync() or at the next
- *             synchronising call.  *_create and *_destroy synchronise.
+ *             stream).  Calls that take a stream only enqueue work and return
+ *             (except the per-launch solver form, which waits for each of its
+ *             launches); errors inside kernels surface at mcc_sync() or at
+ *             the next synchronising call.  *_create, *_destroy and the
+ *             schedule calls synchronise.
  *   Errors.   Every call returns an mcc_status; on anything but MCC_OK a
  *             message is available from mcc_last_error() (thread-local).
  *             Invalid arguments are rejected before any work is enqueued.
@@ -66,8 +68,10 @@ typedef enum {
     MCC_CELL_ERR_FAIL = 3,      /* error-test failures drove h below its minimum */
     MCC_CELL_NONFINITE = 4,     /* non-finite state or derivative */
     MCC_CELL_SINGULAR = 5,      /* zero/non-finite pivot drove h below its minimum
-                                   (mcc_adjoint_step: a singular transposed matrix) */
-    MCC_CELL_BAD_TAPE = 6       /* mcc_adjoint_step: the cell's tape is malformed */
+                                   (mcc_adjoint_step, mcc_replay_step: a singular
+                                   Newton matrix) */
+    MCC_CELL_BAD_TAPE = 6       /* mcc_adjoint_step, mcc_replay_step: the cell's
+                                   tape is malformed or did not fit */
 } mcc_cell_status;
 
 /* Reaction types. */
