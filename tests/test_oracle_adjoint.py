@@ -146,3 +146,23 @@ def test_tape_formats_round_trip_and_assign(oracle_mod):
     assert np.array_equal(lam1, lam2) and np.array_equal(g1, g2)
     buf, lens = tape_format.pack([dv, dv[:4]])
     assert lens.tolist() == [len(dv), 4] and np.isnan(buf[1, 4:]).all()
+
+
+@pytest.mark.parametrize("mech_fn,seed", [(synth.mech_small_thermal, 11), (synth.mech_medium, 12)])
+def test_replay_follows_the_taped_steps(oracle_mod, mech_fn, seed):
+    """The replay of a forward tape with the same rate constants lands on the
+    forward solution (the implicit steps differ only by the forward Newton
+    tolerance), and replaying a replayed tape changes nothing (its states
+    already solve their steps to round-off)."""
+    m = mech_fn()
+    o = oracle_mod.Oracle(m)
+    c = synth.make_cells(m, 1, seed=seed)
+    k = o.rate_constants(c.T, c.jscale)[:, 0]
+    y0 = c.y0[:, 0]
+    y, s, st, tape = o.solve_taped(k, y0, 60.0)
+    assert s == 0 and st["steps"] > 5
+    yr, rt = o.replay(k, y0, tape)
+    assert np.all(np.abs(yr - y) <= 1e-6 * np.abs(y) + 1e2)
+    assert len(rt) == len(tape)  # the same entries, the states replaced
+    yr2, _ = o.replay(k, y0, rt)
+    assert np.all(np.abs(yr2 - yr) <= 1e-12 * (np.abs(yr) + 1.0))
