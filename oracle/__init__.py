@@ -270,3 +270,49 @@ class Oracle:
 
     def max_threads(self) -> int:
         return int(self.lib.orc_max_threads())
+
+
+class Controller:
+    """ctypes view of the oracle's step-size controller (no mechanism): the
+    starting step's two stages, the factor after a failed error test and the
+    order and step-size selection, exactly as both the per-cell and the
+    Multi-cells solves call them."""
+
+    def __init__(self, lib_path: str = LIB_PATH):
+        if not os.path.exists(lib_path):
+            build(out=lib_path)
+        self.lib = L = ctypes.CDLL(lib_path)
+        vp, dbl, i32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32
+        L.orc_start_h0.argtypes = [i32, vp, vp, vp, dbl]
+        L.orc_start_h0.restype = dbl
+        L.orc_start_h.argtypes = [i32, vp, vp, vp, dbl, dbl]
+        L.orc_start_h.restype = dbl
+        L.orc_reject_factor.argtypes = [dbl, i32, dbl, dbl]
+        L.orc_reject_factor.restype = dbl
+        L.orc_select_order.argtypes = [i32, vp, vp, i32, i32, dbl, dbl, dbl, vp]
+        L.orc_select_order.restype = dbl
+
+    @staticmethod
+    def _vec(v):
+        return np.ascontiguousarray(v, dtype=np.float64)
+
+    def start_h0(self, y0, f0, w, dt) -> float:
+        y0, f0, w = self._vec(y0), self._vec(f0), self._vec(w)
+        return float(self.lib.orc_start_h0(len(y0), y0.ctypes.data, f0.ctypes.data, w.ctypes.data, float(dt)))
+
+    def start_h(self, f0, f1, w, h0, dt) -> float:
+        f0, f1, w = self._vec(f0), self._vec(f1), self._vec(w)
+        return float(self.lib.orc_start_h(len(f0), f0.ctypes.data, f1.ctypes.data, w.ctypes.data, float(h0),
+                                          float(dt)))
+
+    def reject_factor(self, err_norm, order, safety=0.9, fac_min=0.2) -> float:
+        return float(self.lib.orc_reject_factor(float(err_norm), int(order), float(safety), float(fac_min)))
+
+    def select_order(self, D, w, order, max_order, err_norm, safety=0.9, fac_max=10.0):
+        """D: difference table [order+3][n].  Returns (factor, new order)."""
+        D, w = self._vec(D), self._vec(w)
+        assert D.ndim == 2 and D.shape[0] >= order + 3 and D.shape[1] == len(w)
+        k = ctypes.c_int32(0)
+        fac = self.lib.orc_select_order(D.shape[1], D.ctypes.data, w.ctypes.data, int(order), int(max_order),
+                                        float(err_norm), float(safety), float(fac_max), ctypes.byref(k))
+        return float(fac), int(k.value)

@@ -35,9 +35,10 @@
  *
  * Parity pins (tests): finite-difference and homogeneity checks of J against
  * f, atom-balance conservation, hand-derived special cases, closed-form
- * solutions of small mechanisms, scipy.linalg.expm for linear mechanisms and
- * an independent implicit Runge-Kutta integrator (scipy Radau) on sampled
- * cells.
+ * solutions of small mechanisms, scipy.linalg.expm for linear mechanisms, an
+ * independent implicit Runge-Kutta integrator (scipy Radau) on sampled
+ * cells, and hand-worked values of the step-size controller (starting step,
+ * rejection factor, order selection) on constructed inputs.
  */
 #include <math.h>
 #include <stdint.h>
@@ -377,6 +378,68 @@ static int all_finite(int n, const double *v)
     return 1;
 }
 
+/* ------------------------------------------------- step-size controller */
+
+/* Starting step size, first stage (Hairer, Norsett & Wanner, Vol. I,
+ * Sec. II.4, starting step size algorithm, steps (a)-(b)): d0 = |y0|,
+ * d1 = |f(y0)| in the weighted norm; h0 = 0.01 d0 / d1, or 1e-6 dt when
+ * either is below 1e-5. */
+static double start_h0(int n, const double *y0, const double *f0, const double *w, double dt)
+{
+    const double d0 = wrms(n, y0, w), d1 = wrms(n, f0, w);
+    return (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+}
+
+/* Second stage (steps (c)-(f), order p = 1): with f1 = f(y0 + h0 f0),
+ * d2 = |f1 - f0| / h0, h1 = (0.01 / max(d1, d2))^(1/(p+1)), or
+ * max(1e-6, 1e-3 h0) when max(d1, d2) <= 1e-15; the step is
+ * min(100 h0, h1), and never beyond the end of the outer step. */
+static double start_h(int n, const double *f0, const double *f1, const double *w, double h0, double dt)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double t = (f1[i] - f0[i]) * w[i];
+        s += t * t;
+    }
+    const double d1 = wrms(n, f0, w), d2 = sqrt(s / n) / h0;
+    const double dm = d1 > d2 ? d1 : d2;
+    const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
+    return fmin(100.0 * h0, fmin(h1, dt));
+}
+
+/* Step-size factor after a failed error test of a step of the given order
+ * (local error ~ h^(order+1)): safety * err^(-1/(order+1)), at least fac_min.
+ * The order is kept. */
+static double reject_factor(double err_norm, int order, double safety, double fac_min)
+{
+    double fac = safety * pow(err_norm, -1.0 / (order + 1));
+    return fac < fac_min ? fac_min : fac;
+}
+
+/* Order and step-size selection once order+1 steps of equal size have been
+ * accepted (Shampine & Reichelt 1997, Sec. 2.3, with kappa = 0).  D holds the
+ * updated differences [order+3][n]: the error estimates of orders k-1, k and
+ * k+1 are |D_k| / k, err_norm (= |d| / (k+1)) and |D_{k+2}| / (k+2); each
+ * allows the factor e^(-1/(order'+1)); the largest wins, ties going to the
+ * current order, then the lower one.  Returns safety * best, at most
+ * fac_max, and the chosen order in *new_order. */
+static double select_order(int n, const double *D, const double *w, int order, int maxord, double err_norm,
+                           double safety, double fac_max, int *new_order)
+{
+    const double e_low = order > 1 ? wrms(n, D + (size_t)order * n, w) / order : INFINITY;
+    const double e_high = order < maxord ? wrms(n, D + (size_t)(order + 2) * n, w) / (order + 2) : INFINITY;
+    const double r_cur = pow(err_norm, -1.0 / (order + 1));
+    const double r_low = order > 1 ? pow(e_low, -1.0 / order) : 0.0;
+    const double r_high = order < maxord ? pow(e_high, -1.0 / (order + 2)) : 0.0;
+    int k = order;
+    double best = r_cur;
+    if (r_low > best) { best = r_low; k = order - 1; }
+    if (r_high > best) { best = r_high; k = order + 1; }
+    *new_order = k;
+    const double fac = safety * best;
+    return fac > fac_max ? fac_max : fac;
+}
+
 /* --------------------------------------------------------- BDF, one cell */
 
 typedef struct {
@@ -477,18 +540,12 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         return ORC_NONFINITE;
     for (int i = 0; i < N; ++i)
         wk->w[i] = 1.0 / (o->rtol * fabs(y[i]) + o->atol);
-    const double d0 = wrms(N, y, wk->w), d1 = wrms(N, wk->f, wk->w);
-    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+    const double h0 = start_h0(N, y, wk->f, wk->w, dt);
     for (int i = 0; i < N; ++i)
         wk->ycur[i] = y[i] + h0 * wk->f[i];
     cell_deriv(m, kc, wk->ycur, wk->tmp, NULL);
     st->f_evals++;
-    for (int i = 0; i < N; ++i)
-        wk->rhs[i] = wk->tmp[i] - wk->f[i];
-    const double d2 = wrms(N, wk->rhs, wk->w) / h0;
-    const double dm = d1 > d2 ? d1 : d2;
-    double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
-    double h = fmin(100.0 * h0, fmin(h1, dt));
+    double h = start_h(N, wk->f, wk->tmp, wk->w, h0, dt);
     if (!(h > 0.0) || !isfinite(h))
         return ORC_NONFINITE;
 
@@ -585,8 +642,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
             err_norm = wrms(N, wk->d, wk->w) / (order + 1);
             if (err_norm > 1.0) {
                 st->rejects++;
-                double fac = o->safety * pow(err_norm, -1.0 / (order + 1));
-                if (fac < o->fac_min) fac = o->fac_min;
+                const double fac = reject_factor(err_norm, order, o->safety, o->fac_min);
                 rescale_rec(N, D, order, fac, tape);
                 h *= fac;
                 n_equal = 0;
@@ -610,18 +666,8 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         if (n_equal < order + 1)
             continue;
         /* order and step-size selection after order+1 steps at constant h */
-        const double e_cur = err_norm;
-        const double e_low = order > 1 ? wrms(N, D + (size_t)order * N, wk->w) / order : INFINITY;
-        const double e_high = order < maxord ? wrms(N, D + (size_t)(order + 2) * N, wk->w) / (order + 2) : INFINITY;
-        const double r_cur = pow(e_cur, -1.0 / (order + 1));
-        const double r_low = order > 1 ? pow(e_low, -1.0 / order) : 0.0;
-        const double r_high = order < maxord ? pow(e_high, -1.0 / (order + 2)) : 0.0;
-        int new_order = order;
-        double best = r_cur;
-        if (r_low > best) { best = r_low; new_order = order - 1; }
-        if (r_high > best) { best = r_high; new_order = order + 1; }
-        double fac = o->safety * best;
-        if (fac > o->fac_max) fac = o->fac_max;
+        int new_order;
+        const double fac = select_order(N, D, wk->w, order, maxord, err_norm, o->safety, o->fac_max, &new_order);
         order = new_order;
         rescale_rec(N, D, order, fac, tape);
         h *= fac;
@@ -924,16 +970,11 @@ int orc_solve_multicell(const orc_mech *m, int64_t n_cells, const double *k, dou
     }
     for (int i = 0; i < NC; ++i) w[i] = 1.0 / (o->rtol * fabs(Y[i]) + o->atol);
     {
-        const double d0 = wrms(NC, Y, w), d1 = wrms(NC, f, w);
-        const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 * dt : 0.01 * d0 / d1;
+        const double h0 = start_h0(NC, Y, f, w, dt);
         for (int i = 0; i < NC; ++i) ycur[i] = Y[i] + h0 * f[i];
         SYS_DERIV(ycur, tmp);
         st->f_evals++;
-        for (int i = 0; i < NC; ++i) rhs[i] = tmp[i] - f[i];
-        const double d2 = wrms(NC, rhs, w) / h0;
-        const double dm = d1 > d2 ? d1 : d2;
-        const double h1 = dm <= 1e-15 ? fmax(1e-6, 1e-3 * h0) : sqrt(0.01 / dm);
-        h = fmin(100.0 * h0, fmin(h1, dt));
+        h = start_h(NC, f, tmp, w, h0, dt);
     }
     if (!(h > 0.0) || !isfinite(h)) {
         status = ORC_NONFINITE;
@@ -1027,8 +1068,7 @@ int orc_solve_multicell(const orc_mech *m, int64_t n_cells, const double *k, dou
                 err_norm = wrms(NC, d, w) / (order + 1);
                 if (err_norm > 1.0) {
                     st->rejects++;
-                    double fac = o->safety * pow(err_norm, -1.0 / (order + 1));
-                    if (fac < o->fac_min) fac = o->fac_min;
+                    const double fac = reject_factor(err_norm, order, o->safety, o->fac_min);
                     rescale_differences(NC, D, order, fac);
                     h *= fac;
                     n_equal = 0;
@@ -1051,18 +1091,8 @@ int orc_solve_multicell(const orc_mech *m, int64_t n_cells, const double *k, dou
             n_equal++;
             if (t >= dt) break;
             if (n_equal < order + 1) continue;
-            const double e_cur = err_norm;
-            const double e_low = order > 1 ? wrms(NC, D + (size_t)order * NC, w) / order : INFINITY;
-            const double e_high = order < maxord ? wrms(NC, D + (size_t)(order + 2) * NC, w) / (order + 2) : INFINITY;
-            const double r_cur = pow(e_cur, -1.0 / (order + 1));
-            const double r_low = order > 1 ? pow(e_low, -1.0 / order) : 0.0;
-            const double r_high = order < maxord ? pow(e_high, -1.0 / (order + 2)) : 0.0;
-            int new_order = order;
-            double best = r_cur;
-            if (r_low > best) { best = r_low; new_order = order - 1; }
-            if (r_high > best) { best = r_high; new_order = order + 1; }
-            double fac = o->safety * best;
-            if (fac > o->fac_max) fac = o->fac_max;
+            int new_order;
+            const double fac = select_order(NC, D, w, order, maxord, err_norm, o->safety, o->fac_max, &new_order);
             order = new_order;
             rescale_differences(NC, D, order, fac);
             h *= fac;
@@ -1117,4 +1147,32 @@ int orc_dense_solve(int32_t n, double *a, double *b)
         lu_solve(n, a, piv, b);
     free(piv);
     return s;
+}
+
+/* The step-size controller's pieces, exported for pinning: the two stages
+ * of the starting step (n components, weights w), the factor after a failed
+ * error test, and the order and step-size selection on a difference table
+ * D [order+3][n].  The per-cell and the Multi-cells solves both call these. */
+double orc_start_h0(int32_t n, const double *y0, const double *f0, const double *w, double dt)
+{
+    return start_h0(n, y0, f0, w, dt);
+}
+
+double orc_start_h(int32_t n, const double *f0, const double *f1, const double *w, double h0, double dt)
+{
+    return start_h(n, f0, f1, w, h0, dt);
+}
+
+double orc_reject_factor(double err_norm, int32_t order, double safety, double fac_min)
+{
+    return reject_factor(err_norm, order, safety, fac_min);
+}
+
+double orc_select_order(int32_t n, const double *D, const double *w, int32_t order, int32_t maxord, double err_norm,
+                        double safety, double fac_max, int32_t *new_order)
+{
+    int k;
+    const double fac = select_order(n, D, w, order, maxord, err_norm, safety, fac_max, &k);
+    *new_order = k;
+    return fac;
 }

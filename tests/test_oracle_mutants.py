@@ -44,6 +44,19 @@ MUTANTS = {
                                    "(i == j ? 1.0 : 0.0) - c * Jt[(size_t)i * N + j];"),
     "error_constant": ("err_norm = wrms(N, wk->d, wk->w) / (order + 1);",
                        "err_norm = wrms(N, wk->d, wk->w) / (order + 1) * 1e-3;"),
+    # the step-size controller (shared by the per-cell and Multi-cells solves)
+    "order_e_low_divisor": ("wrms(n, D + (size_t)order * n, w) / order : INFINITY;",
+                            "wrms(n, D + (size_t)order * n, w) / (order + 1) : INFINITY;"),
+    "order_r_high_exponent": ("pow(e_high, -1.0 / (order + 2))", "pow(e_high, -1.0 / (order + 1))"),
+    "order_tie_to_higher": ("if (r_high > best) { best = r_high; k = order + 1; }",
+                            "if (r_high >= best) { best = r_high; k = order + 1; }"),
+    "start_h0_constant": ("0.01 * d0 / d1", "0.1 * d0 / d1"),
+    "start_growth_cap": ("fmin(100.0 * h0, fmin(h1, dt))", "fmin(10.0 * h0, fmin(h1, dt))"),
+    "start_flat_fallback": ("fmax(1e-6, 1e-3 * h0)", "fmax(1e-6, 1e-2 * h0)"),
+    "order_selection_wait": ("        if (n_equal < order + 1)\n            continue;",
+                             "        if (n_equal < order)\n            continue;"),
+    "reject_exponent": ("double fac = safety * pow(err_norm, -1.0 / (order + 1));",
+                        "double fac = safety * pow(err_norm, -1.0 / order);"),
 }
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "handworked_fj.json")
@@ -221,8 +234,15 @@ def _pin_adjoint(lib):
     return abs(lam @ u - fd) <= 1e-5 * abs(fd) + 1e-12
 
 
+def _pin_controller(lib):
+    """Hand-worked starting steps, rejection factors and order selections,
+    and the first controller decisions of a solve followed by hand."""
+    from test_oracle_controller import check_controller, first_decisions_ok
+    return check_controller(lib) == [] and first_decisions_ok(lib)
+
+
 PINS = [_pin_handworked, _pin_fd_homogeneity_balance, _pin_pieces, _pin_closed_forms, _pin_radau_small, _pin_vjp,
-        _pin_adjoint]
+        _pin_adjoint, _pin_controller]
 
 
 def test_unmodified_oracle_passes_every_pin():
