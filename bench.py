@@ -727,7 +727,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{m.n_species} species / {m.n_reactions} reactions, {C} cells, "
-                               f"one {dt:g} s BDF step + rate constants + fused f/J per step",
+                               f"one {dt:g} s BDF step + rate constants + fused f/J per step; termolecular "
+                               f"pre-factors on the scaled reading (log-uniform 1e-14..1e-10 divided by "
+                               f"M_ref = {synth.M_REF:g} cm^-3)",
                    "cells": C, "species": m.n_species, "reactions": m.n_reactions, "dt_s": dt,
                    "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch,
                    "step_control": "multi-cells (shared)" if args.multicell else "per cell",
