@@ -363,6 +363,21 @@ mcc_status mcc_solve_step_taped(mcc_cells *cells, double *y, double dt, const mc
 mcc_status mcc_solve_step_multicell(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
                                     int32_t *cell_status, mcc_cell_stats *stats, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mcc_solve_step_multicell with the grid-wide reduction slots in a
+ * statically allocated device array of the library (256 KiB per device,
+ * held until the process ends) instead of memory the batch allocates on
+ * first use.  Arguments, results and errors as mcc_solve_step_multicell;
+ * MCC_ERR_INVALID_ARG for more than 16,384 cells.  The call itself
+ * allocates nothing (no hipMalloc or hipFree; the caller passes y, the
+ * statuses and the counters).  Every call on one device shares that
+ * device's slots: calls that overlap on one device (other streams, other
+ * threads) race and give wrong results; calls in sequence are independent
+ * (each writes every slot it reads). */
+mcc_status mcc_solve_step_multicell_noalloc(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
+                                            int32_t *cell_status, mcc_cell_stats *stats, void *stream);
+
 /* Reverse mode of one outer step (the discrete adjoint of the BDF step
  * sequence of mcc_solve_step, Section 2 solver, with that sequence frozen):
  * given lam = dL/dy(dt), overwrite lam with dL/dy0 and write (accumulate != 0:

@@ -963,8 +963,35 @@ static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solve
     return ok();
 }
 
+// The Multi-cells outer step; slots: caller-provided reduction slots
+// [2][n_cells] (the allocation-free entry point), or null for the batch's own.
+static mcc_status solve_step_multicell(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts,
+                                       int32_t *cell_status, mcc_cell_stats *stats, double *slots, void *stream);
+
 mcc_status mcc_solve_step_multicell(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts,
                                     int32_t *cell_status, mcc_cell_stats *stats, void *stream)
+{
+    return solve_step_multicell(c, y, dt, opts, cell_status, stats, nullptr, stream);
+}
+
+mcc_status mcc_solve_step_multicell_noalloc(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts,
+                                            int32_t *cell_status, mcc_cell_stats *stats, void *stream)
+{
+    if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
+    if (c->n_cells > kMcScratchCells)
+        return set_error(MCC_ERR_INVALID_ARG, "mcc_solve_step_multicell_noalloc handles at most " +
+                                                  std::to_string(kMcScratchCells) + " cells (its static reduction "
+                                                  "slots); this batch has " + std::to_string(c->n_cells));
+    DeviceGuard g(c->mech->device);
+    if (!g.ok()) return set_error(MCC_ERR_DEVICE, "cannot select the batch's device");
+    double *slots = nullptr;
+    const hipError_t e = multicell_scratch(c->mech->device, &slots);
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress (static Multi-cells slots)");
+    return solve_step_multicell(c, y, dt, opts, cell_status, stats, slots, stream);
+}
+
+static mcc_status solve_step_multicell(mcc_cells *c, double *y, double dt, const mcc_solver_opts *opts,
+                                       int32_t *cell_status, mcc_cell_stats *stats, double *slots, void *stream)
 {
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
     if (!c->bound) return set_error(MCC_ERR_STATE, "mcc_cells_bind has not been called");
@@ -988,7 +1015,7 @@ mcc_status mcc_solve_step_multicell(mcc_cells *c, double *y, double dt, const mc
     if (c->n_cells > cap)
         return set_error(MCC_ERR_INVALID_ARG, "Multi-cells needs every cell resident at once: at most " +
                                                   std::to_string(cap) + " cells of this mechanism on this device");
-    if (c->mc_cells < c->n_cells) {
+    if (!slots && c->mc_cells < c->n_cells) {
         if (c->mc_slots) (void)hipFree(c->mc_slots);
         c->mc_slots = nullptr;
         c->mc_cells = 0;
@@ -998,7 +1025,7 @@ mcc_status mcc_solve_step_multicell(mcc_cells *c, double *y, double dt, const mc
     }
     SolveParams p = solve_params(c, y, dt, o, cell_status, stats);
     p.order = nullptr;  // the grid-wide sums are taken in workgroup order: keep it the cell order
-    p.mc_slots = c->mc_slots;
+    p.mc_slots = slots ? slots : c->mc_slots;
     e = launch_solve_multicell(p, m->t.NS, m->t.M, (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "Multi-cells solver launch");
     return ok();

@@ -29,6 +29,9 @@
 //               tape.
 #include <hip/hip_cooperative_groups.h>
 
+#include <map>
+#include <mutex>
+
 #include "mcc_internal.hpp"
 
 namespace mcc {
@@ -1360,6 +1363,32 @@ hipError_t multicell_capacity(int NS, int M, size_t lds_bytes, int device, int64
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) *max_cells = (int64_t)per_cu * n_cu;
     return e;
+}
+
+// Multi-cells reduction slots, [2][kMcScratchCells] doubles, for the entry
+// point that allocates nothing (mcc_solve_step_multicell_noalloc).  Every
+// device the library runs on holds its own copy (256 KiB) until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol); it passes the device address that
+// hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) double scratch[2 * kMcScratchCells];
+
+hipError_t multicell_scratch(int device, double **ptr)
+{
+    static std::mutex mu;
+    static std::map<int, double *> addr;  // device -> address of that device's copy
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void *q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));  // the caller made `device` current
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double *>(q);
+    *ptr = static_cast<double *>(q);
+    return hipSuccess;
 }
 
 hipError_t launch_solve_multicell(const SolveParams &p, int NS, int M, hipStream_t s)

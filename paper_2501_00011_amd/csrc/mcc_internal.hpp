@@ -266,5 +266,10 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, hipStream_t s);  // *p = v by 
 // Multi-cells solver: largest co-resident batch (0: no kernel for this shape), cooperative launch.
 hipError_t multicell_capacity(int NS, int M, size_t lds_bytes, int device, int64_t *max_cells);
 hipError_t launch_solve_multicell(const SolveParams &p, int NS, int M, hipStream_t s);
+// Statically allocated Multi-cells reduction slots ([2][kMcScratchCells]
+// doubles per device): the device address of the current device's copy,
+// looked up once per device (that device must be current).
+constexpr int64_t kMcScratchCells = 16384;
+hipError_t multicell_scratch(int device, double **ptr);
 
 }  // namespace mcc

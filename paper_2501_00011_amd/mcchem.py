@@ -83,6 +83,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_cells_set_schedule": ([vp, vp], ctypes.c_int),
         "mcc_cells_schedule_from_stats": ([vp, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_solve_step_multicell_noalloc": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
         "mcc_cells_set_rate_constants": ([vp, vp, vp], ctypes.c_int),
         "mcc_debug_fj_source": ([vp, vp, i64, vp], ctypes.c_int),
@@ -447,15 +448,19 @@ class Cells:
             _dptr(tape_len, "tape_len", torch.int64, (self.n_cells,)), stride, _stream_ptr(stream)))
         return status, stats
 
-    def step_multicell(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, stream=None):
-        """The Multi-cells outer step: all cells as one system (shared h and order)."""
+    def step_multicell(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, stream=None,
+                       noalloc: bool = False):
+        """The Multi-cells outer step: all cells as one system (shared h and
+        order).  noalloc: the entry point that allocates nothing (static
+        reduction slots shared by every call on the device)."""
         import torch
         if status is None:
             status = torch.empty(self.n_cells, dtype=torch.int32, device=y.device)
         if stats is None:
             stats = torch.empty((self.n_cells, STATS_DTYPE.itemsize), dtype=torch.uint8, device=y.device)
         op = ctypes.addressof(opts) if opts is not None else None
-        _check(library().mcc_solve_step_multicell(
+        fn = library().mcc_solve_step_multicell_noalloc if noalloc else library().mcc_solve_step_multicell
+        _check(fn(
             self._h, _dptr(y, "y", torch.float64, self._yshape()), float(dt), op,
             _dptr(status, "status", torch.int32, (self.n_cells,)),
             _dptr(stats, "stats", torch.uint8, (self.n_cells, STATS_DTYPE.itemsize)), _stream_ptr(stream)))
