@@ -31,6 +31,7 @@ struct mcc_mech {
     const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
     const uint64_t *lu_ops = nullptr;
     const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
+    const uint16_t *schur_tab = nullptr;
     int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, off_tm = 0, lds_doubles = 0;
     int live_batches = 0;
     // mechanism-specialised f/J kernel, compiled on first use
@@ -46,6 +47,7 @@ struct mcc_mech {
         const Op16 *fg_ops = nullptr, *nm_ops = nullptr;
         const uint64_t *lu_ops = nullptr;
         const uint16_t *fwd_map = nullptr, *bwd_map = nullptr;
+        const uint16_t *schur_tab = nullptr;
         int32_t off_y = 0, off_k = 0, off_r = 0, off_lu = 0, off_tm = 0, off_w = 0, lds_doubles = 0;
         std::string unavailable;  // empty: the reverse-mode kernel runs for this mechanism
     } adj;
@@ -275,11 +277,11 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     const size_t o_preci = pk.add(t.paper_rec_inv), o_pyldi = pk.add(t.paper_yld_inv);
     const size_t o_perm = pk.add(t.vspecies), o_rxr = pk.add(t.rx_reac), o_part = pk.add(t.part);
     const size_t o_fg = pk.add(t.fg_ops), o_nm = pk.add(t.nm_ops), o_lu = pk.add(t.lu_ops);
-    const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map);
+    const size_t o_fwd = pk.add(t.fwd_map), o_bwd = pk.add(t.bwd_map), o_sch = pk.add(t.schur_tab);
     const HostTables &ta = m->ta;
     const size_t oa_perm = pk.add(ta.vspecies), oa_rxr = pk.add(ta.rx_reac), oa_part = pk.add(ta.part);
     const size_t oa_fg = pk.add(ta.fg_ops), oa_nm = pk.add(ta.nm_ops), oa_lu = pk.add(ta.lu_ops);
-    const size_t oa_fwd = pk.add(ta.fwd_map), oa_bwd = pk.add(ta.bwd_map);
+    const size_t oa_fwd = pk.add(ta.fwd_map), oa_bwd = pk.add(ta.bwd_map), oa_sch = pk.add(ta.schur_tab);
     const size_t oa_nup = pk.add(ta.nu_ptr), oa_nuv = pk.add(ta.nu_vid), oa_nuc = pk.add(ta.nu_coef);
     if ((e = hipMalloc(&m->dev_buf, pk.bytes.size())) != hipSuccess) {
         delete m;
@@ -311,6 +313,7 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     m->lu_ops = (const uint64_t *)(b + o_lu);
     m->fwd_map = (const uint16_t *)(b + o_fwd);
     m->bwd_map = (const uint16_t *)(b + o_bwd);
+    m->schur_tab = (const uint16_t *)(b + o_sch);
     m->adj.vspecies = (const int32_t *)(b + oa_perm);
     m->adj.rx_reac = (const int32_t *)(b + oa_rxr);
     m->adj.part = (const int32_t *)(b + oa_part);
@@ -319,6 +322,7 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     m->adj.lu_ops = (const uint64_t *)(b + oa_lu);
     m->adj.fwd_map = (const uint16_t *)(b + oa_fwd);
     m->adj.bwd_map = (const uint16_t *)(b + oa_bwd);
+    m->adj.schur_tab = (const uint16_t *)(b + oa_sch);
     m->adj.nu_ptr = (const int32_t *)(b + oa_nup);
     m->adj.nu_vid = (const int32_t *)(b + oa_nuv);
     m->adj.nu_coef = (const double *)(b + oa_nuc);
@@ -743,6 +747,8 @@ static SolveParams solve_params(mcc_cells *c, double *y, double dt, const mcc_so
     p.lu_ops = m->lu_ops;
     p.fwd_map = m->fwd_map;
     p.bwd_map = m->bwd_map;
+    p.schur_tab = m->schur_tab;
+    p.schur_ks = m->t.schur_ks;
     for (int q = 0, base = 0; q < kMaxSlots; ++q) {
         p.fg_blocks[q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
         p.fg_base[q] = q < m->t.NS ? m->t.fg_base[q] : 0;
@@ -800,6 +806,8 @@ mcc_status mcc_adjoint_step(const mcc_cells *c, const double *y0, const double *
     p.lu_ops = m->adj.lu_ops;
     p.fwd_map = m->adj.fwd_map;
     p.bwd_map = m->adj.bwd_map;
+    p.schur_tab = m->adj.schur_tab;
+    p.schur_ks = t.schur_ks;
     for (int q = 0, base = 0; q < kMaxSlots; ++q) {
         p.fg_blocks[q] = q < t.NS ? t.fg_blocks[q] : 0;
         p.fg_base[q] = q < t.NS ? t.fg_base[q] : 0;

@@ -103,6 +103,8 @@ struct Prefetcher {
 
 __device__ __forceinline__ int off_at(uint32_t v, int sh) { return (int)((v >> sh) & kOffMask); }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <int NS, int M>
 struct Cell {
     const SolveParams &p;
@@ -120,6 +122,10 @@ struct Cell {
     }
 
     __device__ __forceinline__ bool valid(int s) const { return vld[s]; }
+
+    // offset of entry (row, col) in the tail block (column-major, the rows
+    // of a column permuted against LDS bank conflicts: tail_at)
+    static __device__ __forceinline__ int tat(int row, int col) { return tail_at(M, row, col); }
 
     // order of slot s in the elimination order: the front slots 1.. come
     // before the dense tail in slot 0
@@ -292,62 +298,207 @@ struct Cell {
             if (__builtin_amdgcn_readfirstlane((int)barrier)) __syncthreads();
         }
         const bool front_bad = __any(bad);
+        schur();
         const bool tail_bad = dense_tail();
         return front_bad || tail_bad;
     }
 
-    // Dense tail (the Schur complement left by the front pivots): lane r
-    // holds row r in registers; pivot row k is broadcast one value at a time
-    // with readlane (which reads lane k whatever the execution mask).
-    // 1/U_kk replaces U_kk; the factors go back to the column-major LDS block
-    // (consecutive lanes, consecutive addresses).  Measured on MI355X against
-    // an LDS row buffer with broadcast reads, shuffles, and an LDS-resident
-    // factorisation, this is the fastest of the four.
+    // Schur complement of the front onto the dense tail: T -= L_TF U_FT with
+    // the FP64 16 x 16 x 4 matrix-core product (the tail block is dense after
+    // the fill-reducing order, so this is a dense contraction).  A k-step
+    // brings one 16 x 4 block of L per tile row and one 4 x 16 block of U per
+    // tile column (a lane holds entry (lane % 16, lane / 16) of an A block and
+    // (lane / 16, lane % 16) of a B block; structurally zero entries read the
+    // zero cell).  An accumulator tile holds, in lane l and register r, the
+    // entry (4 r + l / 16, l % 16); tiles start from and go back to the
+    // column-major tail block.  The operand offsets of SK k-steps arrive with
+    // one group of 16-byte loads per lane (the table is laid out [vector]
+    // [lane][8 offsets]); tile rows are taken TI at a time.
+    static constexpr int NT = M / 16;
+    static constexpr int SK = NT == 3 ? 4 : (NT > 0 ? 16 / NT : 1);  // k-steps per table group (2 NT SK % 8 == 0)
+    static constexpr int SV = (2 * NT * SK) / 8;                      // 16-byte vectors per group
+
+    __device__ __forceinline__ void schur()
+    {
+        if constexpr (M > 0) {
+            constexpr int TI = NT <= 2 ? NT : 1;
+            const int KS = p.schur_ks;
+            if (KS == 0) return;
+            const int g = lane >> 4, c16 = lane & 15;
+            double *tb = lu + p.tail_base;
+            const uint4 *tab = reinterpret_cast<const uint4 *>(p.schur_tab) + lane;
+#pragma unroll
+            for (int i0 = 0; i0 < NT; i0 += TI) {
+                v4d acc[TI][NT];
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[i][j][r] = tb[tat(16 * (i0 + i) + 4 * r + g, 16 * j + c16)];
+                for (int k0 = 0; k0 < KS; k0 += SK) {
+                    uint32_t w[4 * SV];
+#pragma unroll
+                    for (int v = 0; v < SV; ++v) {
+                        const uint4 o = tab[(size_t)((k0 / SK) * SV + v) * kWave];
+                        w[4 * v] = o.x;
+                        w[4 * v + 1] = o.y;
+                        w[4 * v + 2] = o.z;
+                        w[4 * v + 3] = o.w;
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < SK; ++kk) {
+                        if (k0 + kk >= KS) break;
+                        auto at = [&](int q) {
+                            const int e = kk * 2 * NT + q;
+                            return lu[(w[e >> 1] >> (16 * (e & 1))) & 0xffff];
+                        };
+                        double a[TI], b[NT];
+#pragma unroll
+                        for (int i = 0; i < TI; ++i) a[i] = -at(i0 + i);
+#pragma unroll
+                        for (int j = 0; j < NT; ++j) b[j] = at(NT + j);
+#pragma unroll
+                        for (int i = 0; i < TI; ++i)
+#pragma unroll
+                            for (int j = 0; j < NT; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) tb[tat(16 * (i0 + i) + 4 * r + g, 16 * j + c16)] = acc[i][j][r];
+            }
+            __syncthreads();
+        }
+    }
+
+    // Dense tail (the Schur complement left by the front pivots), M x M in
+    // LDS (entry (i, j) at tat(i, j)), factorised in place by blocked
+    // right-looking LU with panels of four columns:
+    //   1. the panel (its four columns, all rows): lane = row, the pivot row's
+    //      values broadcast with readlane; 1/U_kk replaces U_kk;
+    //   2. the panel's four rows right of it: U12 = L11^-1 A12, lane = column;
+    //   3. the trailing matrix: A22 -= L21 U12 with the FP64 16 x 16 x 4
+    //      matrix-core product on the 16 x 16 tiles that meet A22 (the
+    //      operands' entries outside A22 read as zero, so the rest of such a
+    //      tile is unchanged).
+    // Returns true if a pivot is zero, tiny or not finite (uniform).
     __device__ __forceinline__ bool dense_tail()
     {
         if constexpr (M == 0) {
             return false;
         } else {
+            double *T = lu + p.tail_base;
             const bool in = lane < M;
-            double a[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) a[c] = in ? lu[p.tail_base + c * M + lane] : 0.0;
+            const int row = in ? lane : 0;  // this lane's row (panel phase) or column (row phase)
+            const int g = lane >> 4, c16 = lane & 15;
             bool bad = false;
+#pragma unroll 1
+            for (int k0 = 0; k0 < M; k0 += 4) {
+                // 1. panel
+                double a[4];
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const double ukk = lane_bcast(a[k], k);
-                bad |= !(fabs(ukk) >= 1e-300) || !isfinite(ukk);
-                const double inv = 1.0 / ukk;
-                if (lane > k && in) {
-                    const double l = a[k] * inv;
-                    a[k] = l;
+                for (int c = 0; c < 4; ++c) a[c] = T[tat(row, k0 + c)];
 #pragma unroll
-                    for (int c = k + 1; c < M; ++c) a[c] -= l * lane_bcast(a[c], k);
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = k0 + kk;
+                    const double ukk = lane_bcast(a[kk], k);
+                    bad |= !(fabs(ukk) >= 1e-300) || !isfinite(ukk);
+                    const double inv = 1.0 / ukk;
+                    if (lane > k && in) {
+                        const double l = a[kk] * inv;
+                        a[kk] = l;
+#pragma unroll
+                        for (int c = kk + 1; c < 4; ++c) a[c] -= l * lane_bcast(a[c], k);
+                    }
+                    if (lane == k) a[kk] = inv;
                 }
-                if (lane == k) a[k] = inv;
-            }
-            __syncthreads();
+                if (in && lane >= k0)
 #pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (in) lu[p.tail_base + c * M + lane] = a[c];
-            __syncthreads();
-            return bad;
+                    for (int c = 0; c < 4; ++c) T[tat(row, k0 + c)] = a[c];
+                __syncthreads();
+                const int kt = k0 + 4;
+                if (kt >= M) break;
+                // 2. the panel's rows right of it (unit lower L11 from the panel)
+                if (lane >= kt && in) {
+                    const double l10 = T[tat(k0 + 1, k0)], l20 = T[tat(k0 + 2, k0)], l30 = T[tat(k0 + 3, k0)];
+                    const double l21 = T[tat(k0 + 2, k0 + 1)], l31 = T[tat(k0 + 3, k0 + 1)];
+                    const double l32 = T[tat(k0 + 3, k0 + 2)];
+                    const double u0 = T[tat(k0, row)];
+                    double u1 = T[tat(k0 + 1, row)], u2 = T[tat(k0 + 2, row)], u3 = T[tat(k0 + 3, row)];
+                    u1 -= l10 * u0;
+                    u2 -= l20 * u0;
+                    u2 -= l21 * u1;
+                    u3 -= l30 * u0;
+                    u3 -= l31 * u1;
+                    u3 -= l32 * u2;
+                    T[tat(k0 + 1, row)] = u1;
+                    T[tat(k0 + 2, row)] = u2;
+                    T[tat(k0 + 3, row)] = u3;
+                }
+                __syncthreads();
+                // 3. trailing update on the tiles that meet rows and columns >= kt
+                const int t0 = kt / 16;
+                double af[NT], bf[NT];
+#pragma unroll
+                for (int q = 0; q < NT; ++q)
+                    if (q >= t0) {
+                        const int rc = 16 * q + c16;
+                        af[q] = rc >= kt ? -T[tat(rc, k0 + g)] : 0.0;  // A(rc, g) = L(rc, k0 + g)
+                        bf[q] = rc >= kt ? T[tat(k0 + g, rc)] : 0.0;   // B(g, rc) = U(k0 + g, rc)
+                    }
+#pragma unroll
+                for (int i = 0; i < NT; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        if (i < t0 || j < t0) continue;
+                        v4d acc;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r] = T[tat(16 * i + 4 * r + g, 16 * j + c16)];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) T[tat(16 * i + 4 * r + g, 16 * j + c16)] = acc[r];
+                    }
+                __syncthreads();
+            }
+            return __any(bad);
         }
     }
 
     // b <- (LU)^-1 b with b held in registers by virtual index.  Columns are
     // swept in elimination order (front slots, then the tail in slot 0);
-    // each column's value is broadcast from its lane with readlane; the LU
-    // offsets of 8 columns come with one 16-byte load per slot, one block
-    // ahead.
+    // each column's value is broadcast from its lane with readlane.  For the
+    // front columns, the LU offsets of 8 columns come with one 16-byte load
+    // per slot, one block ahead; the dense tail block is addressed directly
+    // (column-major, lane = row).
     __device__ __forceinline__ void solve(double (&b)[NS])
     {
         const int NVB = p.NV / 8;
         const uint4 *fw = reinterpret_cast<const uint4 *>(p.fwd_map);
         const uint4 *bw = reinterpret_cast<const uint4 *>(p.bwd_map);
+        const double *T = lu + p.tail_base;
+        const int trow = M > 0 && lane < M ? lane : 0;  // this lane's tail row
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             const int ks = M > 0 ? (t + 1) % NS : t;
+            if (M > 0 && ks == 0) {
+                // tail columns: only tail rows (slot 0) lie below them
+#pragma unroll 1
+                for (int k8 = 0; k8 < M; k8 += 8) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int k = k8 + i;
+                        const double tv = T[tat(trow, k)];
+                        const double xk = lane_bcast(b[0], k);
+                        if (lane > k && lane < M) b[0] -= tv * xk;
+                    }
+                }
+                continue;
+            }
             const int ncol = p.slot_cols[ks];
             const int b0 = ks * 8, b1 = ks * 8 + (ncol + 7) / 8;
             if (b0 >= b1) continue;
@@ -383,6 +534,38 @@ struct Cell {
 #pragma unroll
         for (int t = NS - 1; t >= 0; --t) {
             const int ks = M > 0 ? (t + 1) % NS : t;
+            if (M > 0 && ks == 0) {
+                // tail columns (slot 0, blocks 0 .. M/8 - 1): the tail rows
+                // above (dense, addressed directly) and the front rows (slots
+                // 1.., their U entries from the map)
+                uint4 nxt[NS];
+#pragma unroll
+                for (int s = 1; s < NS; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + M / 8 - 1];
+#pragma unroll 1
+                for (int blk = M / 8 - 1; blk >= 0; --blk) {
+                    double v[NS][8];
+#pragma unroll
+                    for (int s = 1; s < NS; ++s) {
+                        const uint4 o = nxt[s];
+                        const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                    }
+                    if (blk > 0)
+#pragma unroll
+                        for (int s = 1; s < NS; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + blk - 1];
+#pragma unroll
+                    for (int i = 7; i >= 0; --i) {
+                        const int kl = blk * 8 + i;
+                        const double tv = T[tat(trow, kl)];  // 1/U_kk on the diagonal, U above it
+                        const double xk = lane_bcast(b[0] * tv, kl);
+                        b[0] = lane == kl ? xk : (lane < kl ? b[0] - tv * xk : b[0]);
+#pragma unroll
+                        for (int s = 1; s < NS; ++s) b[s] -= v[s][i] * xk;
+                    }
+                }
+                continue;
+            }
             const int ncol = p.slot_cols[ks];
             const int b0 = ks * 8, b1 = ks * 8 + (ncol + 7) / 8;
             if (b0 >= b1) continue;

@@ -16,6 +16,16 @@ constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kMaxOrder = 5;  // BDF orders 1..5
 constexpr int kMaxSlots = 4;  // species slots per lane in the solver: N <= 256
 constexpr int kBlk = 4;       // ops per lane per prefetched block of an op stream
+// The dense tail block (M x M, M a multiple of 16) is stored column-major
+// with the rows of column j permuted by row ^ 4 (j & m), m + 1 = (the largest
+// power of two dividing M) / 4: consecutive rows of a column stay contiguous,
+// while the 16 x 16 matrix-core tiles (16 columns of 4 rows per access) and
+// the k-step operand blocks spread over all LDS banks.
+__host__ __device__ constexpr int tail_swizzle_mask(int M) { return ((M & -M) >> 2) - 1; }
+__host__ __device__ constexpr int tail_at(int M, int row, int col)
+{
+    return col * M + (row ^ (4 * (col & tail_swizzle_mask(M))));
+}
 constexpr int kOffBits = 14;  // bits of an LDS offset inside an op
 constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
 // op flags (bits 56.. of an LU op; bits 28.. of a 16-byte op's meta word)
@@ -103,7 +113,7 @@ struct HostTables {
     std::vector<int32_t> vpos;        // [N]: virtual index of position p
     int NV = 0;                       // NS * 64
     int M = 0, F = 0;                 // dense tail size and front size (F = N - M)
-    int tail_base = 0;                // LU offset of the column-major tail block
+    int tail_base = 0;                // LU offset of the tail block (entry (i, j) at tail_base + tail_at(M, i, j))
     std::vector<int32_t> slot_cols;   // [NS]: columns (lanes) in use per slot
     // The solver's LDS copy of the state is compact: virtual index (slot s,
     // lane l) at ybase[s] + l, with ybase[s] the lanes in use of the slots
@@ -122,6 +132,23 @@ struct HostTables {
     // dst | l | u | d and flags in bits 56..; barrier flag ends a level.
     std::vector<uint64_t> lu_ops;
     int lu_blocks = 0, lu_steps = 0;
+    // Schur complement of the front pivots onto the dense tail, as FP64
+    // matrix-core products (16 x 16 x 4 blocks): the tail block T (M x M)
+    // receives T -= L_TF U_FT, where L_TF holds the final L entries of the tail
+    // rows in the front columns and U_FT the final U entries of the front rows
+    // in the tail columns.  schur_tab[(ks * 2 * nt + q) * 64 + lane] (nt =
+    // M / 16) is the LU offset of the operand a lane contributes to k-step ks:
+    // q < nt, the A block of tile row q (row F + 16 q + lane % 16, column
+    // 4 ks + lane / 16 of L); q >= nt, the B block of tile column q - nt (row
+    // 4 ks + lane / 16, column F + 16 (q - nt) + lane % 16 of U); the zero cell
+    // where the entry is structurally zero or beyond the front.  Stored as
+    // 16-bit offsets grouped for 16-byte loads: the entries of one lane in
+    // (ks, q) order, cut into vectors of 8; vector v of lane l at
+    // schur_tab[(v * 64 + l) * 8 ...].  A group of schur_sk k-steps fills
+    // whole vectors; the last group is padded with the zero cell.
+    std::vector<uint16_t> schur_tab;
+    int schur_sk = 0;                 // k-steps per group of vectors
+    int schur_ks = 0;                 // k-steps: ceil(F / 4)
     // Triangular solves: [slot][lane][NV] LU offsets per virtual column.
     std::vector<uint16_t> fwd_map, bwd_map;
     int64_t lu_lower = 0, lu_upper = 0;  // strictly lower / upper nonzeros of the sparse factors
@@ -169,6 +196,8 @@ struct SolveParams {
     const Op16 *fg_ops, *nm_ops;
     const uint64_t *lu_ops;
     const uint16_t *fwd_map, *bwd_map;
+    const uint16_t *schur_tab;  // Schur complement operands (HostTables::schur_tab)
+    int32_t schur_ks;
     int32_t fg_blocks[kMaxSlots], fg_base[kMaxSlots], slot_cols[kMaxSlots];
     int32_t ybase[kMaxSlots];  // compact LDS state vector: slot s at ybase[s] + lane
     int32_t nm_blocks, lu_blocks, NV, tail_base;

@@ -517,7 +517,8 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
             if (lp[i][j] && !(i >= F && j >= F)) lpos[i][j] = nlu++;
     t->tail_base = nlu;
     for (int j = F; j < N; ++j)
-        for (int i = F; i < N; ++i) lpos[i][j] = nlu++;
+        for (int i = F; i < N; ++i) lpos[i][j] = t->tail_base + tail_at(M, i - F, j - F);
+    nlu = t->tail_base + M * M;
     t->lu_nnz = nlu;
     if (nlu + 2 >= (1 << kOffBits)) {
         *err = "LU fill exceeds the 14-bit offset range of the solver tables";
@@ -649,6 +650,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
                 if (!lp[i][k]) continue;
                 for (int j = k + 1; j < N; ++j) {
                     if (!lp[k][j]) continue;
+                    if (i >= F && j >= F) continue;  // into the tail block: the Schur product below
                     by_dst[lpos[i][j]].push_back(lu_op(lpos[i][j], lpos[i][k], lpos[k][j], lpos[k][k], 0));
                 }
             }
@@ -666,6 +668,38 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         emit_step(chains);
     }
     t->lu_blocks = (int)(t->lu_ops.size() / (kWave * kBlk));
+
+    // ---- solver: Schur complement of the front onto the tail ----------------
+    // Every update of a tail entry by a front pivot, a_ij -= l_ik u_kj with
+    // i, j >= F and k < F, together: T -= L_TF U_FT once the front is done
+    // (its L columns scaled), in 16 x 16 x 4 matrix-core blocks.
+    t->schur_ks = 0;
+    t->schur_sk = 0;
+    t->schur_tab.clear();
+    if (M > 0 && F > 0) {
+        const int nt = M / 16, KS = (F + 3) / 4;
+        const int SK = nt == 3 ? 4 : 16 / nt;  // 2 nt SK offsets fill whole vectors of 8
+        const int groups = (KS + SK - 1) / SK, per_lane = groups * SK * 2 * nt;
+        t->schur_ks = KS;
+        t->schur_sk = SK;
+        t->schur_tab.assign((size_t)per_lane * kWave, (uint16_t)ZERO);
+        for (int ks = 0; ks < KS; ++ks)
+            for (int lane = 0; lane < kWave; ++lane) {
+                const int kc = 4 * ks + lane / 16;
+                if (kc >= F) continue;
+                for (int q = 0; q < 2 * nt; ++q) {
+                    const int e = ks * 2 * nt + q;  // this lane's e-th offset: vector e / 8, place e % 8
+                    const size_t at = ((size_t)(e / 8) * kWave + lane) * 8 + e % 8;
+                    if (q < nt) {
+                        const int row = F + 16 * q + lane % 16;
+                        if (lp[row][kc]) t->schur_tab[at] = (uint16_t)lpos[row][kc];
+                    } else {
+                        const int col = F + 16 * (q - nt) + lane % 16;
+                        if (lp[kc][col]) t->schur_tab[at] = (uint16_t)lpos[kc][col];
+                    }
+                }
+            }
+    }
 
     // ---- solver: column maps for the triangular solves ---------------------
     // [slot][lane][v]: for the column at virtual index v, the offset of L(p,k)

@@ -135,11 +135,39 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
     }
     if (!step_writes.empty()) bad++;  // the last level must end with a barrier
 
+    // Schur complement onto the tail in 16 x 16 x 4 blocks, as the matrix
+    // cores take them: for tile (I, J) and k-step ks, lane i + 16 kk holds
+    // A(i, kk) and lane j + 16 kk holds B(kk, j); T(16 I + i, 16 J + j) -=
+    // sum_kk A(i, kk) B(kk, j).  Operands must lie outside the tail block.
+    if (M > 0 && t.schur_ks > 0) {
+        const int nt = M / 16, KS = t.schur_ks, SK = t.schur_sk;
+        if (SK < 1 || (2 * nt * SK) % 8 || t.schur_tab.size() != (size_t)((KS + SK - 1) / SK) * SK * 2 * nt * kWave)
+            bad++;
+        auto opnd = [&](int ks, int q, int lane) {
+            const int e = ks * 2 * nt + q;
+            const size_t at = ((size_t)(e / 8) * kWave + lane) * 8 + e % 8;
+            const int o = at < t.schur_tab.size() ? (int)chk(t.schur_tab[at], t.lu_nnz + 1) : ZERO;
+            if (o >= t.tail_base && o < t.lu_nnz) bad++;  // an operand inside the tail block
+            return lu[o];
+        };
+        for (int I = 0; I < nt; ++I)
+            for (int J = 0; J < nt; ++J)
+                for (int i = 0; i < 16; ++i)
+                    for (int j = 0; j < 16; ++j) {
+                        double &dst = lu[t.tail_base + tail_at(M, 16 * I + i, 16 * J + j)];
+                        double acc = dst;
+                        for (int ks = 0; ks < KS; ++ks)
+                            for (int kk = 0; kk < 4; ++kk)
+                                acc -= opnd(ks, I, i + 16 * kk) * opnd(ks, nt + J, j + 16 * kk);
+                        dst = acc;
+                    }
+    }
+
     // dense tail: row r of the Schur complement, pivot rows broadcast
     if (M > 0) {
         std::vector<std::vector<double>> a(M, std::vector<double>(M));
         for (int r = 0; r < M; ++r)
-            for (int c = 0; c < M; ++c) a[r][c] = lu[t.tail_base + c * M + r];
+            for (int c = 0; c < M; ++c) a[r][c] = lu[t.tail_base + tail_at(M, r, c)];
         for (int kk = 0; kk < M; ++kk) {
             const double inv = 1.0 / a[kk][kk];
             for (int r = kk + 1; r < M; ++r) {
@@ -150,7 +178,7 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
             a[kk][kk] = inv;
         }
         for (int r = 0; r < M; ++r)
-            for (int c = 0; c < M; ++c) lu[t.tail_base + c * M + r] = a[r][c];
+            for (int c = 0; c < M; ++c) lu[t.tail_base + tail_at(M, r, c)] = a[r][c];
     }
 
     // triangular sweeps in elimination order over virtual columns; a column
