@@ -130,6 +130,10 @@ def parse():
     ap.add_argument("--fd-params", type=int, default=4,
                     help="with --gradient: parameters checked against central differences (h = 1e-6) of the "
                          "frozen step sequences replayed on the GPU")
+    ap.add_argument("--consecutive", type=int, default=5,
+                    help="after the timed steps, this many consecutive outer steps with y advancing and the "
+                         "cells scheduled longest first by the previous step's counters, cold and warm started "
+                         "(reported beside the headline; 0: skip)")
     ap.add_argument("--no-balance", action="store_true",
                     help="keep the identity cell schedule (no longest-first ordering from the previous step)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -148,9 +152,11 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
 
 
-def cpu_baseline(m, c, dt, target_s):
+def cpu_baseline(m, c, dt, target_s, y_gpu=None, atol=1.0):
     """The oracle as it stands, on all host threads it is given, on a bounded
-    sample of the same cells; cell-timesteps/s."""
+    sample of the same cells; cell-timesteps/s.  With y_gpu (the timed
+    step's output, [N][C] host array) the oracle's results for the sampled
+    cells are also compared with it: the parity of what was timed."""
     import numpy as np
     import oracle
     if not os.path.exists(oracle.LIB_PATH):
@@ -163,15 +169,21 @@ def cpu_baseline(m, c, dt, target_s):
     sel = np.arange(warm)
     o.solve(o.rate_constants(c.T[sel], c.jscale[sel]), c.y0[:, sel], dt)
     start, n, wall, failed = warm, 0, 0.0, 0
+    worst, compared = 0.0, 0
     while wall < target_s and start < c.n_cells:
         sel = np.arange(start, min(c.n_cells, start + chunk))
         k = o.rate_constants(c.T[sel], c.jscale[sel])
         t0 = time.perf_counter()
-        _, st, _ = o.solve(k, c.y0[:, sel], dt)
+        yo, st, _ = o.solve(k, c.y0[:, sel], dt)
         wall += time.perf_counter() - t0
         failed += int((st != 0).sum())
         n += len(sel)
         start += len(sel)
+        if y_gpu is not None:
+            ok = st == 0
+            err = np.abs(y_gpu[:, sel][:, ok] - yo[:, ok]) / (1e-6 * np.abs(yo[:, ok]) + 1e2 * atol)
+            worst = max(worst, float(err.max()) if err.size else 0.0)
+            compared += int(ok.sum())
     # the same oracle on one thread (the paper's single-thread baseline), a
     # shorter sample of the next cells
     n1, wall1 = 0, 0.0
@@ -189,12 +201,17 @@ def cpu_baseline(m, c, dt, target_s):
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n / wall, "unit": "cell-timesteps/s", "cores": threads, "kind": "oracle",
-            "sample": f"cells {warm}..{warm + n - 1} of {c.n_cells}, one {dt:g} s step each, "
-                      f"{wall:.1f} s wall on {threads} OpenMP threads ({failed} failed)",
-            "host_cpu": model,
-            "value_1_thread": n1 / wall1 if wall1 > 0 else None,
-            "sample_1_thread": f"the next {n1} cells, {wall1:.1f} s wall on one thread"}
+    out = {"value": n / wall, "unit": "cell-timesteps/s", "cores": threads, "kind": "oracle",
+           "sample": f"cells {warm}..{warm + n - 1} of {c.n_cells}, one {dt:g} s step each, "
+                     f"{wall:.1f} s wall on {threads} OpenMP threads ({failed} failed)",
+           "host_cpu": model,
+           "value_1_thread": n1 / wall1 if wall1 > 0 else None,
+           "sample_1_thread": f"the next {n1} cells, {wall1:.1f} s wall on one thread"}
+    if y_gpu is not None:
+        out["parity"] = {"cells": compared, "worst_ratio_to_bar": worst, "pass": bool(worst <= 1.0 and compared > 0),
+                         "bar": "|y_gpu - y_oracle| <= 1e-6 |y_oracle| + 1e2 atol, the timed step's output, "
+                                "cells of the oracle sample"}
+    return out
 
 
 def bench_mixed(args):
@@ -564,6 +581,43 @@ def bench_gradient(args):
     print(json.dumps(out), flush=True)
 
 
+def consecutive_steps(cells, y0, T, P, s, dt, args, stream):
+    """Consecutive outer steps as an application runs them: y advances from
+    step to step, and before each step the cells are scheduled longest first
+    by the previous step's counters (a prediction, not the step being timed);
+    once starting every step afresh, once warm started from the previous
+    step's step size.  Wall time per step, schedule upload included."""
+    import torch
+
+    from paper_2501_00011_amd import mcchem
+    out = {}
+    n = args.consecutive
+    for warm in (0, 1):
+        y = y0.clone()
+        cells.set_schedule(None)
+        _, stats = cells.step(y, dt, stream=stream)  # the first step, cold: sets the counters
+        torch.cuda.synchronize()
+        opts = mcchem.default_opts(warm_start=warm)
+        steps = []
+        t0 = time.perf_counter()
+        for _ in range(n):
+            cells.balance(stats)
+            st, stats = cells.step(y, dt, opts, stats=stats, stream=stream)
+            steps.append(stats.clone())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sn = [mcchem.stats_numpy(x) for x in steps]
+        out["warm" if warm else "cold"] = {
+            "value": cells.n_cells * n / wall, "ms_per_step": wall / n * 1e3,
+            "steps_mean": float(sum(x["steps"].mean() for x in sn) / n),
+            "failed_cells": int((st != 0).sum())}
+    cells.set_schedule(None)
+    out["note"] = (f"{n} consecutive {dt:g} s outer steps after a first cold one, y advancing, cells ordered "
+                   "longest first by the previous step's attempts; warm: first step size from the previous "
+                   "step (opts.warm_start)")
+    return out
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -759,9 +813,18 @@ def main():
                    "attempts_mean": float((sn["steps"] + sn["rejects"] + sn["newton_fails"]).mean()),
                    "newton_per_attempt": float(sn["newton_iters"].sum() / max(sn["lu_count"].sum(), 1))},
     }
+    if args.consecutive > 0 and not args.multicell:
+        result["consecutive_steps"] = consecutive_steps(cells, y0, T, P, s, dt, args, stream)
+    failed_parity = False
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(m, c, dt, args.cpu_seconds)
+        cb = cpu_baseline(m, c, dt, args.cpu_seconds, y_gpu=y.cpu().numpy(), atol=opts.atol)
+        result["parity"] = cb.pop("parity")
+        failed_parity = not result["parity"]["pass"]
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
+    if failed_parity:
+        print(f"bench: the timed output differs from the oracle ({result['parity']})", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -113,16 +113,27 @@ typedef struct {
  * every unfinished cell at most K accepted steps further, the cell's solver
  * state (backward differences, t, h, order, counters) kept in HBM between
  * launches, and the host relaunches until no cell is left (it waits for
- * each launch, so this form cannot be captured into a graph). */
+ * each launch, so this form cannot be captured into a graph).
+ * warm_start (0 or 1): 0 = every outer step starts afresh at order 1 with the
+ * Hairer-Norsett-Wanner starting step (the per-call re-initialisation of the
+ * solver that Section 3 describes for the per-cell calls); 1 = each cell
+ * starts at order 1 with the step size its previous outer step would have
+ * taken next, read from its stats record (stats->h_next, so stats must be
+ * given and hold that step's counters; a non-positive or non-finite h_next
+ * falls back to the starting-step algorithm), skipping the ramp up from a
+ * tiny first step.  The Multi-cells solver requires 0. */
 typedef struct {
     double rtol, atol, eta_newton, safety, fac_min, fac_max, fac_newton_fail, h_min_rel;
-    int32_t max_order, max_newton, max_steps, steps_per_launch;
+    int32_t max_order, max_newton, max_steps, steps_per_launch, warm_start;
 } mcc_solver_opts;
 
-/* Per-cell counters of one mcc_solve_step. */
+/* Per-cell counters of one mcc_solve_step.  h_last: the last step size
+ * taken (the landing step that ends on dt, usually shortened); h_next: the
+ * step size the controller had chosen before that shortening (the step the
+ * cell would take next; read back by warm_start). */
 typedef struct {
     int32_t steps, rejects, newton_fails, newton_iters, f_evals, jac_evals, lu_count, order;
-    double h_last, y_min;
+    double h_last, y_min, h_next;
 } mcc_cell_stats;
 
 typedef struct mcc_mech mcc_mech;
@@ -136,7 +147,8 @@ const char *mcc_version(void);
 
 /* Fill *opts with the defaults: rtol 1e-8, atol 1.0, eta_newton 0.03,
  * safety 0.9, fac_min 0.2, fac_max 10, fac_newton_fail 0.5, h_min_rel 1e-30,
- * max_order 5, max_newton 4, max_steps 100000. */
+ * max_order 5, max_newton 4, max_steps 100000, steps_per_launch 0,
+ * warm_start 0. */
 mcc_status mcc_solver_opts_default(mcc_solver_opts *opts);
 
 /* Validate a mechanism, compile its tables (Jacobian pattern, gather lists,
@@ -312,8 +324,10 @@ mcc_status mcc_cells_set_rate_constants(mcc_cells *cells, const double *k, void 
  * with a sparse Jacobian; Section 6: the whole solve on the GPU).
  * y: device [n_species][ld], overwritten with y(dt).  cell_status: device
  * int32 [n_cells] (mcc_cell_status).  stats: device mcc_cell_stats
- * [n_cells] or NULL.  opts: host, NULL = defaults.  A cell that fails keeps
- * its last accepted state; other cells are unaffected. */
+ * [n_cells] or NULL (required with opts->warm_start, which reads each
+ * record's h_next before overwriting the record).  opts: host, NULL =
+ * defaults.  A cell that fails keeps its last accepted state; other cells are
+ * unaffected. */
 mcc_status mcc_solve_step(mcc_cells *cells, double *y, double dt, const mcc_solver_opts *opts,
                           int32_t *cell_status, mcc_cell_stats *stats, void *stream);
 

@@ -46,19 +46,19 @@ class Opts(ctypes.Structure):
                 ("fac_min", ctypes.c_double), ("fac_max", ctypes.c_double),
                 ("fac_newton_fail", ctypes.c_double), ("h_min_rel", ctypes.c_double),
                 ("max_order", ctypes.c_int32), ("max_newton", ctypes.c_int32),
-                ("max_steps", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_fails", np.int32),
                         ("newton_iters", np.int32), ("f_evals", np.int32), ("jac_evals", np.int32),
                         ("lu_count", np.int32), ("order", np.int32),
-                        ("h_last", np.float64), ("y_min", np.float64)])
+                        ("h_last", np.float64), ("y_min", np.float64), ("h_next", np.float64)])
 
 
 def default_opts(rtol=1e-8, atol=1.0, **kw) -> Opts:
     """Solver constants: rtol 1e-8; atol 1 molecule cm^-3 (use ~1e-14 for O(1) tests)."""
     o = Opts(rtol=rtol, atol=atol, eta_newton=0.03, safety=0.9, fac_min=0.2, fac_max=10.0,
-             fac_newton_fail=0.5, h_min_rel=1e-30, max_order=5, max_newton=4, max_steps=100000)
+             fac_newton_fail=0.5, h_min_rel=1e-30, max_order=5, max_newton=4, max_steps=100000, warm_start=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -190,8 +190,9 @@ class Oracle:
                          gk.ctypes.data)
         return gy, gk
 
-    def solve(self, k, y0, dt, opts: Opts | None = None, n_threads: int = 0):
-        """One outer BDF step of length dt for every cell.
+    def solve(self, k, y0, dt, opts: Opts | None = None, n_threads: int = 0, h_warm=None):
+        """One outer BDF step of length dt for every cell.  h_warm [C]: the
+        first step sizes of a warm start (with opts.warm_start = 1).
 
         Returns (y [N][C], status [C] int32, stats structured array [C])."""
         if opts is None:
@@ -201,6 +202,8 @@ class Oracle:
         C = y.shape[1]
         status = np.empty(C, dtype=np.int32)
         stats = np.zeros(C, dtype=STATS_DTYPE)
+        if h_warm is not None:
+            stats["h_next"] = np.asarray(h_warm, dtype=np.float64)
         self.lib.orc_solve(self._mp(), C, k.ctypes.data, y.ctypes.data, float(dt),
                            ctypes.addressof(opts), status.ctypes.data, stats.ctypes.data,
                            int(n_threads))
@@ -220,12 +223,14 @@ class Oracle:
         return y, int(s), stats[0]
 
     # -- reverse mode through one outer step of one cell --------------------
-    def solve_taped(self, k_cell, y0_cell, dt, opts: Opts | None = None):
+    def solve_taped(self, k_cell, y0_cell, dt, opts: Opts | None = None, h_warm: float = 0.0):
         """One outer step of one cell (k [R], y0 [N]) recording its step
-        tape.  Returns (y, status, stats, tape)."""
+        tape (h_warm: the first step size of a warm start, with
+        opts.warm_start = 1).  Returns (y, status, stats, tape)."""
         k = np.ascontiguousarray(k_cell, dtype=np.float64)
         y = np.array(y0_cell, dtype=np.float64, copy=True)
         st = np.zeros(1, dtype=STATS_DTYPE)
+        st["h_next"] = h_warm
         tape = Tape(self.lib)
         o = opts or default_opts()
         s = self.lib.orc_cell_solve_taped(self._mp(), k.ctypes.data, y.ctypes.data, float(dt), ctypes.addressof(o),

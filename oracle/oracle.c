@@ -67,11 +67,13 @@ typedef struct {
     int32_t max_order;        /* 1..5 */
     int32_t max_newton;       /* Newton iterations per attempt */
     int32_t max_steps;        /* step attempts per outer step */
+    int32_t warm_start;       /* 1: start from the previous step's h_next (stats in/out) */
 } orc_opts;
 
 typedef struct {
     int32_t steps, rejects, newton_fails, newton_iters, f_evals, jac_evals, lu_count, order;
     double h_last, y_min;
+    double h_next;            /* the step size chosen before the landing cut */
 } orc_stats;
 
 enum { ORC_OK = 0, ORC_TOO_MUCH_WORK = 1, ORC_CONV_FAIL = 2, ORC_ERR_FAIL = 3,
@@ -523,9 +525,12 @@ static void rescale_rec(int N, double *D, int order, double rho, orc_tape *tape)
 }
 
 /* Integrate y' = f(y) of one cell from t = 0 to t = dt; y is overwritten
- * with y(dt).  Returns an ORC_* status. */
+ * with y(dt).  h_warm > 0 (finite): the first step size, taken at order 1
+ * instead of the starting-step algorithm (a warm start from the previous
+ * outer step's h_next; the paper's per-cell calls re-initialise the solver
+ * every time, Section 3).  Returns an ORC_* status. */
 static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
-                      const orc_opts *o, orc_stats *st, orc_work *wk, orc_tape *tape)
+                      const orc_opts *o, orc_stats *st, orc_work *wk, orc_tape *tape, double h_warm)
 {
     const int N = m->n_species;
     const int maxord = o->max_order < 1 ? 1 : (o->max_order > ORC_MAXORD ? ORC_MAXORD : o->max_order);
@@ -538,14 +543,19 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
     st->f_evals++;
     if (!all_finite(N, y) || !all_finite(N, wk->f))
         return ORC_NONFINITE;
-    for (int i = 0; i < N; ++i)
-        wk->w[i] = 1.0 / (o->rtol * fabs(y[i]) + o->atol);
-    const double h0 = start_h0(N, y, wk->f, wk->w, dt);
-    for (int i = 0; i < N; ++i)
-        wk->ycur[i] = y[i] + h0 * wk->f[i];
-    cell_deriv(m, kc, wk->ycur, wk->tmp, NULL);
-    st->f_evals++;
-    double h = start_h(N, wk->f, wk->tmp, wk->w, h0, dt);
+    double h;
+    if (h_warm > 0.0 && isfinite(h_warm)) {
+        h = fmin(h_warm, dt);
+    } else {
+        for (int i = 0; i < N; ++i)
+            wk->w[i] = 1.0 / (o->rtol * fabs(y[i]) + o->atol);
+        const double h0 = start_h0(N, y, wk->f, wk->w, dt);
+        for (int i = 0; i < N; ++i)
+            wk->ycur[i] = y[i] + h0 * wk->f[i];
+        cell_deriv(m, kc, wk->ycur, wk->tmp, NULL);
+        st->f_evals++;
+        h = start_h(N, wk->f, wk->tmp, wk->w, h0, dt);
+    }
     if (!(h > 0.0) || !isfinite(h))
         return ORC_NONFINITE;
 
@@ -555,7 +565,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
     }
     tape_op(tape, TAPE_START, 0, h, NULL, 0);
     int order = 1, n_equal = 0, attempts = 0;
-    double t = 0.0;
+    double t = 0.0, h_uncut = 0.0, h_next = 0.0;
 
     while (t < dt) {
         /* one accepted step: attempts until the error test passes */
@@ -564,13 +574,14 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         while (!accepted) {
             if (attempts >= o->max_steps) {
                 for (int i = 0; i < N; ++i) y[i] = D[i];
-                st->order = order; st->h_last = h;
+                st->order = order; st->h_last = h; st->h_next = h;
                 return ORC_TOO_MUCH_WORK;
             }
             attempts++;
             landing = 0;
             if (h >= dt - t) {
                 const double hn = dt - t;
+                h_uncut = h;
                 rescale_rec(N, D, order, hn / h, tape);
                 h = hn;
                 n_equal = 0;
@@ -633,7 +644,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
                 n_equal = 0;
                 if (h < o->h_min_rel * dt || t + h == t) {
                     for (int i = 0; i < N; ++i) y[i] = D[i];
-                    st->order = order; st->h_last = h;
+                    st->order = order; st->h_last = h; st->h_next = h;
                     return singular ? ORC_SINGULAR : ORC_CONV_FAIL;
                 }
                 continue;
@@ -648,7 +659,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
                 n_equal = 0;
                 if (h < o->h_min_rel * dt || t + h == t) {
                     for (int i = 0; i < N; ++i) y[i] = D[i];
-                    st->order = order; st->h_last = h;
+                    st->order = order; st->h_last = h; st->h_next = h;
                     return ORC_ERR_FAIL;
                 }
                 continue;
@@ -657,6 +668,7 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
         }
         /* accept: t advances, differences are updated */
         t = landing ? dt : t + h;
+        if (t >= dt) h_next = landing ? h_uncut : h;
         st->steps++;
         accept_differences(N, D, wk->d, order);
         tape_op(tape, TAPE_STEP, order, h / bdf_gamma(order), D, N);  /* z = the new D_0 */
@@ -681,11 +693,14 @@ static int cell_solve(const orc_mech *m, const double *kc, double *y, double dt,
     st->order = order;
     st->h_last = h;
     st->y_min = ymin;
+    st->h_next = h_next;
     return all_finite(N, y) ? ORC_OK : ORC_NONFINITE;
 }
 
 /* One outer step of length dt for every cell.  k: [R][C]; y: [N][C] in/out;
- * status: [C]; stats: [C] (may be NULL).  n_threads <= 0: OpenMP default.
+ * status: [C]; stats: [C] (may be NULL; with o->warm_start each record's
+ * h_next is read as the cell's first step size, then the record is
+ * overwritten).  n_threads <= 0: OpenMP default.
  * Returns the number of cells whose status is not ORC_OK. */
 int orc_solve(const orc_mech *m, int64_t n_cells, const double *k, double *y, double dt,
               const orc_opts *o, int32_t *status, orc_stats *stats, int n_threads)
@@ -707,7 +722,8 @@ int orc_solve(const orc_mech *m, int64_t n_cells, const double *k, double *y, do
             orc_stats st;
             gather_cell(k, R, n_cells, c, kc);
             gather_cell(y, N, n_cells, c, yc);
-            const int s = cell_solve(m, kc, yc, dt, o, &st, &wk, NULL);
+            const double h_warm = o->warm_start && stats ? stats[c].h_next : 0.0;
+            const int s = cell_solve(m, kc, yc, dt, o, &st, &wk, NULL, h_warm);
             scatter_cell(yc, N, n_cells, c, y);
             status[c] = s;
             if (stats) stats[c] = st;
@@ -738,14 +754,15 @@ void orc_tape_assign(orc_tape *t, const double *v, int64_t n)
 }
 
 /* One outer step of one cell as cell_solve, recording the tape.  kc [R],
- * y [N] in/out. */
+ * y [N] in/out; st out (with o->warm_start, st->h_next in). */
 int orc_cell_solve_taped(const orc_mech *m, const double *kc, double *y, double dt, const orc_opts *o,
                          orc_stats *st, orc_tape *tape)
 {
     orc_work wk;
     work_alloc(&wk, m->n_species);
     tape->n = 0;
-    const int s = cell_solve(m, kc, y, dt, o, st, &wk, tape);
+    const double h_warm = o->warm_start ? st->h_next : 0.0;
+    const int s = cell_solve(m, kc, y, dt, o, st, &wk, tape, h_warm);
     work_free(&wk);
     return s;
 }
@@ -934,7 +951,7 @@ void orc_cell_adjoint(const orc_mech *m, const double *kc, const double *y0, con
  * factorised block by block (the same elimination that dense LU with partial
  * pivoting performs on the whole matrix, whose pivot search never leaves a
  * block).  k: [R][C], y: [N][C] in/out; one status and one stats record for
- * the whole system. */
+ * the whole system.  Every call starts afresh (o->warm_start is not used). */
 int orc_solve_multicell(const orc_mech *m, int64_t n_cells, const double *k, double *y, double dt,
                         const orc_opts *o, orc_stats *st)
 {

@@ -20,6 +20,16 @@ import torch
 from . import mcchem
 
 
+def _check_forward(status: torch.Tensor) -> None:
+    """A cell that did not reach the end of its outer step (too much work, a
+    convergence, error-test or non-finite failure) has no derivative of the
+    map being differentiated: refuse it rather than return a state short of dt."""
+    if status.numel() and int((status != mcchem.CELL_OK).sum()) > 0:
+        bad = torch.unique(status[status != mcchem.CELL_OK]).tolist()
+        raise mcchem.MccError("forward step failed for some cells (status " +
+                              ", ".join(mcchem.CELL_STATUS.get(int(s), str(s)) for s in bad) + ")")
+
+
 class _Deriv(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y, lnk, cells):
@@ -59,9 +69,9 @@ class _SolveStep(torch.autograd.Function):
             if cells.n_cells == 0 or int(tape_len.min()) >= 0:
                 break
             stride *= 2  # a tape did not fit: the same step again with room for it
+        _check_forward(status)
         ctx.save_for_backward(y0, k, tape, tape_len)
         ctx.cells = cells
-        ctx.status = status
         return y
 
     @staticmethod
@@ -107,10 +117,10 @@ class _Integrate(torch.autograd.Function):
         for _ in range(n_steps):
             checkpoints.append(y.clone())  # the state each outer step starts from
             status, stats = cells.step(y, dt, opts, stats=stats)
+            _check_forward(status)
             stride = max(stride, _tape_bound(stats, N))
         ctx.save_for_backward(k, *checkpoints)
         ctx.cells, ctx.dt, ctx.opts, ctx.stride = cells, dt, opts, stride
-        ctx.status = status
         return y
 
     @staticmethod

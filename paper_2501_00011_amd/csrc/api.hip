@@ -146,6 +146,7 @@ mcc_status mcc_solver_opts_default(mcc_solver_opts *o)
     o->max_newton = 4;
     o->max_steps = 100000;
     o->steps_per_launch = 0;
+    o->warm_start = 0;
     return ok();
 }
 
@@ -731,6 +732,10 @@ static bool opts_valid(const mcc_solver_opts &o, std::string *why)
         *why = "need steps_per_launch >= 0";
         return false;
     }
+    if (o.warm_start != 0 && o.warm_start != 1) {
+        *why = "warm_start must be 0 or 1";
+        return false;
+    }
     return true;
 }
 
@@ -922,6 +927,8 @@ static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solve
     if (!opts_valid(o, &why)) return set_error(MCC_ERR_INVALID_ARG, why);
     if (c->n_cells == 0) return ok();
     if (!y || !cell_status) return set_error(MCC_ERR_INVALID_ARG, "y and cell_status must not be null");
+    if (o.warm_start && !stats)
+        return set_error(MCC_ERR_INVALID_ARG, "warm_start reads each cell's previous stats: stats must not be null");
     const mcc_mech *m = c->mech;
     DeviceGuard g(m->device);
     SolveParams p = solve_params(c, y, dt, o, cell_status, stats);
@@ -1012,6 +1019,7 @@ static mcc_status solve_step_multicell(mcc_cells *c, double *y, double dt, const
     std::string why;
     if (!opts_valid(o, &why)) return set_error(MCC_ERR_INVALID_ARG, why);
     if (o.steps_per_launch != 0) return set_error(MCC_ERR_INVALID_ARG, "Multi-cells runs in one launch: steps_per_launch must be 0");
+    if (o.warm_start != 0) return set_error(MCC_ERR_INVALID_ARG, "Multi-cells starts every step afresh: warm_start must be 0");
     if (c->n_cells == 0) return ok();
     if (!y || !cell_status) return set_error(MCC_ERR_INVALID_ARG, "y and cell_status must not be null");
     const mcc_mech *m = c->mech;
@@ -1078,7 +1086,9 @@ mcc_status mcc_cells_schedule_from_stats(mcc_cells *c, const mcc_cell_stats *sta
     if (!stats) return set_error(MCC_ERR_INVALID_ARG, "stats is null");
     DeviceGuard g(c->mech->device);
     std::vector<mcc_cell_stats> st((size_t)n);
-    hipError_t e = hipMemcpy(st.data(), stats, (size_t)n * sizeof(mcc_cell_stats), hipMemcpyDeviceToHost);
+    // the counters may come from work on any stream (e.g. a non-blocking one)
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(st.data(), stats, (size_t)n * sizeof(mcc_cell_stats), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_error(e, "copying the counters to the host");
     // longest first: attempts = accepted steps + rejections + Newton failures
     std::vector<int32_t> order((size_t)n);

@@ -740,6 +740,15 @@ struct GridSum {
 template <int NS, int M>
 constexpr int kSolveWaves = (NS <= 2 && M <= 48) ? 2 : 1;
 
+// The reverse-mode kernel holds the multipliers of the backward differences
+// and the per-reaction gradient in registers besides the solver's own state;
+// compiled for two wavefronts per SIMD it spills, and the 32-row-tail build
+// then returned wrong d L / d ln k (the multipliers stayed right; measured
+// against the oracle's adjoint).  It is compiled for one wavefront per SIMD,
+// where nothing spills.
+template <int NS, int M>
+constexpr int kAdjointWaves = 1;
+
 // MC: Multi-cells (one system over all cells); TAPE: record the step tape.
 template <int NS, int M, bool MC, bool TAPE = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void bdf_kernel(SolveParams p)
@@ -790,6 +799,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
     int steps = 0, rejects = 0, newton_fails = 0, newton_iters = 0, f_evals = 0, jac_evals = 0, lu_count = 0;
     int status = MCC_CELL_OK;
     double h = 0.0, t = 0.0;
+    double h_uncut = 0.0, h_next = 0.0;  // the step size before the landing cut, and the one to take next
     int order = 1, n_equal = 0, attempts = 0;
     bool bad = false;
     // step tape (reverse mode): start, re-samplings and accepted steps with
@@ -833,12 +843,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
         status = (int)st_s[14];
     } else {
         // ---- starting step size -------------------------------------------------
+        // warm start: the step size the cell's previous outer step would have taken next
+        const double h_warm = !MC && o.warm_start ? p.stats[cell].h_next : 0.0;
         C.deriv(D[0], f);
         f_evals++;
         bad = any_cell(C.any_nonfinite(D[0]) || C.any_nonfinite(f));
         if (bad) {
             status = MCC_CELL_NONFINITE;
             order = 0;
+        } else if (h_warm > 0.0 && isfinite(h_warm)) {
+            h = fmin(h_warm, dt);
         } else {
 #pragma unroll
             for (int s = 0; s < NS; ++s) w[s] = C.valid(s) ? 1.0 / (o.rtol * fabs(D[0][s]) + o.atol) : 0.0;
@@ -889,6 +903,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
                 attempts++;
                 landing = false;
                 if (h >= dt - t) {
+                    h_uncut = h;
                     const double hn = dt - t, rho = hn / h;
                     rescale<NS>(D, order, rho, C.tm);
                     record(1, order, rho, false);
@@ -978,6 +993,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
             }
             if (done) break;
             t = landing ? dt : t + h;
+            if (t >= dt) h_next = landing ? h_uncut : h;
             steps++;
             steps_here++;
 #pragma unroll
@@ -1094,6 +1110,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
             st.order = order;
             st.h_last = h;
             st.y_min = ymin;
+            st.h_next = status == MCC_CELL_OK ? h_next : h;
             p.stats[cell] = st;
         }
         if (K > 0) {  // finished: later launches of this outer step skip the cell
@@ -1124,7 +1141,7 @@ __global__ void fill_i32_kernel(int32_t *q, int32_t v)
 constexpr int kAdjMaxRPass = kAdjMaxR / kWave;  // reactions per lane
 
 template <int NS, int M>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void adjoint_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAdjointWaves<NS, M>))) void adjoint_kernel(
     SolveParams p, AdjointParams a)
 {
     extern __shared__ double smem[];

@@ -21,8 +21,8 @@ CELL_OK, CELL_SINGULAR, CELL_BAD_TAPE = 0, 5, 6
 STATS_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_fails", np.int32),
                         ("newton_iters", np.int32), ("f_evals", np.int32), ("jac_evals", np.int32),
                         ("lu_count", np.int32), ("order", np.int32),
-                        ("h_last", np.float64), ("y_min", np.float64)])
-assert STATS_DTYPE.itemsize == 48
+                        ("h_last", np.float64), ("y_min", np.float64), ("h_next", np.float64)])
+assert STATS_DTYPE.itemsize == 56
 
 
 class MccError(RuntimeError):
@@ -34,7 +34,8 @@ class SolverOpts(ctypes.Structure):
                 ("safety", ctypes.c_double), ("fac_min", ctypes.c_double), ("fac_max", ctypes.c_double),
                 ("fac_newton_fail", ctypes.c_double), ("h_min_rel", ctypes.c_double),
                 ("max_order", ctypes.c_int32), ("max_newton", ctypes.c_int32),
-                ("max_steps", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32)]
 
 
 class _MechDesc(ctypes.Structure):
@@ -416,7 +417,8 @@ class Cells:
     def step(self, y, dt, opts: SolverOpts | None = None, status=None, stats=None, want_stats=True,
              stream=None):
         """One outer step of length dt in place on y.  Returns (status, stats)
-        device tensors: int32 [n_cells] and uint8 [n_cells, 48] (see stats_numpy)."""
+        device tensors: int32 [n_cells] and uint8 [n_cells, 56] (see stats_numpy).
+        With opts.warm_start, stats must be the previous step's counters."""
         import torch
         if status is None:
             status = torch.empty(self.n_cells, dtype=torch.int32, device=y.device)
