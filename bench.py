@@ -367,8 +367,10 @@ def _solver_mechanism(args, m, c, dt):
         return mcchem.Mechanism(m, device=0)
     n = min(8192, c.n_cells)
     sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
-    # the reverse-mode kernels are built for tails of 0, 32 and 48 rows
-    mech, _ = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts(), candidates=(0, 32, 48))
+    # the reverse-mode kernels are built for tails of 0, 32 and 48 rows (and
+    # for the library's register budget only)
+    mech, _, _ = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts(), candidates=(0, 32, 48), waves=(0,),
+                                        schedules=("longest",))
     return mech
 
 
@@ -646,13 +648,15 @@ def main():
 
     m, c, dt = synth.workload(args.workload, args.cells)
     dev = torch.device("cuda:0")
-    tuned = None
+    tuned, choice = None, None
+    schedule = "longest"
     if args.dense_tail is not None:
         mech = mcchem.Mechanism(m, device=0, dense_tail=args.dense_tail)
     elif args.autotune and not args.multicell:  # Multi-cells is built for fewer tail sizes
         n = min(8192, c.n_cells)
         sample = synth.Cells(T=c.T[:n], P=c.P[:n], jscale=c.jscale[:n], y0=c.y0[:, :n])
-        mech, tuned = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts())
+        mech, tuned, choice = mcchem.autotune_solver(m, sample, dt, mcchem.default_opts())
+        schedule = choice[2]
     else:
         mech = mcchem.Mechanism(m, device=0)
     C = c.n_cells
@@ -694,7 +698,8 @@ def main():
         step(ev0)
         torch.cuda.synchronize()
         unbalanced_ms = ev0[0].elapsed_time(ev0[1])
-        cells.balance(stats)
+        if schedule != "identity":
+            cells.balance(stats, schedule)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -788,10 +793,13 @@ def main():
                    "rtol": opts.rtol, "atol": opts.atol, "steps_per_launch": args.steps_per_launch,
                    "step_control": "multi-cells (shared)" if args.multicell else "per cell",
                    "dense_tail": mech.schedule_info()["dense_tail"],
-                   "cell_schedule": "identity" if unbalanced_ms is None else
-                   "longest first by the previous outer step's attempts",
+                   "waves_per_simd": mech.schedule_info()["waves_per_simd"],
+                   "cell_schedule": "identity" if unbalanced_ms is None or schedule == "identity" else
+                   f"{schedule} by the previous outer step's attempts",
                    "solve_ms_identity_schedule": unbalanced_ms,
-                   "autotune_ms": {str(k): round(v, 2) for k, v in tuned.items()} if tuned else None},
+                   "autotune_ms": {k: round(v, 2) for k, v in tuned.items()} if tuned else None,
+                   "autotune_note": "keys: dense tail / wavefronts per SIMD / cell schedule; one outer step of "
+                                    "the first 8,192 cells" if tuned else None},
         "roofline": {"kernel": "bdf_kernel (solve_step)", "bound": "alu", "achieved": achieved_tf,
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_VALU_PEAK_TFLOPS,

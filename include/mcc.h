@@ -164,16 +164,23 @@ mcc_status mcc_solver_opts_default(mcc_solver_opts *opts);
 mcc_status mcc_mech_create(const mcc_mech_desc *desc, int device, mcc_mech **out);
 
 /* Choices the mechanism compiler otherwise makes itself.  dense_tail: the
- * number of trailing pivots of the solver's LU factorised as a dense block
- * in registers, one of 0, 32, 48, 64 (at most n_species), or -1 for the
- * compiler's cost model.  Results are the same mathematics either way; the
- * rounding order of the LU differs.  reserved: zero. */
+ * number of trailing pivots of the solver's LU factorised as a dense block,
+ * one of 0, 32, 48, 64 (at most n_species), or -1 for the compiler's cost
+ * model.  Results are the same mathematics either way; the rounding order of
+ * the LU differs.  waves_per_simd: the register budget of the solver build
+ * launched by mcc_solve_step -- 0 the library's choice (two wavefronts per
+ * SIMD for one or two species slots with a tail of at most 48, else one), 1
+ * one wavefront (more registers, fewer cells per compute unit; built for
+ * every shape), 2 two wavefronts (only where that is the library's choice;
+ * MCC_ERR_INVALID_ARG otherwise).  Results are identical bit for bit.
+ * reserved: zero. */
 typedef struct {
     int32_t dense_tail;
-    int32_t reserved[7];
+    int32_t waves_per_simd;
+    int32_t reserved[6];
 } mcc_mech_config;
 
-/* Fill *cfg with the defaults (dense_tail -1). */
+/* Fill *cfg with the defaults (dense_tail -1, waves_per_simd 0). */
 mcc_status mcc_mech_config_default(mcc_mech_config *cfg);
 
 /* mcc_mech_create with a configuration (NULL = defaults); an invalid choice
@@ -254,9 +261,10 @@ mcc_status mcc_debug_fj_source(const mcc_mech *mech, char *buf, int64_t cap, int
  * compiler log in mcc_last_error() on failure. */
 mcc_status mcc_debug_compile_fj(const mcc_mech *mech, const char *arch, int64_t *code_bytes);
 
-/* Testing aid: sizes of the solver schedule, written to out[0..7]: LU
+/* Testing aid: sizes of the solver schedule, written to out[0..8]: LU
  * blocks, LU levels, Newton-matrix blocks, f-gather blocks of slots 0..3,
- * and the size of the dense tail factorised in registers. */
+ * the size of the dense tail, and the wavefronts per SIMD of the solver
+ * build mcc_solve_step launches. */
 mcc_status mcc_debug_schedule_info(const mcc_mech *mech, int64_t *out);
 
 /* Release a mechanism.  MCC_ERR_STATE if cell batches created from it are
@@ -436,6 +444,15 @@ mcc_status mcc_cells_set_schedule(mcc_cells *cells, const int32_t *order);
  * (copied to the host; synchronous).  Equal counts keep their cell order.
  * order_out: host int32 [n_cells] receiving the schedule, or NULL. */
 mcc_status mcc_cells_schedule_from_stats(mcc_cells *cells, const mcc_cell_stats *stats, int32_t *order_out);
+
+/* mcc_cells_schedule_from_stats with a choice of order (the solver
+ * autotuner times them): MCC_SCHEDULE_LONGEST_FIRST as above, or
+ * MCC_SCHEDULE_ZIGZAG, the longest-first list taken alternately from its two
+ * ends (longest, shortest, second longest, ...).  MCC_ERR_INVALID_ARG for
+ * another kind. */
+enum { MCC_SCHEDULE_LONGEST_FIRST = 0, MCC_SCHEDULE_ZIGZAG = 1 };
+mcc_status mcc_cells_schedule_from_stats_ex(mcc_cells *cells, const mcc_cell_stats *stats, int32_t kind,
+                                            int32_t *order_out);
 
 /* Wait for all work of this batch's device and report any asynchronous error. */
 mcc_status mcc_sync(mcc_cells *cells);

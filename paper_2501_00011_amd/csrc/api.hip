@@ -34,6 +34,7 @@ struct mcc_mech {
     const uint16_t *schur_tab = nullptr;
     int32_t off_y = 0, off_k = 0, off_r = 0, off_p = 0, off_lu = 0, off_tm = 0, lds_doubles = 0;
     int live_batches = 0;
+    int solve_waves = 0;  // wavefronts per SIMD of the solver build launched
     // mechanism-specialised f/J kernel, compiled on first use
     int fj_kind = MCC_FJ_GENERATED;
     std::string arch;
@@ -177,6 +178,10 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     mcc_mech *m = new (std::nothrow) mcc_mech;
     if (!m) return set_error(MCC_ERR_OOM, "host allocation failed");
     std::string err;
+    if (c.waves_per_simd < 0 || c.waves_per_simd > 2) {
+        delete m;
+        return set_error(MCC_ERR_INVALID_ARG, "waves_per_simd must be 0, 1 or 2");
+    }
     mcc_status st = compile_mechanism(desc, c.dense_tail, &m->t, &err);
     if (st == MCC_OK) st = compile_mechanism(desc, c.dense_tail, &m->ta, &err, true);
     if (st != MCC_OK) {
@@ -185,6 +190,13 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
     }
     HostTables &t = m->t;
     m->device = device;
+    m->solve_waves = c.waves_per_simd ? c.waves_per_simd : solve_default_waves(t.NS, t.M);
+    if (!solve_waves_available(t.NS, t.M, m->solve_waves)) {
+        const std::string why = "no solver build for " + std::to_string(m->solve_waves) + " wavefronts per SIMD with " +
+                                std::to_string(t.NS) + " species slots and a dense tail of " + std::to_string(t.M);
+        delete m;
+        return set_error(MCC_ERR_INVALID_ARG, why);
+    }
 
     // LDS layout of one solver cell (doubles): the compact state (N + 1),
     // k, one scratch region for the rates (f), the rate partials (Newton
@@ -385,6 +397,7 @@ mcc_status mcc_debug_schedule_info(const mcc_mech *m, int64_t *out)
     out[2] = m->t.nm_blocks;
     for (int q = 0; q < 4; ++q) out[3 + q] = q < m->t.NS ? m->t.fg_blocks[q] : 0;
     out[7] = m->t.M;
+    out[8] = m->solve_waves;
     return ok();
 }
 
@@ -936,7 +949,7 @@ static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solve
     p.tape_len = tape_len;
     p.tape_stride = tape_stride;
     if (o.steps_per_launch <= 0) {  // the whole outer step in one launch
-        hipError_t e = launch_solve(p, m->t.NS, m->t.M, (hipStream_t)stream);
+        hipError_t e = launch_solve(p, m->t.NS, m->t.M, p.tape ? 0 : m->solve_waves, (hipStream_t)stream);
         if (e != hipSuccess) return hip_error(e, "solver kernel launch");
         return ok();
     }
@@ -969,7 +982,7 @@ static mcc_status solve_step(mcc_cells *c, double *y, double dt, const mcc_solve
     for (int64_t launch = 0;; ++launch) {
         if (launch >= max_launches) return set_error(MCC_ERR_DEVICE, "per-launch solver did not finish");
         hipError_t e = launch_fill_i32(c->pending, 0, s);
-        if (e == hipSuccess) e = launch_solve(p, m->t.NS, m->t.M, s);
+        if (e == hipSuccess) e = launch_solve(p, m->t.NS, m->t.M, p.tape ? 0 : m->solve_waves, s);
         if (e == hipSuccess) e = hipMemcpyAsync(c->pending_host, c->pending, sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_error(e, "per-launch solver");
@@ -1080,6 +1093,14 @@ mcc_status mcc_cells_set_schedule(mcc_cells *c, const int32_t *order)
 
 mcc_status mcc_cells_schedule_from_stats(mcc_cells *c, const mcc_cell_stats *stats, int32_t *order_out)
 {
+    return mcc_cells_schedule_from_stats_ex(c, stats, MCC_SCHEDULE_LONGEST_FIRST, order_out);
+}
+
+mcc_status mcc_cells_schedule_from_stats_ex(mcc_cells *c, const mcc_cell_stats *stats, int32_t kind,
+                                            int32_t *order_out)
+{
+    if (kind != MCC_SCHEDULE_LONGEST_FIRST && kind != MCC_SCHEDULE_ZIGZAG)
+        return set_error(MCC_ERR_INVALID_ARG, "unknown schedule kind");
     if (!c) return set_error(MCC_ERR_INVALID_ARG, "cells is null");
     const int64_t n = c->n_cells;
     if (n == 0) return ok();
@@ -1098,6 +1119,15 @@ mcc_status mcc_cells_schedule_from_stats(mcc_cells *c, const mcc_cell_stats *sta
         const int64_t wb = (int64_t)st[b].steps + st[b].rejects + st[b].newton_fails;
         return wa > wb;
     });
+    if (kind == MCC_SCHEDULE_ZIGZAG) {  // longest, shortest, second longest, second shortest, ...
+        std::vector<int32_t> z;
+        z.reserve((size_t)n);
+        for (int64_t lo = 0, hi = n - 1; lo <= hi; ++lo, --hi) {
+            z.push_back(order[(size_t)lo]);
+            if (hi != lo) z.push_back(order[(size_t)hi]);
+        }
+        order.swap(z);
+    }
     const mcc_status r = mcc_cells_set_schedule(c, order.data());
     if (r == MCC_OK && order_out) std::memcpy(order_out, order.data(), (size_t)n * sizeof(int32_t));
     return r;

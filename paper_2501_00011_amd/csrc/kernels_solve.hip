@@ -749,9 +749,10 @@ constexpr int kSolveWaves = (NS <= 2 && M <= 48) ? 2 : 1;
 template <int NS, int M>
 constexpr int kAdjointWaves = 1;
 
-// MC: Multi-cells (one system over all cells); TAPE: record the step tape.
-template <int NS, int M, bool MC, bool TAPE = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<NS, M>))) void bdf_kernel(SolveParams p)
+// MC: Multi-cells (one system over all cells); TAPE: record the step tape;
+// W: wavefronts per SIMD the registers are budgeted for.
+template <int NS, int M, bool MC, bool TAPE = false, int W = kSolveWaves<NS, M>>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W))) void bdf_kernel(SolveParams p)
 {
     extern __shared__ double smem[];
     if ((int64_t)blockIdx.x >= p.n_cells) return;
@@ -1427,6 +1428,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kSolveWaves<
     X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 32) X(2, 32) X(3, 32) X(4, 32) \
     X(1, 48) X(2, 48) X(3, 48) X(4, 48) X(1, 64) X(2, 64) X(3, 64) X(4, 64)
 
+// The shapes built for two wavefronts per SIMD also come built for one (the
+// solver autotuner times both).
+#define MCC_SOLVE_ONEWAVE_VARIANTS(X) X(1, 0) X(2, 0) X(1, 32) X(2, 32) X(1, 48) X(2, 48)
+
 // Multi-cells instantiations (small and 72-species class mechanisms).
 #define MCC_MULTICELL_VARIANTS(X) X(1, 0) X(2, 0) X(2, 48)
 
@@ -1443,6 +1448,12 @@ hipError_t prepare_solve_kernels(int max_lds_bytes)
                                 max_lds_bytes);
     MCC_SOLVE_VARIANTS(MCC_SET_LDS)
 #undef MCC_SET_LDS
+#define MCC_SET_LDS_1W(ns, m)                                                                                \
+    if (e == hipSuccess)                                                                                    \
+        e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m, false, false, 1>,                            \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes);
+    MCC_SOLVE_ONEWAVE_VARIANTS(MCC_SET_LDS_1W)
+#undef MCC_SET_LDS_1W
 #define MCC_SET_LDS_MC(ns, m)                                                                                \
     if (e == hipSuccess)                                                                                    \
         e = hipFuncSetAttribute((const void *)bdf_kernel<ns, m, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
@@ -1464,7 +1475,19 @@ hipError_t launch_fill_i32(int32_t *q, int32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
+int solve_default_waves(int NS, int M) { return (NS <= 2 && M <= 48) ? 2 : 1; }
+
+bool solve_waves_available(int NS, int M, int waves)
+{
+    if (waves == solve_default_waves(NS, M)) return true;
+#define MCC_1W_OK(ns, m) \
+    if (waves == 1 && NS == ns && M == m) return true;
+    MCC_SOLVE_ONEWAVE_VARIANTS(MCC_1W_OK)
+#undef MCC_1W_OK
+    return false;
+}
+
+hipError_t launch_solve(const SolveParams &p, int NS, int M, int waves, hipStream_t s)
 {
     if (p.n_cells == 0) return hipSuccess;
     if (p.n_cells > 0x7fffffff) return hipErrorInvalidValue;
@@ -1478,6 +1501,16 @@ hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s)
     }
         MCC_ADJOINT_VARIANTS(MCC_LAUNCH_TAPE)
 #undef MCC_LAUNCH_TAPE
+        return hipErrorInvalidValue;
+    }
+    if (waves != solve_default_waves(NS, M)) {
+#define MCC_LAUNCH_1W(ns, m)                                                                \
+    if (waves == 1 && NS == ns && M == m) {                                                 \
+        hipLaunchKernelGGL((bdf_kernel<ns, m, false, false, 1>), grid, block, lds, s, p); \
+        return hipGetLastError();                                                           \
+    }
+        MCC_SOLVE_ONEWAVE_VARIANTS(MCC_LAUNCH_1W)
+#undef MCC_LAUNCH_1W
         return hipErrorInvalidValue;
     }
 #define MCC_LAUNCH(ns, m)                                                         \

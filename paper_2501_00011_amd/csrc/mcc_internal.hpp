@@ -283,7 +283,10 @@ hipError_t launch_paper_deriv(const int32_t *rec, const double *yld, bool invert
                               const double *k, double *f, int N, int R, int64_t n_cells, hipStream_t s);  // appended to the f/J source: one module
 constexpr int kVjpRxnGroup = 16;  // reactions per d/d ln k work item
 bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log);
-hipError_t launch_solve(const SolveParams &p, int NS, int M, hipStream_t s);
+// waves: wavefronts per SIMD of the build to launch (solve_waves_available).
+hipError_t launch_solve(const SolveParams &p, int NS, int M, int waves, hipStream_t s);
+int solve_default_waves(int NS, int M);
+bool solve_waves_available(int NS, int M, int waves);
 // Raise the dynamic-LDS limit of the solver kernels (once per device).
 hipError_t prepare_solve_kernels(int max_lds_bytes);
 // Reverse-mode kernels: shapes available, LDS limit, launch.

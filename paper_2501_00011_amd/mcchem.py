@@ -83,6 +83,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_replay_step": ([vp, vp, vp, vp, i64, vp, i32, dbl, vp, vp], ctypes.c_int),
         "mcc_cells_set_schedule": ([vp, vp], ctypes.c_int),
         "mcc_cells_schedule_from_stats": ([vp, vp, vp], ctypes.c_int),
+        "mcc_cells_schedule_from_stats_ex": ([vp, vp, i32, vp], ctypes.c_int),
         "mcc_solve_step_multicell": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_solve_step_multicell_noalloc": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_ablation_paper_deriv": ([vp, i64, vp, vp, vp, i32, vp], ctypes.c_int),
@@ -146,7 +147,7 @@ def _dptr(t, what, dtype=None, shape=None):
 class Mechanism:
     """A compiled mechanism resident on one GPU (mcc_mech_create)."""
 
-    def __init__(self, mech, device: int = 0, dense_tail: int = -1):
+    def __init__(self, mech, device: int = 0, dense_tail: int = -1, waves_per_simd: int = 0):
         L = library()
         self.source = mech
         arrays = [np.ascontiguousarray(a, dtype=dt) for a, dt in (
@@ -158,6 +159,7 @@ class Mechanism:
         cfg = (ctypes.c_int32 * 8)()
         _check(L.mcc_mech_config_default(ctypes.addressof(cfg)))
         cfg[0] = int(dense_tail)
+        cfg[1] = int(waves_per_simd)
         _check(L.mcc_mech_create_ex(ctypes.addressof(desc), int(device), ctypes.addressof(cfg), ctypes.byref(h)))
         self._h = h
         self.device = int(device)
@@ -237,11 +239,11 @@ class Mechanism:
 
     def schedule_info(self) -> dict:
         """Sizes of the solver schedule (testing aid)."""
-        buf = (ctypes.c_int64 * 8)()
+        buf = (ctypes.c_int64 * 16)()
         _check(library().mcc_debug_schedule_info(self._h, ctypes.addressof(buf)))
         v = list(buf)
         return {"lu_blocks": v[0], "lu_levels": v[1], "nm_blocks": v[2], "fg_blocks": v[3:7],
-                "dense_tail": v[7]}
+                "dense_tail": v[7], "waves_per_simd": v[8]}
 
     def jac_pattern(self):
         rp = np.zeros(self.n_species + 1, dtype=np.int32)
@@ -397,15 +399,18 @@ class Cells:
             raise MccError(f"order must have shape ({self.n_cells},)")
         _check(library().mcc_cells_set_schedule(self._h, o.ctypes.data))
 
-    def balance(self, stats):
-        """Schedule the cells longest first by their step attempts in stats
-        (device counters of a previous outer step; mcc_cells_schedule_from_stats).
+    SCHEDULES = {"longest": 0, "zigzag": 1}
+
+    def balance(self, stats, kind: str = "longest"):
+        """Schedule the cells by their step attempts in stats (device
+        counters of a previous outer step; mcc_cells_schedule_from_stats_ex):
+        "longest" first, or "zigzag" (longest, shortest, second longest, ...).
         Returns the order."""
         import torch
         order = np.empty(self.n_cells, dtype=np.int32)
-        _check(library().mcc_cells_schedule_from_stats(
+        _check(library().mcc_cells_schedule_from_stats_ex(
             self._h, _dptr(stats, "stats", torch.uint8, (self.n_cells, STATS_DTYPE.itemsize)),
-            order.ctypes.data))
+            self.SCHEDULES[kind], order.ctypes.data))
         return order
 
     def set_rate_constants(self, k, stream=None):
@@ -509,15 +514,19 @@ def _check_hip(e):
 
 
 def autotune_solver(mech, cells, dt: float, opts: SolverOpts | None = None, device: int = 0,
-                    candidates=(0, 32, 48, 64), reps: int = 2):
-    """Pick the solver's dense-tail size for `mech` by measurement: every
-    candidate the mechanism admits is compiled, and one outer step of the
-    sample `cells` (a synth.Cells) is timed with HIP events, best of `reps`
-    after one warm-up step whose counters schedule the cells longest first
-    (Cells.balance).  The choice changes how many cells a compute unit holds
-    (LDS per cell), so the sample should fill the device several times over
-    (several thousand cells).  Returns (Mechanism compiled with the fastest
-    choice, {choice: ms})."""
+                    candidates=(0, 32, 48, 64), waves=(0, 1), schedules=("identity", "longest", "zigzag"),
+                    reps: int = 2):
+    """Pick the solver build and the cell schedule for `mech` by measurement.
+    Every admissible combination of dense-tail size (`candidates`) and
+    register budget (`waves`: 0 the library's choice, 1 one wavefront per
+    SIMD) is compiled; for each, one outer step of the sample `cells` (a
+    synth.Cells) runs untimed to produce per-cell counters, then one timed
+    step per schedule (`schedules`: the identity, longest first by those
+    counters, zigzag) with HIP events, best of `reps`.  The choices change
+    how many cells a compute unit holds and in which order the dispatcher
+    starts them, so the sample should fill the device several times over
+    (several thousand cells).  Returns (Mechanism of the fastest build,
+    {"tail/waves/schedule": ms}, the fastest (tail, waves, schedule))."""
     import torch
     dev = torch.device(f"cuda:{device}")
     T = torch.from_numpy(np.ascontiguousarray(cells.T)).to(dev)
@@ -528,33 +537,43 @@ def autotune_solver(mech, cells, dt: float, opts: SolverOpts | None = None, devi
     for m_tail in candidates:
         if m_tail > mech.n_species:
             continue
-        try:
-            h = Mechanism(mech, device=device, dense_tail=m_tail)
-        except MccError:
-            continue  # this choice does not fit the solver's register slots or LDS
-        c = Cells(h, cells.n_cells)
-        c.bind(T, P, s)
-        y = torch.empty_like(y0)
-        ts = []
-        for r in range(reps + 1):
-            y.copy_(y0)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            _, stats = c.step(y, dt, opts)
-            b.record()
+        for w in waves:
+            try:
+                h = Mechanism(mech, device=device, dense_tail=m_tail, waves_per_simd=w)
+            except MccError:
+                continue  # this choice does not fit the solver's register slots or LDS, or has no build
+            w_eff = h.schedule_info()["waves_per_simd"]
+            if any(k[0] == m_tail and k[1] == w_eff for k in times):
+                h.close()
+                continue  # the same build as the library's choice
+            c = Cells(h, cells.n_cells)
+            c.bind(T, P, s)
+            y = y0.clone()
+            _, stats = c.step(y, dt, opts)  # untimed: the counters the schedules are made from
             torch.cuda.synchronize()
-            if r == 0:
-                c.balance(stats)
+            for sched in schedules:
+                if sched == "identity":
+                    c.set_schedule(None)
+                else:
+                    c.balance(stats, sched)
+                ts = []
+                for _ in range(reps):
+                    y.copy_(y0)
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    c.step(y, dt, opts)
+                    b.record()
+                    torch.cuda.synchronize()
+                    ts.append(a.elapsed_time(b))
+                times[(m_tail, w_eff, sched)] = min(ts)
+            c.close()
+            fastest = min((k for k in times if k[0] == m_tail and k[1] == w_eff), key=times.get)
+            if best is None or times[fastest] < times[best[0]]:
+                if best is not None:
+                    best[1].close()
+                best = (fastest, h)
             else:
-                ts.append(a.elapsed_time(b))
-        times[m_tail] = min(ts)
-        c.close()
-        if best is None or times[m_tail] < times[best[0]]:
-            if best is not None:
-                best[1].close()
-            best = (m_tail, h)
-        else:
-            h.close()
+                h.close()
     if best is None:
-        raise MccError("no dense-tail choice compiles for this mechanism")
-    return best[1], times
+        raise MccError("no solver build compiles for this mechanism")
+    return best[1], {f"{k[0]}/{k[1]}/{k[2]}": v for k, v in times.items()}, best[0]

@@ -594,13 +594,20 @@ def test_paper_deriv_kernel(dev, oracle_mod, inverted):
 
 
 def test_autotune_solver(dev, oracle_mod):
-    """The autotuner times the admissible dense-tail sizes and returns the
-    fastest; the tuned mechanism meets the solver's parity bar."""
+    """The autotuner times every admissible dense-tail size, register budget
+    and cell schedule and returns the fastest; the tuned mechanism meets the
+    solver's parity bar."""
     m, c, dt = synth.workload("medium10k", 600)
-    h, times = mcchem.autotune_solver(m, c, dt, reps=1)
-    assert set(times) == {0, 32, 48, 64} and all(t > 0 for t in times.values())
+    h, times, choice = mcchem.autotune_solver(m, c, dt, reps=1)
+    tails = {int(k.split("/")[0]) for k in times}
+    waves = {int(k.split("/")[1]) for k in times}
+    scheds = {k.split("/")[2] for k in times}
+    assert tails == {0, 32, 48, 64} and waves == {1, 2} and scheds == {"identity", "longest", "zigzag"}
+    assert all(t > 0 for t in times.values())
     best = min(times, key=times.get)
-    assert h.schedule_info()["dense_tail"] == best
+    assert f"{choice[0]}/{choice[1]}/{choice[2]}" == best
+    info = h.schedule_info()
+    assert (info["dense_tail"], info["waves_per_simd"]) == (choice[0], choice[1])
     sub = synth.Cells(T=c.T[:40], P=c.P[:40], jscale=c.jscale[:40], y0=c.y0[:, :40])
     b = Batch.__new__(Batch)
     b.m, b.c, b.C, b.ld, b.dev, b.h = m, sub, 40, 40, dev, h
@@ -1062,6 +1069,32 @@ def test_cell_schedule_leaves_results_unchanged(dev, K):
                 assert torch.equal(x, y)
     b.cells.set_schedule(None)
     assert torch.equal(run()[0], ref[0])
+
+
+def test_register_budget_and_zigzag_leave_results_unchanged(dev):
+    """The solver built for one wavefront per SIMD, and the zigzag cell
+    schedule, give every cell the bits of the default build and order."""
+    m, c, dt = synth.workload("medium10k", 300)
+    ref = Batch(dev, m, c, dense_tail=32)
+    y_ref = ref.y_dev()
+    _, st_ref = ref.cells.step(y_ref, dt)
+    one = Batch.__new__(Batch)
+    one.m, one.c, one.C, one.ld, one.dev = m, c, 300, 300, dev
+    one.h = mcchem.Mechanism(m, dense_tail=32, waves_per_simd=1)
+    assert one.h.schedule_info()["waves_per_simd"] == 1 and ref.h.schedule_info()["waves_per_simd"] == 2
+    one.cells = mcchem.Cells(one.h, 300)
+    one.cells.bind(ref.T, ref.P, ref.s)
+    order = one.cells.balance(st_ref, "zigzag")
+    att = mcchem.stats_numpy(st_ref)
+    a = (att["steps"] + att["rejects"] + att["newton_fails"]).astype(np.int64)
+    lf = np.argsort(-a, kind="stable")
+    assert order[0] == lf[0] and order[1] == lf[-1] and order[2] == lf[1] and sorted(order) == list(range(300))
+    y = one.y_dev()
+    _, st = one.cells.step(y, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_ref) and torch.equal(st, st_ref)
+    with pytest.raises(mcchem.MccError, match="wavefronts"):
+        mcchem.Mechanism(synth.mech_large(), waves_per_simd=2)
 
 
 def test_cell_schedule_rejects_non_permutations(dev):
