@@ -18,7 +18,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# MCC_ORACLE_LIB: another build of the same source (e.g. one with sanitizers)
+LIB_PATH = os.environ.get("MCC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 STATUS = {0: "OK", 1: "TOO_MUCH_WORK", 2: "CONV_FAIL", 3: "ERR_FAIL", 4: "NONFINITE", 5: "SINGULAR"}

@@ -1,0 +1,98 @@
+"""Property tests (hypothesis): random tiny mechanisms -- reactions of arity
+1 to 3 with repeated reactants (multiplicities), rational yields, species
+that appear on both sides -- compiled by the library on the host, and the
+host emulation of its f/J tables and solver tables compared with the oracle:
+f and J to 1e-12 of the scale, the Newton-matrix solve to round-off, and a
+relabelling of the species permutes every result."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle as oracle_pkg
+from paper_2501_00011_amd import mcchem, synth
+
+
+@st.composite
+def tiny_mechanisms(draw):
+    n = draw(st.integers(2, 8))
+    n_rx = draw(st.integers(1, 10))
+    rx = []
+    for _ in range(n_rx):
+        reac = draw(st.lists(st.integers(0, n - 1), min_size=1, max_size=3))
+        n_prod = draw(st.integers(0, 3))
+        prods = []
+        for _ in range(n_prod):
+            s = draw(st.integers(0, n - 1))
+            y = Fraction(draw(st.integers(1, 9)), draw(st.integers(1, 4)))
+            prods.append((s, float(y)))
+        log_k = draw(st.floats(-3.0, 1.0))
+        rx.append((reac, prods, 10.0 ** log_k, 0.0, 0))
+    seed = draw(st.integers(0, 2 ** 31 - 1))
+    return n, rx, seed
+
+
+def _state(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.1, 3.0, size=n), rng.normal(size=n), float(10.0 ** rng.uniform(-2, 1))
+
+
+def _check(n, rx, seed):
+    m = synth.mechanism_from_lists(n, rx)
+    h = mcchem.Mechanism(m, device=-1)
+    o = oracle_pkg.Oracle(m)
+    k = np.array([r[2] for r in rx])
+    y, b, c = _state(n, seed)
+    f_ref, fs = o.deriv(k[:, None], y[:, None])
+    J_ref, Js = o.jac(k[:, None], y[:, None])
+    f_ref, fs, J_ref, Js = f_ref[:, 0], fs[:, 0], J_ref[0], Js[0]
+    # the streaming f/J tables
+    f, J, viol = h.emulate_fj(k, y)
+    assert viol == 0
+    assert np.all(np.abs(f - f_ref) <= 1e-12 * fs)
+    rp, ci = h.jac_pattern()
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    assert np.all(np.abs(J - J_ref[rows, ci]) <= 1e-12 * Js[rows, ci])
+    mask = np.ones((n, n), dtype=bool)
+    mask[rows, ci] = False
+    assert np.all(J_ref[mask] == 0.0)
+    # the solver tables: f, and x = (I - c J)^-1 b
+    fs2, x, viol = h.emulate_cell(k, y, c, b)
+    assert viol == 0
+    assert np.all(np.abs(fs2 - f_ref) <= 1e-12 * fs)
+    Mm = np.eye(n) - c * J_ref
+    assert np.all(np.abs(Mm @ x - b) <= 1e-11 * (np.abs(Mm) @ np.abs(x) + np.abs(b)))
+    return f, J_ref, x
+
+
+@settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_mechanisms())
+def test_random_mechanisms_tables_match_oracle(mech):
+    n, rx, seed = mech
+    _check(n, rx, seed)
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_mechanisms(), st.randoms(use_true_random=False))
+def test_relabelled_species_permute_the_results(mech, rnd):
+    """Renaming the species (a permutation p: old index i becomes p[i])
+    gives f and the solve's x permuted the same way (the compiler's
+    elimination order changes with the names; the mathematics does not)."""
+    n, rx, seed = mech
+    perm = list(range(n))
+    rnd.shuffle(perm)
+    f, J, x = _check(n, rx, seed)
+    rx2 = [([perm[s] for s in reac], [(perm[s], yl) for s, yl in prods], A, th, t) for reac, prods, A, th, t in rx]
+    m2 = synth.mechanism_from_lists(n, rx2)
+    h2 = mcchem.Mechanism(m2, device=-1)
+    k = np.array([r[2] for r in rx])
+    y, b, c = _state(n, seed)
+    y2, b2 = np.empty(n), np.empty(n)
+    y2[perm], b2[perm] = y, b
+    f2, x2, viol = h2.emulate_cell(k, y2, c, b2)
+    assert viol == 0
+    scale = np.abs(f).max() + 1e-300
+    assert np.all(np.abs(f2[perm] - f) <= 1e-12 * scale)
+    assert np.allclose(x2[perm], x, rtol=1e-10, atol=1e-12 * (np.abs(x).max() + 1.0))
