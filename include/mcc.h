@@ -239,6 +239,15 @@ mcc_status mcc_debug_emulate_cell_adjoint(const mcc_mech *mech, const double *k,
 mcc_status mcc_debug_emulate_fj(const mcc_mech *mech, const double *k, const double *y, double *f, double *jac,
                                 int32_t *violations);
 
+/* Testing aid (host only): the generated VJP kernel's work items for one
+ * cell, run on the host in the kernel's order: gy = J^T v [n_species] and
+ * glnk = d(v.f)/d ln k [n_reactions] at y with rate constants k (host
+ * arrays); *violations counts plan errors (0 for a sound plan: every
+ * species column formed once, every reaction's d/d ln k written once, every
+ * reaction in the item of each of its reactants). */
+mcc_status mcc_debug_emulate_vjp(const mcc_mech *mech, const double *k, const double *y, const double *v,
+                                 double *gy, double *glnk, int32_t *violations);
+
 /* Which f/J kernel mcc_calc_deriv / mcc_calc_jac / mcc_calc_deriv_jac of
  * this mechanism launch.  MCC_FJ_GENERATED (the default): straight-line HIP
  * written for this mechanism from its f/J tables and compiled with hipRTC

@@ -46,19 +46,28 @@ std::string fill(std::string s, bool pair)
     return s;
 }
 
-// Kernel head: block -> (64-lane tile, work item), the tiles of one XCD
-// together.  One-cell variant: lane = cell c_begin + tile * 64 + lane.  Pair
-// variant: lane = cells 2c and 2c + 1 with c = tile * 64 + lane, 16-byte
-// accesses (the caller guarantees an even ld, 16-byte aligned arrays and
-// whole pairs: n_cells even).
+// Kernel head: block -> (64-lane tile, work item).  Blocks come in groups
+// of 8 * grp_tiles tiles times n_items; within a group the order is item
+// major: block q of XCD xcd (bid = 8 q + xcd) runs item r / grp_tiles on tile
+// (group * grp_tiles + r % grp_tiles) * 8 + xcd, r = q mod (n_items *
+// grp_tiles).  grp_tiles = 1 runs all items of a tile on one XCD, one tile
+// after the other (the inputs of a tile are fetched once and then served by
+// that XCD's L2); a larger grp_tiles runs each item over 8 * grp_tiles
+// consecutive tiles at about the same time, so that the first reads of every
+// row are long runs of consecutive cells.  One-cell variant: lane = cell
+// c_begin + tile * 64 + lane.  Pair variant: lane = cells 2c and 2c + 1 with
+// c = tile * 64 + lane, 16-byte accesses (the caller guarantees an even ld,
+// 16-byte aligned arrays and whole pairs: n_cells even).
 std::string head(const char *name, const char *args, const char *ptrs, bool pair)
 {
     std::ostringstream o;
     o << "extern \"C\" __global__ __launch_bounds__(64) void " << name << (pair ? "2" : "") << "(\n" << args
-      << ", long long n_cells, long long ld, long long c_begin, int item_begin, int n_items, int n_tiles)\n"
+      << ", long long n_cells, long long ld, long long c_begin, int item_begin, int n_items, int n_tiles,\n"
+      << "    int grp_tiles)\n"
       << "{\n"
       << "    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;\n"
-      << "    const int item = item_begin + q % n_items, tile = (q / n_items) * 8 + xcd;\n"
+      << "    const int grp = q / (n_items * grp_tiles), r = q - grp * (n_items * grp_tiles);\n"
+      << "    const int item = item_begin + r / grp_tiles, tile = (grp * grp_tiles + r % grp_tiles) * 8 + xcd;\n"
       << "    if (tile >= n_tiles) return;\n";
     if (pair)
         o << "    const long long c = (long long)tile * 64 + threadIdx.x;  // pair index\n"
@@ -81,7 +90,11 @@ std::string generate_preamble()
            "__device__ __forceinline__ d2 operator+(d2 a, d2 b) { return d2{a.x + b.x, a.y + b.y}; }\n"
            "__device__ __forceinline__ d2 operator*(d2 a, d2 b) { return d2{a.x * b.x, a.y * b.y}; }\n"
            "__device__ __forceinline__ d2 operator*(double s, d2 b) { return d2{s * b.x, s * b.y}; }\n"
-           "__device__ __forceinline__ d2 &operator+=(d2 &a, d2 b) { a.x += b.x; a.y += b.y; return a; }\n";
+           "__device__ __forceinline__ d2 &operator+=(d2 &a, d2 b) { a.x += b.x; a.y += b.y; return a; }\n"
+           "// outputs are stored non-temporally: no kernel reads them back soon\n"
+           "__device__ __forceinline__ void st_out(double *p, double x) { __builtin_nontemporal_store(x, p); }\n"
+           "typedef double d2v __attribute__((ext_vector_type(2)));\n"
+           "__device__ __forceinline__ void st_out(d2 *p, d2 x) { __builtin_nontemporal_store(d2v{x.x, x.y}, (d2v *)p); }\n";
 }
 
 std::string generate_fj_source(const HostTables &t, bool pair)
@@ -147,7 +160,10 @@ std::string generate_fj_source(const HostTables &t, bool pair)
                 if (flags & kFjStore) {
                     const std::string dst = row < (uint32_t)N ? "F[" + std::to_string(row) + " * @L@]"
                                                               : "G[" + std::to_string(row - N) + " * @L@]";
-                    o << "            " << dst << ((flags & kFjAdd) ? " += acc;\n" : " = acc;\n");
+                    if (flags & kFjAdd)
+                        o << "            " << dst << " += acc;\n";  // a later part of a split sum
+                    else
+                        o << "            st_out(&" << dst << ", acc);\n";
                 }
             }
             o << "            (void)acc;\n        }\n";
@@ -162,26 +178,19 @@ std::string generate_fj_source(const HostTables &t, bool pair)
 
 namespace mcc {
 
-// Vector-Jacobian products, generated from the same tables.  Work items
-// 0 .. n_jitems-1 are the Jacobian-column items of the f/J kernel: each J
-// entry (i, s) they form is contracted at once with v_i into a register
-// accumulator gy_s (gy = J^T v), stored when the item ends (a column never
-// spans two items).  Items n_jitems .. are groups of kVjpRxnGroup reactions:
-// glnk_j = r_j * sum_i nu_ij v_i, the derivative of v.f with respect to
-// ln k_j (f is linear in each k_j).
+// Vector-Jacobian products (reverse mode of f), one switch case per work
+// item of the plan (plan_vjp): per load round, the round's k, y and v rows
+// are loaded together; then per reaction w_j = sum_i nu_ij v_i, the item's
+// columns among j's reactants gain w_j * d r_j / d y_s, and the item that
+// owns j writes d(v.f)/d ln k_j = r_j * w_j.  gy_s is written when the item
+// ends.  A null gy or glnk skips its stores (the same arithmetic runs).
 std::string generate_vjp_source(const HostTables &t, bool pair)
 {
-    const int N = t.N, R = t.R;
-    std::vector<int> entry_row(t.nnz), entry_col(t.nnz);
-    for (int i = 0; i < N; ++i)
-        for (int e = t.row_ptr[i]; e < t.row_ptr[i + 1]; ++e) {
-            entry_row[e] = i;
-            entry_col[e] = t.col_idx[e];
-        }
     std::ostringstream o;
     o << head("mcc_vjp_generated",
               "    const double *__restrict__ y, const double *__restrict__ k, const double *__restrict__ v,\n"
               "    double *__restrict__ gy, double *__restrict__ glnk",
+              "    const bool want_gy = gy != nullptr, want_glnk = glnk != nullptr;\n"
               "    const @V@ *__restrict__ Y = (const @V@ *)y + c;\n"
               "    const @V@ *__restrict__ K = (const @V@ *)k + c;\n"
               "    const @V@ *__restrict__ V = (const @V@ *)v + c;\n"
@@ -189,89 +198,65 @@ std::string generate_vjp_source(const HostTables &t, bool pair)
               "    @V@ *__restrict__ GK = (@V@ *)glnk + c;\n",
               pair)
       << "    switch (item) {\n";
-
-    int case_no = 0;
-    for (int it = t.n_fitems; it < t.n_fitems + t.n_jitems; ++it, ++case_no) {
-        o << "    case " << case_no << ": {\n";
-        std::set<int> ys, ks, vs, cols;
-        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
-            const FjChunk &ch = t.fj_chunks[ci];
-            for (int qm = 0; qm < ch.n_mono; ++qm) {
-                const FjMono &m = t.fj_monos[ch.mono_begin + qm];
-                if (m.j >= 0) ks.insert(m.j);
-                for (int f3 : {m.a, m.b, m.c})
-                    if (f3 >= 0) ys.insert(f3);
-            }
-            for (int r = 0; r < ch.n_rec; ++r) {
-                const FjRec &rec = t.fj_recs[ch.rec_begin + r];
-                const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
-                if ((flags & kFjStore) && row >= (uint32_t)N) {
-                    vs.insert(entry_row[row - N]);
-                    cols.insert(entry_col[row - N]);
-                }
-            }
-        }
-        for (int j : ks) o << "        const @V@ k" << j << " = K[" << j << " * @L@];\n";
-        for (int r : ys) o << "        const @V@ y" << r << " = Y[" << r << " * @L@];\n";
-        for (int r : vs) o << "        const @V@ v" << r << " = V[" << r << " * @L@];\n";
-        for (int sc : cols) o << "        @V@ g" << sc << " = @Z@;\n";
-        for (int ci = t.fj_items[it]; ci < t.fj_items[it + 1]; ++ci) {
-            const FjChunk &ch = t.fj_chunks[ci];
+    for (size_t it = 0; it < t.vjp_items.size(); ++it) {
+        const VjpItem &item = t.vjp_items[it];
+        std::set<int> cols(item.cols.begin(), item.cols.end()), owned(item.glnk.begin(), item.glnk.end());
+        o << "    case " << it << ": {\n";
+        for (int s : item.cols) o << "        @V@ g" << s << " = @Z@;\n";
+        for (const std::vector<int32_t> &round : item.rounds) {
             o << "        {\n";
-            std::vector<std::string> mono(kFjQmax);
-            for (int qm = 0; qm < ch.n_mono; ++qm) {
-                const FjMono &m = t.fj_monos[ch.mono_begin + qm];
-                if (m.j < 0 && m.a < 0 && m.b < 0 && m.c < 0) continue;
-                std::string e;
-                if (m.j >= 0) e = "k" + std::to_string(m.j);
-                for (int f3 : {m.a, m.b, m.c})
-                    if (f3 >= 0) e += (e.empty() ? "" : " * ") + ("y" + std::to_string(f3));
-                mono[qm] = "m" + std::to_string(qm);
-                o << "            const @V@ " << mono[qm] << " = " << e << ";\n";
+            std::set<int> ks, ys, vs;
+            for (int j : round) {
+                ks.insert(j);
+                for (int q = 0; q < 3; ++q)
+                    if (t.rx_sp[3 * j + q] >= 0) ys.insert(t.rx_sp[3 * j + q]);
+                for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) vs.insert(t.nu_sp[e]);
             }
-            o << "            @V@ acc = @Z@;\n";
-            for (int r = 0; r < ch.n_rec; ++r) {
-                const FjRec &rec = t.fj_recs[ch.rec_begin + r];
-                const uint32_t flags = rec.meta >> 24, row = rec.meta & kFjRowMask;
-                std::string sum;
-                for (int qq = 0; qq < 3; ++qq) {
-                    const int slot = (rec.slots >> (8 * qq)) & 0xff;
-                    if (slot >= kFjQmax || rec.coef[qq] == 0.0 || mono[slot].empty()) continue;
-                    sum += (sum.empty() ? "" : " + ") + lit(rec.coef[qq]) + " * " + mono[slot];
+            for (int j : ks) o << "            const @V@ k" << j << " = K[" << j << " * @L@];\n";
+            for (int r : ys) o << "            const @V@ y" << r << " = Y[" << r << " * @L@];\n";
+            for (int r : vs) o << "            const @V@ v" << r << " = V[" << r << " * @L@];\n";
+            for (int j : round) {
+                std::string w;
+                for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e)
+                    w += (w.empty() ? "" : " + ") + lit(t.nu_coef[e]) + " * v" + std::to_string(t.nu_sp[e]);
+                o << "            const @V@ w" << j << " = " << (w.empty() ? "@Z@" : w) << ";\n";
+                const int32_t *a = &t.rx_sp[3 * j];
+                for (int q = 0; q < 3; ++q) {
+                    const int s = a[q];
+                    if (s < 0 || !cols.count(s)) continue;
+                    bool first = true;  // each distinct reactant once
+                    for (int p = 0; p < q; ++p) first = first && a[p] != s;
+                    if (!first) continue;
+                    int mult = 0;
+                    bool skipped = false;
+                    std::string d = "k" + std::to_string(j);
+                    for (int p = 0; p < 3; ++p) {
+                        if (a[p] < 0) continue;
+                        if (a[p] == s) {
+                            mult++;
+                            if (!skipped) {
+                                skipped = true;
+                                continue;
+                            }
+                        }
+                        d += " * y" + std::to_string(a[p]);
+                    }
+                    o << "            g" << s << " += w" << j << " * ("
+                      << (mult > 1 ? lit((double)mult) + " * (" + d + ")" : d) << ");\n";
                 }
-                if (sum.empty()) sum = "@Z@";
-                if (!(flags & (kFjKeep | kFjStore)) && sum == "@Z@") continue;
-                o << "            acc " << ((flags & kFjKeep) ? "+=" : "=") << " " << sum << ";\n";
-                if ((flags & kFjStore) && row >= (uint32_t)N) {
-                    const int e = (int)row - N;
-                    o << "            g" << entry_col[e] << " += v" << entry_row[e] << " * acc;\n";
+                if (owned.count(j)) {
+                    std::string r = "k" + std::to_string(j);
+                    for (int p = 0; p < 3; ++p)
+                        if (a[p] >= 0) r += " * y" + std::to_string(a[p]);
+                    o << "            if (want_glnk) st_out(&GK[" << j << " * @L@], (" << r << ") * w" << j << ");\n";
                 }
             }
-            o << "            (void)acc;\n        }\n";
+            o << "        }\n";
         }
-        for (int sc : cols) o << "        GY[" << sc << " * @L@] = g" << sc << ";\n";
-        o << "    } break;\n";
-    }
-    for (int j0 = 0; j0 < R; j0 += kVjpRxnGroup, ++case_no) {
-        const int j1 = std::min(R, j0 + kVjpRxnGroup);
-        o << "    case " << case_no << ": {\n";
-        std::set<int> ys, vs;
-        for (int j = j0; j < j1; ++j) {
-            for (int q = 0; q < 3; ++q)
-                if (t.rx_sp[3 * j + q] >= 0) ys.insert(t.rx_sp[3 * j + q]);
-            for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) vs.insert(t.nu_sp[e]);
-        }
-        for (int r : ys) o << "        const @V@ y" << r << " = Y[" << r << " * @L@];\n";
-        for (int r : vs) o << "        const @V@ v" << r << " = V[" << r << " * @L@];\n";
-        for (int j = j0; j < j1; ++j) {
-            std::string rate = "K[" + std::to_string(j) + " * @L@]";
-            for (int q = 0; q < 3; ++q)
-                if (t.rx_sp[3 * j + q] >= 0) rate += " * y" + std::to_string(t.rx_sp[3 * j + q]);
-            std::string w;
-            for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e)
-                w += (w.empty() ? "" : " + ") + lit(t.nu_coef[e]) + " * v" + std::to_string(t.nu_sp[e]);
-            if (w.empty()) w = "@Z@";
-            o << "        GK[" << j << " * @L@] = (" << rate << ") * (" << w << ");\n";
+        if (!item.cols.empty()) {
+            o << "        if (want_gy) {\n";
+            for (int s : item.cols) o << "            st_out(&GY[" << s << " * @L@], g" << s << ");\n";
+            o << "        }\n";
         }
         o << "    } break;\n";
     }

@@ -71,6 +71,21 @@ struct alignas(16) Op16 {
     uint32_t pad;
 };
 
+// A work item of the generated VJP kernel (reverse mode of f).  With
+// w_j = sum_i nu_ij v_i, gy = J^T v is gy_s = sum_j w_j d r_j / d y_s over
+// the reactions with s among their reactants, and d(v.f)/d ln k_j = r_j w_j.
+// An item forms gy_s for its species columns `cols` from the reactions in
+// `rounds` (every reaction with a reactant in cols; each round's k, y and v
+// rows are loaded together, at most kVjpRoundLoads of them unless a single
+// reaction needs more) and writes d/d ln k_j for the reactions in `glnk`
+// (each reaction in exactly one item: the item of its first reactant).
+struct VjpItem {
+    std::vector<int32_t> cols;
+    std::vector<std::vector<int32_t>> rounds;
+    std::vector<int32_t> glnk;
+};
+constexpr int kVjpRoundLoads = 64;  // measured: 48-96 beat 16-32 at 200k cells, equal at 10k
+
 // ---------------------------------------------------------------------------
 // Host-side compiled mechanism (built once by compile_mechanism).
 // ---------------------------------------------------------------------------
@@ -99,6 +114,7 @@ struct HostTables {
     std::vector<int32_t> nu_ptr, nu_sp;
     std::vector<double> nu_coef;
     std::vector<int32_t> nu_vid;      // nu_sp as indices of the solver's compact LDS state vector
+    std::vector<VjpItem> vjp_items;   // work items of the generated VJP kernel (plan_vjp)
     // the paper's Derivative kernel data (ablation): records and inverted
     std::vector<int32_t> paper_rec, paper_rec_inv;
     std::vector<double> paper_yld, paper_yld_inv;
@@ -166,6 +182,16 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
                  const double *b_species, double *f_species, double *x_species);
 // Host emulation of the streaming f/J tables for one cell (testing aid).
 int emulate_fj(const HostTables &t, const double *k, const double *y_species, double *f, double *jac);
+// Host emulation of the generated VJP kernel's work items for one cell
+// (same plan, same arithmetic in the same order).  Returns the number of
+// plan violations: a column formed twice or never, a reaction whose
+// d/d ln k is written twice or never, a reaction missing from the item of
+// one of its reactants, a round over the load budget with more than one
+// reaction, an index out of range.
+int emulate_vjp(const HostTables &t, const double *k, const double *y_species, const double *v, double *gy,
+                double *glnk);
+// Groups the species columns into VJP work items (see VjpItem).
+std::vector<VjpItem> plan_vjp(const HostTables &t, int round_loads);
 
 // ---------------------------------------------------------------------------
 // Device parameter blocks (passed by value as kernel arguments).
@@ -281,7 +307,6 @@ constexpr int kPaperProd = 4;
 constexpr int kPaperRec = 5 + kPaperProd;
 hipError_t launch_paper_deriv(const int32_t *rec, const double *yld, bool inverted, const double *y,
                               const double *k, double *f, int N, int R, int64_t n_cells, hipStream_t s);  // appended to the f/J source: one module
-constexpr int kVjpRxnGroup = 16;  // reactions per d/d ln k work item
 bool compile_fj_source(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log);
 // waves: wavefronts per SIMD of the build to launch (solve_waves_available).
 hipError_t launch_solve(const SolveParams &p, int NS, int M, int waves, hipStream_t s);

@@ -224,6 +224,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
             }
         t->nu_ptr.push_back((int32_t)t->nu_sp.size());
     }
+    t->vjp_items = plan_vjp(*t, kVjpRoundLoads);
 
     // ---- the paper's Derivative kernel data (ablation only) ---------------
     t->paper_ok = true;
@@ -743,6 +744,114 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
     }
 
     return MCC_OK;
+}
+
+// VJP work items.  Rows are numbered k_j -> j, y_s -> R + s, v_s -> R + N + s.
+// Columns are taken largest first (most rows to load); each item then grows
+// by the column that shares reactions with it and adds the fewest new rows,
+// while its rows stay within the budget (a column over the budget on its own
+// is an item of its own, loaded in several rounds).  Columns of species that
+// are no reactant (gy_s = 0) are dealt out over the items at the end.
+std::vector<VjpItem> plan_vjp(const HostTables &t, int round_loads)
+{
+    const int N = t.N, R = t.R, n_rows = R + 2 * N;
+    std::vector<std::vector<int32_t>> rx_rows(R), col_rx(N);
+    for (int j = 0; j < R; ++j) {
+        std::vector<int32_t> &r = rx_rows[j];
+        r.push_back(j);
+        for (int q = 0; q < 3; ++q) {
+            const int s = t.rx_sp[3 * j + q];
+            if (s < 0) continue;
+            r.push_back(R + s);
+            if (col_rx[s].empty() || col_rx[s].back() != j) col_rx[s].push_back(j);
+        }
+        for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) r.push_back(R + N + t.nu_sp[e]);
+        std::sort(r.begin(), r.end());
+        r.erase(std::unique(r.begin(), r.end()), r.end());
+    }
+    std::vector<std::vector<int32_t>> col_rows(N);
+    for (int s = 0; s < N; ++s) {
+        for (int j : col_rx[s]) col_rows[s].insert(col_rows[s].end(), rx_rows[j].begin(), rx_rows[j].end());
+        std::sort(col_rows[s].begin(), col_rows[s].end());
+        col_rows[s].erase(std::unique(col_rows[s].begin(), col_rows[s].end()), col_rows[s].end());
+    }
+    std::vector<int> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return col_rows[a].size() > col_rows[b].size(); });
+    std::vector<char> done(N, 0), in_item(n_rows, 0);
+    std::vector<VjpItem> items;
+    std::vector<int> zero_cols;
+    for (int s0 : order) {
+        if (done[s0]) continue;
+        if (col_rx[s0].empty()) {
+            zero_cols.push_back(s0);
+            done[s0] = 1;
+            continue;
+        }
+        VjpItem it;
+        std::vector<int32_t> rows = col_rows[s0];
+        for (int r : rows) in_item[r] = 1;
+        it.cols.push_back(s0);
+        done[s0] = 1;
+        while (true) {
+            int best = -1, best_n = 0;
+            for (int c0 : it.cols)
+                for (int j : col_rx[c0])
+                    for (int q = 0; q < 3; ++q) {
+                        const int s = t.rx_sp[3 * j + q];
+                        if (s < 0 || done[s]) continue;
+                        int n = 0;
+                        for (int r : col_rows[s]) n += !in_item[r];
+                        if ((int)rows.size() + n > round_loads) continue;
+                        if (best < 0 || n < best_n || (n == best_n && s < best)) best = s, best_n = n;
+                    }
+            if (best < 0) break;
+            for (int r : col_rows[best])
+                if (!in_item[r]) in_item[r] = 1, rows.push_back(r);
+            it.cols.push_back(best);
+            done[best] = 1;
+        }
+        for (int r : rows) in_item[r] = 0;
+        items.push_back(it);
+    }
+    if (items.empty()) items.push_back(VjpItem{});  // no reaction has a reactant
+    for (size_t q = 0; q < zero_cols.size(); ++q) items[q % items.size()].cols.push_back(zero_cols[q]);
+    // reactions of each item, d/d ln k ownership, then the load rounds
+    std::vector<int> owner(R, -1), col_item(N, -1);
+    for (size_t i = 0; i < items.size(); ++i)
+        for (int s : items[i].cols) col_item[s] = (int)i;
+    std::vector<std::vector<int32_t>> item_rx(items.size());
+    for (int j = 0; j < R; ++j) {
+        const int s = t.rx_sp[3 * j];
+        owner[j] = s >= 0 ? col_item[s] : (int)items.size() - 1;  // no reactant: the last item
+        if (s < 0) item_rx[owner[j]].push_back(j);
+    }
+    for (size_t i = 0; i < items.size(); ++i) {
+        for (int s : items[i].cols) item_rx[i].insert(item_rx[i].end(), col_rx[s].begin(), col_rx[s].end());
+        std::vector<int32_t> &rx = item_rx[i];
+        std::sort(rx.begin(), rx.end());
+        rx.erase(std::unique(rx.begin(), rx.end()), rx.end());
+        std::vector<int32_t> cur;
+        std::vector<int32_t> round_rows;
+        for (int j : rx) {
+            int n = 0;
+            for (int r : rx_rows[j]) n += !in_item[r];
+            if (!cur.empty() && (int)round_rows.size() + n > round_loads) {
+                items[i].rounds.push_back(cur);
+                for (int r : round_rows) in_item[r] = 0;
+                cur.clear();
+                round_rows.clear();
+            }
+            cur.push_back(j);
+            for (int r : rx_rows[j])
+                if (!in_item[r]) in_item[r] = 1, round_rows.push_back(r);
+            if (owner[j] == (int)i) items[i].glnk.push_back(j);
+        }
+        if (!cur.empty()) items[i].rounds.push_back(cur);
+        for (int r : round_rows) in_item[r] = 0;
+    }
+    return items;
 }
 
 }  // namespace mcc

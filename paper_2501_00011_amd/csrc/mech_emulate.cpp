@@ -5,6 +5,7 @@
 // the end of each LU level) and checks on the way that every offset is in
 // range and that no op reads or writes what another op of the same LU level
 // writes.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <set>
@@ -283,6 +284,94 @@ int emulate_fj(const HostTables &t, const double *k, const double *y_species, do
         if (!written[r]) bad++;
     for (int r = 0; r < N; ++r) f[r] = out[r];
     for (int e = 0; e < t.nnz; ++e) jac[e] = out[N + e];
+    return bad;
+}
+
+// The generated VJP kernel's arithmetic for one cell, item by item and round
+// by round as in the generated source (plan_vjp): w_j = sum_i nu_ij v_i in
+// the stored order, then gy_s += w_j * (multiplicity * k_j * the other
+// reactants) for the item's columns among j's reactants, and
+// glnk_j = (k_j * reactants) * w_j in the item that owns j.
+int emulate_vjp(const HostTables &t, const double *k, const double *y_species, const double *v, double *gy,
+                double *glnk)
+{
+    const int N = t.N, R = t.R;
+    int bad = 0;
+    std::vector<int> col_seen(N, 0), rx_seen(R, 0);
+    for (const VjpItem &it : t.vjp_items) {
+        std::vector<double> g(it.cols.size(), 0.0);
+        std::vector<int> col_slot(N, -1);
+        for (size_t q = 0; q < it.cols.size(); ++q) {
+            const int s = it.cols[q];
+            if (s < 0 || s >= N) { bad++; continue; }
+            col_seen[s]++;
+            col_slot[s] = (int)q;
+        }
+        std::vector<char> in_item(R, 0), owned(R, 0);
+        for (int j : it.glnk) {
+            if (j < 0 || j >= R) { bad++; continue; }
+            owned[j] = 1;
+            rx_seen[j]++;
+        }
+        for (const std::vector<int32_t> &round : it.rounds) {
+            std::vector<int> rows;
+            for (int j : round) {
+                if (j < 0 || j >= R) { bad++; continue; }
+                rows.push_back(j);
+                for (int q = 0; q < 3; ++q)
+                    if (t.rx_sp[3 * j + q] >= 0) rows.push_back(R + t.rx_sp[3 * j + q]);
+                for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) rows.push_back(R + N + t.nu_sp[e]);
+            }
+            std::sort(rows.begin(), rows.end());
+            const int n_rows = (int)(std::unique(rows.begin(), rows.end()) - rows.begin());
+            if (n_rows > kVjpRoundLoads && round.size() > 1) bad++;
+            for (int j : round) {
+                if (j < 0 || j >= R) continue;
+                in_item[j] = 1;
+                double w = 0.0;
+                for (int e = t.nu_ptr[j]; e < t.nu_ptr[j + 1]; ++e) w += t.nu_coef[e] * v[t.nu_sp[e]];
+                const int *a = &t.rx_sp[3 * j];
+                for (int q = 0; q < 3; ++q) {
+                    const int s = a[q];
+                    if (s < 0 || col_slot[s] < 0) continue;
+                    bool first = true;  // each distinct reactant once
+                    for (int p = 0; p < q; ++p) first = first && a[p] != s;
+                    if (!first) continue;
+                    int mult = 0;
+                    double d = k[j];
+                    bool skipped = false;
+                    for (int p = 0; p < 3; ++p) {
+                        if (a[p] < 0) continue;
+                        if (a[p] == s) {
+                            mult++;
+                            if (!skipped) { skipped = true; continue; }
+                        }
+                        d *= y_species[a[p]];
+                    }
+                    g[col_slot[s]] += w * (mult > 1 ? mult * d : d);
+                }
+                if (owned[j]) {
+                    double r = k[j];
+                    for (int p = 0; p < 3; ++p)
+                        if (a[p] >= 0) r *= y_species[a[p]];
+                    glnk[j] = r * w;
+                }
+            }
+        }
+        // every reaction with a reactant among the columns is in the item; owned ones too
+        for (int s : it.cols)
+            for (int j = 0; j < R && s >= 0 && s < N; ++j)
+                for (int q = 0; q < 3; ++q)
+                    if (t.rx_sp[3 * j + q] == s && !in_item[j]) bad++;
+        for (int j : it.glnk)
+            if (j >= 0 && j < R && !in_item[j]) bad++;
+        for (size_t q = 0; q < it.cols.size(); ++q)
+            if (it.cols[q] >= 0 && it.cols[q] < N) gy[it.cols[q]] = g[q];
+    }
+    for (int s = 0; s < N; ++s)
+        if (col_seen[s] != 1) bad++;
+    for (int j = 0; j < R; ++j)
+        if (rx_seen[j] != 1) bad++;
     return bad;
 }
 

@@ -75,6 +75,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mcc_debug_emulate_cell": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_debug_schedule_info": ([vp, vp], ctypes.c_int),
         "mcc_debug_emulate_fj": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mcc_debug_emulate_vjp": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mcc_debug_emulate_cell_adjoint": ([vp, vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "mcc_mech_set_fj_kernel": ([vp, ctypes.c_int32], ctypes.c_int),
         "mcc_calc_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -203,6 +204,20 @@ class Mechanism:
         _check(library().mcc_debug_emulate_fj(self._h, k.ctypes.data, y.ctypes.data, f.ctypes.data,
                                               J.ctypes.data, ctypes.byref(v)))
         return f, J[:self.nnz], v.value
+
+    def emulate_vjp(self, k, y, v):
+        """Host emulation of the generated VJP kernel's work items for one
+        cell (testing aid): returns (gy = J^T v, glnk = d(v.f)/d ln k,
+        violations)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        gy = np.zeros(self.n_species)
+        glnk = np.zeros(max(self.n_reactions, 1))
+        n = ctypes.c_int32()
+        _check(library().mcc_debug_emulate_vjp(self._h, k.ctypes.data, y.ctypes.data, v.ctypes.data, gy.ctypes.data,
+                                               glnk.ctypes.data, ctypes.byref(n)))
+        return gy, glnk[:self.n_reactions], n.value
 
     FJ_GENERATED, FJ_TABLES = 0, 1
 

@@ -1,10 +1,11 @@
 // Host-side checks of the mechanism compiler, run under AddressSanitizer
 // and UndefinedBehaviorSanitizer by tests/test_sanitizers.py: for every
 // dense-tail size a mechanism admits (and for the transposed system of the
-// reverse mode), compile the tables, run the host emulation of the solver
-// and of the f/J kernel on a seeded state, and generate the per-mechanism
-// kernel source.  Exit status 0 when every emulation reports no table
-// violation (a sanitizer finding aborts the process on its own).
+// reverse mode), compile the tables, run the host emulation of the solver,
+// of the f/J kernel and of the VJP kernel's work items on a seeded state,
+// and generate the per-mechanism kernel source.  Exit status 0 when every
+// emulation reports no table violation (a sanitizer finding aborts the
+// process on its own).
 //
 // Input: a mechanism file written by the test (int32 N, R, reactant and
 // product counts, then the arrays of mcc_mech_desc in order).
@@ -60,10 +61,12 @@ int main(int argc, char **argv)
             const int v = emulate_cell(t, k.data(), y.data(), 0.37, b.data(), fv.data(), x.data());
             std::vector<double> ff(N), jac(t.nnz > 0 ? t.nnz : 1);
             const int vf = transpose ? 0 : emulate_fj(t, k.data(), y.data(), ff.data(), jac.data());
+            std::vector<double> gy(N), gk(R > 0 ? R : 1);
+            const int vv = transpose ? 0 : emulate_vjp(t, k.data(), y.data(), b.data(), gy.data(), gk.data());
             const std::string src = transpose ? std::string() : generate_module_source(t);
-            printf("tail %d (built %d)%s: %d solver-table and %d f/J-table violations, source %zu bytes\n", tail, t.M,
-                   transpose ? " transposed" : "", v, vf, src.size());
-            total += v + vf;
+            printf("tail %d (built %d)%s: %d solver-table, %d f/J-table and %d VJP-plan violations, source %zu bytes\n",
+                   tail, t.M, transpose ? " transposed" : "", v, vf, vv, src.size());
+            total += v + vf + vv;
         }
     }
     return total == 0 ? 0 : 1;

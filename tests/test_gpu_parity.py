@@ -163,6 +163,70 @@ def test_full_size_fj_sampled_and_homogeneity(dev, oracle_mod, kind):
     assert np.all(np.abs(Jy - rhs) <= 1e-12 * bound)
 
 
+@pytest.mark.parametrize("ld_pad", [0, 1])
+def test_streaming_fj_and_vjp_at_200k_cells(dev, oracle_mod, ld_pad):
+    """200,000 cells, where the inputs exceed the memory-side cache and the
+    f/J launch runs each work item over 128 consecutive tiles at once: every
+    output written (prefilled with NaN), Euler's identity at every cell,
+    sampled cells (first and last tiles among them) against the oracle for
+    f/J and for the VJP.  ld_pad 1: odd leading dimension, the one-cell
+    kernel everywhere."""
+    m, c, _ = synth.workload("medium200k")
+    ld = c.n_cells + ld_pad
+    b = Batch(dev, m, c, ld=ld, oracle_mod=oracle_mod)
+    y = b.y_dev()
+    f = torch.full((m.n_species, ld), float("nan"), dtype=torch.float64, device=dev)
+    J = torch.full((b.h.nnz, ld), float("nan"), dtype=torch.float64, device=dev)
+    b.cells.deriv_jac(y, f, J)
+    rng = np.random.default_rng(2024)
+    v = rng.normal(size=c.y0.shape)
+    gy = torch.full_like(f, float("nan"))
+    gk = torch.full((m.n_reactions, ld), float("nan"), dtype=torch.float64, device=dev)
+    b.cells.vjp(y, _t(_padded(v, ld), dev), gy, gk)
+    torch.cuda.synchronize()
+    C = c.n_cells
+    fn = f.cpu().numpy()[:, :C]
+    gyn, gkn = gy.cpu().numpy()[:, :C], gk.cpu().numpy()[:, :C]
+    assert np.isfinite(fn).all() and np.isfinite(gyn).all() and np.isfinite(gkn).all()
+    sel = np.unique(np.concatenate([np.arange(130), np.arange(C - 130, C), rng.choice(C, 60, replace=False)]))
+    Jn_sel = J[:, torch.from_numpy(sel).to(dev)].cpu().numpy()
+    sub = synth.Cells(T=c.T[sel], P=c.P[sel], jscale=c.jscale[sel], y0=c.y0[:, sel])
+    bs = Batch.__new__(Batch)
+    bs.m, bs.c, bs.h, bs.o = m, sub, b.h, b.o
+    _check_fj(bs, fn[:, sel], Jn_sel, sub.y0)
+    k = b.o.rate_constants(sub.T, sub.jscale)
+    gy_ref, gk_ref = b.o.vjp(k, sub.y0, v[:, sel])
+    _, Js = b.o.jac(k, sub.y0)
+    by, bk = _vjp_bounds(m, k, sub.y0, v[:, sel], Js)
+    assert np.all(np.abs(gyn[:, sel] - gy_ref) <= 1e-12 * by)
+    assert np.all(np.abs(gkn[:, sel] - gk_ref) <= 1e-12 * bk)
+    # Euler's identity at every cell, J copied over in blocks of cells
+    rp, ci = b.h.jac_pattern()
+    rows = np.repeat(np.arange(m.n_species), np.diff(rp))
+    kg = b.k_gpu()
+    for c0 in range(0, C, 50000):
+        c1 = min(C, c0 + 50000)
+        Jn = J[:, c0:c1].cpu().numpy()
+        assert np.isfinite(Jn).all()
+        y0 = c.y0[:, c0:c1]
+        Jy = np.zeros((m.n_species, c1 - c0))
+        np.add.at(Jy, rows, Jn * y0[ci])
+        rhs = np.zeros_like(Jy)
+        bound = np.zeros_like(Jy)
+        for j in range(m.n_reactions):
+            reac = m.reac_idx[m.reac_ptr[j]:m.reac_ptr[j + 1]]
+            r = kg[j, c0:c1] * np.prod(y0[reac], axis=0)
+            order = len(reac)
+            for s in reac:
+                rhs[s] -= order * r
+                bound[s] += order * abs(r)
+            for s, yl in zip(m.prod_idx[m.prod_ptr[j]:m.prod_ptr[j + 1]],
+                             m.prod_yield[m.prod_ptr[j]:m.prod_ptr[j + 1]]):
+                rhs[s] += order * yl * r
+                bound[s] += order * abs(yl * r)
+        assert np.all(np.abs(Jy - rhs) <= 1e-12 * bound)
+
+
 def _solve_parity(b, dt, opts_kw=None, y0=None):
     opts_kw = opts_kw or {}
     y0 = b.c.y0 if y0 is None else y0

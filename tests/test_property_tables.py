@@ -2,8 +2,9 @@
 1 to 3 with repeated reactants (multiplicities), rational yields, species
 that appear on both sides -- compiled by the library on the host, and the
 host emulation of its f/J tables and solver tables compared with the oracle:
-f and J to 1e-12 of the scale, the Newton-matrix solve to round-off, and a
-relabelling of the species permutes every result."""
+f and J to 1e-12 of the scale, the Newton-matrix solve to round-off, the
+work items of the generated VJP kernel (gy = J^T v, d(v.f)/d ln k) to 1e-12
+of their scales, and a relabelling of the species permutes every result."""
 from fractions import Fraction
 
 import numpy as np
@@ -64,6 +65,14 @@ def _check(n, rx, seed):
     assert np.all(np.abs(fs2 - f_ref) <= 1e-12 * fs)
     Mm = np.eye(n) - c * J_ref
     assert np.all(np.abs(Mm @ x - b) <= 1e-11 * (np.abs(Mm) @ np.abs(x) + np.abs(b)))
+    # the VJP kernel's work items: gy = J^T v and d(v.f)/d ln k
+    gy, gk, viol = h.emulate_vjp(k, y, b)
+    assert viol == 0
+    gy_ref, gk_ref = o.vjp(k[:, None], y[:, None], b[:, None])
+    assert np.all(np.abs(gy - gy_ref[:, 0]) <= 1e-12 * (np.abs(b) @ Js + 1e-300))
+    reac_abs = np.array([abs(k[j]) * np.prod(y[r[0]]) * (sum(abs(b[s]) for s in r[0]) + sum(abs(yl * b[s]) for s, yl in r[1]))
+                         for j, r in enumerate(rx)])
+    assert np.all(np.abs(gk - gk_ref[:, 0]) <= 1e-12 * (reac_abs + 1e-300))
     return f, J_ref, x
 
 

@@ -125,8 +125,8 @@ def test_fj_tables_wide_item():
 
 @pytest.mark.parametrize("mech_fn", [synth.mech_small_thermal, synth.mech_medium])
 def test_generated_fj_kernel_compiles(mech_fn):
-    """The mechanism-specialised f/J kernel is generated from the same tables
-    and compiles for gfx950 with hipRTC (no GPU needed)."""
+    """The mechanism-specialised f/J and VJP kernels are generated from the
+    compiled tables and compile for gfx950 with hipRTC (no GPU needed)."""
     m = mech_fn()
     h = mcchem.Mechanism(m, device=-1)
     src = h.fj_source()
@@ -135,9 +135,12 @@ def test_generated_fj_kernel_compiles(mech_fn):
     assert n_items >= 2
     rp, _ = h.jac_pattern()
     for i in range(m.n_species):
-        assert src.count(f"F[{i} * ld] = acc;") == 1
+        assert src.count(f"st_out(&F[{i} * ld], acc);") == 1
+        assert src.count(f"st_out(&GY[{i} * ld], g{i});") == 1
     for e in range(int(rp[-1])):
-        assert src.count(f"G[{e} * ld] = acc;") == 1
+        assert src.count(f"st_out(&G[{e} * ld], acc);") == 1
+    for j in range(m.n_reactions):
+        assert src.count(f"st_out(&GK[{j} * ld], ") == 1
     assert h.compile_fj("gfx950") > 0
 
 
