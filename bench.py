@@ -719,55 +719,53 @@ def main():
     solve_s = float(np.mean(solve_ms)) / 1e3
     achieved_tf = flops / solve_s / 1e12
 
-    # f+J roofline: back-to-back fused launches between two events on the
-    # launch stream; the average launch time
-    for _ in range(10):
-        cells.deriv_jac(y0, f, J, stream=stream)
-    fj_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    fj_ev[0].record(stream)
-    for _ in range(max(args.fj_reps, 1)):
-        cells.deriv_jac(y0, f, J, stream=stream)
-    fj_ev[1].record(stream)
-    torch.cuda.synchronize()
-    fj_s = fj_ev[0].elapsed_time(fj_ev[1]) / 1e3 / max(args.fj_reps, 1)
-    fj_gbs = oc["fj_bytes"] * C / fj_s / 1e9
-
-    # reverse mode: J^T v and d(v.f)/d ln k in one launch, back to back
+    # f+J and VJP rooflines: each kernel's average launch duration, from 20
+    # back-to-back launches captured in a HIP graph (host launch gaps, about
+    # 9 us per call through the Python binding, would otherwise pad the
+    # short launches) and replayed 5 times between two events on the launch
+    # stream; eager back-to-back launches beside them for reference
     v = torch.ones_like(y0)
     gy = torch.empty_like(y0)
     glnk = torch.empty((m.n_reactions, C), dtype=torch.float64, device=dev)
-    for _ in range(10):
-        cells.vjp(y0, v, gy, glnk, stream=stream)
-    vj_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    vj_ev[0].record(stream)
-    for _ in range(max(args.fj_reps, 1)):
-        cells.vjp(y0, v, gy, glnk, stream=stream)
-    vj_ev[1].record(stream)
-    torch.cuda.synchronize()
-    vj_s = vj_ev[0].elapsed_time(vj_ev[1]) / 1e3 / max(args.fj_reps, 1)
+
+    def per_launch(fn, n_graph=20, replays=5):
+        for _ in range(10):
+            fn(stream)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record(stream)
+        for _ in range(max(args.fj_reps, 1)):
+            fn(stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        eager = ev[0].elapsed_time(ev[1]) / 1e3 / max(args.fj_reps, 1)
+        graph = None
+        try:
+            cap = torch.cuda.Stream(device=dev)
+            cap.wait_stream(stream)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                for _ in range(n_graph):
+                    fn(cap)
+            g.replay()
+            torch.cuda.synchronize()
+            ge = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            with torch.cuda.stream(stream):  # replays go to the current stream
+                ge[0].record(stream)
+                for _ in range(replays):
+                    g.replay()
+                ge[1].record(stream)
+            torch.cuda.synchronize()
+            graph = ge[0].elapsed_time(ge[1]) / 1e3 / (n_graph * replays)
+        except RuntimeError as e:  # capture refused: reported, the eager figure used
+            print(f"graph capture failed: {e}", file=sys.stderr)
+        return (graph if graph is not None else eager), eager, graph
+
+    fj_s, fj_eager_s, fj_graph_s = per_launch(lambda s_: cells.deriv_jac(y0, f, J, stream=s_))
+    fj_gbs = oc["fj_bytes"] * C / fj_s / 1e9
+    # reverse mode: J^T v and d(v.f)/d ln k in one launch
+    vj_s, vj_eager_s, vj_graph_s = per_launch(lambda s_: cells.vjp(y0, v, gy, glnk, stream=s_))
     vj_bytes = 8 * (3 * m.n_species + 2 * m.n_reactions)  # read y, v, k; write gy, glnk
     vj_gbs = vj_bytes * C / vj_s / 1e9
-
-    # the same f+J launches captured in a HIP graph (launch gaps amortised)
-    fj_graph_us = None
-    try:
-        cap = torch.cuda.Stream(device=dev)
-        cap.wait_stream(stream)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=cap):
-            for _ in range(20):
-                cells.deriv_jac(y0, f, J, stream=cap)
-        g.replay()
-        torch.cuda.synchronize()
-        ge = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-        ge[0].record()
-        for _ in range(5):
-            g.replay()
-        ge[1].record()
-        torch.cuda.synchronize()
-        fj_graph_us = ge[0].elapsed_time(ge[1]) * 1e3 / 100
-    except RuntimeError as e:  # capture refused: reported, not fatal
-        print(f"f+J graph capture failed: {e}", file=sys.stderr)
 
     # counter figures were taken for one scheduled launch per outer step
     plain = args.steps_per_launch == 0 and not args.multicell and unbalanced_ms is not None
@@ -810,10 +808,13 @@ def main():
                         "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
                         "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
                         "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"],
-                        "launch_us_in_graph": fj_graph_us},
+                        "launch_us_eager": fj_eager_s * 1e6,
+                        "timing": "20 launches in a HIP graph" if fj_graph_s is not None else "eager"},
         "vjp_roofline": {"kernel": "mcc_vjp_generated2 (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
                          "achieved": vj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vj_gbs / HBM_PEAK_GBS,
-                         "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes},
+                         "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes,
+                         "launch_us_eager": vj_eager_s * 1e6,
+                         "timing": "20 launches in a HIP graph" if vj_graph_s is not None else "eager"},
         "per_launch_state": per_launch_state(sn, args.steps_per_launch, m.n_species, mech),
         "solver": {"failed_cells": int((st != 0).sum()),
                    "steps_mean": float(sn["steps"].mean()), "steps_max": int(sn["steps"].max()),

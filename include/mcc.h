@@ -281,14 +281,23 @@ mcc_status mcc_debug_schedule_info(const mcc_mech *mech, int64_t *out);
 mcc_status mcc_mech_destroy(mcc_mech *mech);
 
 /* A batch of n_cells cells (0 allowed: every call is then a no-op) with
- * leading dimension ld >= n_cells for every per-cell array.  Allocates the
- * device array of rate constants [n_reactions][ld].  Synchronous. */
+ * leading dimension ld >= n_cells for every per-cell array (Section 3,
+ * Multi-cells: many grid cells of one mechanism solved together, their
+ * data laid out so that consecutive cells are consecutive in memory for
+ * every species and reaction).  Allocates the device array of rate
+ * constants [n_reactions][ld].  MCC_ERR_INVALID_ARG for n_cells < 0 or
+ * ld < n_cells or n_cells > 2^31 - 1; MCC_ERR_STATE for a host-only
+ * mechanism.  Synchronous. */
 mcc_status mcc_cells_create(const mcc_mech *mech, int64_t n_cells, int64_t ld, mcc_cells **out);
 
 /* Per-cell environment (device arrays [n_cells]): temperature T in K
  * (finite, > 0), pressure P in hPa (reserved: the current reaction types do
  * not use it, may be NULL), photolysis scale jscale (may be NULL = 1).
- * Computes the rate constants k [n_reactions][ld] on `stream`. */
+ * Computes the rate constants k [n_reactions][ld] on `stream` and keeps
+ * them with the batch for every later call (Section 2: rate constants are
+ * evaluated from the environment once and stored with the reaction
+ * parameters; Section 4: thermal reactions follow the Arrhenius form
+ * A exp(-theta / T), photolysis reactions A times the cell's scale). */
 mcc_status mcc_cells_bind(mcc_cells *cells, const double *T, const double *P,
                           const double *jscale, void *stream);
 

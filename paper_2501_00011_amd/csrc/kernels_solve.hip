@@ -166,15 +166,23 @@ struct Cell {
     // Reaction rates at v into rv (lane per reaction); rv[R] = 0.
     __device__ __forceinline__ void rates(const double (&v)[NS])
     {
-        put_y(v);
+        // the first round's reactant ids are requested before y is stored,
+        // so that their global-memory latency overlaps that store
         const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
-        for (int j0 = 0; j0 < p.R; j0 += 4 * kWave) {
-            int4 a[4];
+        int4 a[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = j0 + u * kWave + lane;
-                a[u] = j < p.R ? rx[j] : make_int4(p.NV, p.NV, p.NV, 0);
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int j = u * kWave + lane;
+            a[u] = j < p.R ? rx[j] : make_int4(p.NV, p.NV, p.NV, 0);
+        }
+        put_y(v);
+        for (int j0 = 0; j0 < p.R; j0 += 4 * kWave) {
+            if (j0 > 0)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * kWave + lane;
+                    a[u] = j < p.R ? rx[j] : make_int4(p.NV, p.NV, p.NV, 0);
+                }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = j0 + u * kWave + lane;
@@ -219,15 +227,21 @@ struct Cell {
     // Rate partials d r_j / d y_s at v into pv (lane per partial); pv[P] = 0.
     __device__ __forceinline__ void partials(const double (&v)[NS])
     {
-        put_y(v);
         const int4 *pt = reinterpret_cast<const int4 *>(p.part);
-        for (int q0 = 0; q0 < p.P; q0 += 4 * kWave) {
-            int4 a[4];
+        int4 a[4];  // requested before y is stored, as in rates()
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = q0 + u * kWave + lane;
-                a[u] = q < p.P ? pt[q] : make_int4(0, p.NV, p.NV, 0);
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int q = u * kWave + lane;
+            a[u] = q < p.P ? pt[q] : make_int4(0, p.NV, p.NV, 0);
+        }
+        put_y(v);
+        for (int q0 = 0; q0 < p.P; q0 += 4 * kWave) {
+            if (q0 > 0)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * kWave + lane;
+                    a[u] = q < p.P ? pt[q] : make_int4(0, p.NV, p.NV, 0);
+                }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u * kWave + lane;
@@ -486,15 +500,22 @@ struct Cell {
         for (int t = 0; t < NS; ++t) {
             const int ks = M > 0 ? (t + 1) % NS : t;
             if (M > 0 && ks == 0) {
-                // tail columns: only tail rows (slot 0) lie below them
+                // tail columns: only tail rows (slot 0) lie below them.  A
+                // block's eight entries are loaded together ahead of the
+                // dependent chain of broadcasts (the scheduling barrier keeps
+                // the compiler from sinking each load to its use, which put a
+                // local-memory round trip into every column).
 #pragma unroll 1
                 for (int k8 = 0; k8 < M; k8 += 8) {
+                    double tv[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) tv[i] = T[tat(trow, k8 + i)];
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
                         const int k = k8 + i;
-                        const double tv = T[tat(trow, k)];
                         const double xk = lane_bcast(b[0], k);
-                        if (lane > k && lane < M) b[0] -= tv * xk;
+                        if (lane > k && lane < M) b[0] -= tv[i] * xk;
                     }
                 }
                 continue;
@@ -554,12 +575,15 @@ struct Cell {
                     if (blk > 0)
 #pragma unroll
                         for (int s = 1; s < NS; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + blk - 1];
+                    double tv[8];  // 1/U_kk on the diagonal, U above it; loaded ahead as above
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) tv[i] = T[tat(trow, blk * 8 + i)];
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int i = 7; i >= 0; --i) {
                         const int kl = blk * 8 + i;
-                        const double tv = T[tat(trow, kl)];  // 1/U_kk on the diagonal, U above it
-                        const double xk = lane_bcast(b[0] * tv, kl);
-                        b[0] = lane == kl ? xk : (lane < kl ? b[0] - tv * xk : b[0]);
+                        const double xk = lane_bcast(b[0] * tv[i], kl);
+                        b[0] = lane == kl ? xk : (lane < kl ? b[0] - tv[i] * xk : b[0]);
 #pragma unroll
                         for (int s = 1; s < NS; ++s) b[s] -= v[s][i] * xk;
                     }
