@@ -33,8 +33,9 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wavefront-instructions/s
 SOLVE_SOURCES = ["paper_2501_00011_amd/csrc/kernels_solve.hip", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
                  "paper_2501_00011_amd/csrc/mech_compile.cpp"]
 FJ_SOURCES = ["paper_2501_00011_amd/csrc/fj_codegen.cpp", "paper_2501_00011_amd/csrc/mcc_internal.hpp",
-              "paper_2501_00011_amd/csrc/mech_compile.cpp"]
+              "paper_2501_00011_amd/csrc/mech_compile.cpp", "paper_2501_00011_amd/csrc/api.hip"]
 FJ_KERNEL = "mcc_fj_generated2"  # the two-cell variant (even leading dimension)
+VJP_KERNEL = "mcc_vjp_generated2"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_medium10k.txt")
 
 
@@ -55,8 +56,10 @@ def measured_counter(kernel, sources, key="traffic_bytes"):
     return rec.get(key) if h.hexdigest()[:16] == rec["source_sha256_16"] else None
 
 
-def measured_traffic(kernel, sources):
-    return measured_counter(kernel, sources, "traffic_bytes")
+def measured_traffic(kernel, sources, n_cells=10000):
+    """HBM bytes per launch of a generated kernel, measured at 10,000 cells
+    (key: the kernel's name) or at another size (key: name@cells)."""
+    return measured_counter(kernel if n_cells == 10000 else f"{kernel}@{n_cells}", sources, "traffic_bytes")
 
 
 def solver_counter(key, n_cells, dense_tail):
@@ -806,12 +809,13 @@ def main():
                      "issue": issue_roofline(solve_s, C, tail_measured)},
         "fj_roofline": {"kernel": FJ_KERNEL + " (calc_deriv_jac, generated for this mechanism)", "bound": "hbm",
                         "achieved": fj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fj_gbs / HBM_PEAK_GBS,
-                        "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES) if C == 10000 else None,
+                        "traffic": measured_traffic(FJ_KERNEL, FJ_SOURCES, C),
                         "launch_us": fj_s * 1e6, "bytes_per_cell": oc["fj_bytes"],
                         "launch_us_eager": fj_eager_s * 1e6,
                         "timing": "20 launches in a HIP graph" if fj_graph_s is not None else "eager"},
-        "vjp_roofline": {"kernel": "mcc_vjp_generated2 (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
+        "vjp_roofline": {"kernel": VJP_KERNEL + " (calc_vjp: J^T v and d(v.f)/d ln k)", "bound": "hbm",
                          "achieved": vj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": vj_gbs / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(VJP_KERNEL, FJ_SOURCES, C),
                          "launch_us": vj_s * 1e6, "bytes_per_cell": vj_bytes,
                          "launch_us_eager": vj_eager_s * 1e6,
                          "timing": "20 launches in a HIP graph" if vj_graph_s is not None else "eager"},
