@@ -290,9 +290,9 @@ struct Cell {
             for (int i = 0; i < kBlk; ++i) {
                 const uint32_t lo = (uint32_t)op[i], hi = (uint32_t)(op[i] >> 32);
                 ad[i] = lu[lo & kOffMask];
-                al[i] = lu[(lo >> kOffBits) & kOffMask];
-                au[i] = lu[((lo >> 28) | (hi << 4)) & kOffMask];
-                ag[i] = lu[(hi >> 10) & kOffMask];
+                al[i] = lu[(lo >> 16) & kOffMask];
+                au[i] = lu[hi & kOffMask];
+                ag[i] = lu[(hi >> 16) & kOffMask];
             }
             bool any_recip = false;
             double res[kBlk];
@@ -300,13 +300,16 @@ struct Cell {
             bool store[kBlk], recip[kBlk];
 #pragma unroll
             for (int i = 0; i < kBlk; ++i) {
-                const uint32_t fl = (uint32_t)(op[i] >> 56);
-                const double a0 = (fl & kFirst) ? ad[i] : acc;
-                acc = (fl & kScale) ? a0 * ag[i] : a0 - (al[i] * ag[i]) * au[i];
+                const double a0 = (op[i] & kLuFirst) ? ad[i] : acc;
+                // a scaling op reads the zero cell for l and u, so one form
+                // serves both kinds: (a0 or a0 / U_kk) - l / U_kk * u.  Every
+                // operand is then used on every lane, and no branch per op
+                // re-reads l and u inside it.
+                acc = ((op[i] & kLuScale) ? a0 * ag[i] : a0) - (al[i] * ag[i]) * au[i];
                 res[i] = acc;
                 dst[i] = (int)(op[i] & kOffMask);
-                store[i] = fl & kLast;
-                recip[i] = fl & kRecip;
+                store[i] = op[i] & kLuLast;
+                recip[i] = op[i] & kLuRecip;
                 any_recip |= recip[i];
             }
             if (__any(any_recip)) {
@@ -320,7 +323,7 @@ struct Cell {
 #pragma unroll
             for (int i = 0; i < kBlk; ++i)
                 if (store[i]) lu[dst[i]] = res[i];
-            const bool barrier = (op[kBlk - 1] >> 56) & kBarrier;
+            const bool barrier = op[kBlk - 1] & kLuBarrier;
             if (__builtin_amdgcn_readfirstlane((int)barrier)) __syncthreads();
         }
         const bool front_bad = __any(bad);

@@ -28,8 +28,14 @@ __host__ __device__ constexpr int tail_at(int M, int row, int col)
 }
 constexpr int kOffBits = 14;  // bits of an LDS offset inside an op
 constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
-// op flags (bits 56.. of an LU op; bits 28.. of a 16-byte op's meta word)
-constexpr uint32_t kFirst = 1, kLast = 2, kRecip = 4, kScale = 8, kBarrier = 16, kDiag = 4;
+// flags of a 16-byte op's meta word (bits 28..)
+constexpr uint32_t kFirst = 1, kLast = 2, kDiag = 4;
+// An LU op (64 bits) is four 16-bit fields -- destination, l, u and the
+// stored 1/U_kk, each a 14-bit LDS index from bit 0 of its field, so that a
+// field is taken out with one mask or bit-field extract -- with the flags in
+// the fields' top bits.
+constexpr uint64_t kLuFirst = 1ull << 14, kLuLast = 1ull << 15, kLuScale = 1ull << 30, kLuRecip = 1ull << 31,
+                   kLuBarrier = 1ull << 46;
 
 // Streaming f/J kernel tables.  A work item is a run of chunks processed by
 // one wavefront in order.  A chunk computes its monomials -- the product of
@@ -144,8 +150,9 @@ struct HostTables {
     // Newton matrix: chains of terms per LU entry.
     std::vector<Op16> nm_ops;
     int nm_blocks = 0;
-    // LU: level-scheduled update / reciprocal / scale ops, 14-bit offsets
-    // dst | l | u | d and flags in bits 56..; barrier flag ends a level.
+    // LU: level-scheduled update / reciprocal / scale ops (kLu* layout:
+    // dst | l | u | d in 16-bit fields, flags in their top bits); the
+    // barrier flag ends a level.
     std::vector<uint64_t> lu_ops;
     int lu_blocks = 0, lu_steps = 0;
     // Schur complement of the front pivots onto the dense tail, as FP64

@@ -123,10 +123,9 @@ Op16 make_op16(double coef, uint32_t meta)
     return o;
 }
 
-uint64_t lu_op(int dst, int l, int u, int dg, uint32_t flags)
+uint64_t lu_op(int dst, int l, int u, int dg, uint64_t flags)
 {
-    return (uint64_t)dst | ((uint64_t)l << kOffBits) | ((uint64_t)u << (2 * kOffBits)) |
-           ((uint64_t)dg << (3 * kOffBits)) | ((uint64_t)flags << 56);
+    return (uint64_t)dst | ((uint64_t)l << 16) | ((uint64_t)u << 32) | ((uint64_t)dg << 48) | flags;
 }
 
 // Longest-first greedy assignment of op chains to the 64 lanes of a wave.
@@ -619,7 +618,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
             if (lp[k][q] && lp[q][k]) diag_last[k] = std::max(diag_last[k], level[q]);
     t->lu_ops.clear();
     t->lu_steps = 0;
-    const uint64_t NOP = lu_op(TRASH, ZERO, ZERO, ZERO, kFirst | kLast);
+    const uint64_t NOP = lu_op(TRASH, ZERO, ZERO, ZERO, kLuFirst | kLuLast);
     auto emit_step = [&](std::vector<std::vector<uint64_t>> &chains) {
         if (chains.empty()) return;
         auto lanes = pack_chains(chains);
@@ -628,7 +627,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         len = (len + kBlk - 1) / kBlk * kBlk;
         for (auto &l : lanes) {
             while (l.size() < len) l.push_back(NOP);
-            l.back() |= (uint64_t)kBarrier << 56;
+            l.back() |= kLuBarrier;
         }
         emit_blocks(lanes, NOP, &t->lu_ops);
         t->lu_steps++;
@@ -636,7 +635,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
     if (F > 0) {
         std::vector<std::vector<uint64_t>> chains;
         for (int k = 0; k < F; ++k)
-            if (diag_last[k] == 0) chains.push_back({lu_op(lpos[k][k], ZERO, ZERO, ZERO, kFirst | kLast | kRecip)});
+            if (diag_last[k] == 0) chains.push_back({lu_op(lpos[k][k], ZERO, ZERO, ZERO, kLuFirst | kLuLast | kLuRecip)});
         emit_step(chains);
     }
     for (int L = 1; L <= maxlev + 1 && F > 0; ++L) {
@@ -645,7 +644,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         for (int k = 0; k < F; ++k) {
             if (level[k] == L - 1)  // scale column k of a pivot finished one level ago
                 for (int i = k + 1; i < N; ++i)
-                    if (lp[i][k]) chains.push_back({lu_op(lpos[i][k], ZERO, ZERO, lpos[k][k], kFirst | kLast | kScale)});
+                    if (lp[i][k]) chains.push_back({lu_op(lpos[i][k], ZERO, ZERO, lpos[k][k], kLuFirst | kLuLast | kLuScale)});
             if (level[k] != L) continue;
             for (int i = k + 1; i < N; ++i) {
                 if (!lp[i][k]) continue;
@@ -658,12 +657,12 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         }
         for (auto &kv : by_dst) {
             auto &c = kv.second;
-            c.front() |= (uint64_t)kFirst << 56;
-            c.back() |= (uint64_t)kLast << 56;
+            c.front() |= kLuFirst;
+            c.back() |= kLuLast;
             const int dst = kv.first;
             // front diagonal entry whose last update happens at this level
             for (int k = 0; k < F; ++k)
-                if (lpos[k][k] == dst && diag_last[k] == L) c.back() |= (uint64_t)kRecip << 56;
+                if (lpos[k][k] == dst && diag_last[k] == L) c.back() |= kLuRecip;
             chains.push_back(c);
         }
         emit_step(chains);

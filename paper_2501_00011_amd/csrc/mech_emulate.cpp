@@ -94,11 +94,10 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
         for (int lane = 0; lane < kWave; ++lane)
             for (int i = 0; i < kBlk; ++i) {
                 const uint64_t w = t.lu_ops[((size_t)bk * kWave + lane) * kBlk + i];
-                const int dst = chk(w & kOffMask, t.lu_nnz + 2), l = chk((w >> 14) & kOffMask, t.lu_nnz + 2);
-                const int u = chk((w >> 28) & kOffMask, t.lu_nnz + 2), g = chk((w >> 42) & kOffMask, t.lu_nnz + 2);
-                const uint32_t fl = (uint32_t)(w >> 56);
-                const double a0 = (fl & kFirst) ? lu[dst] : acc[lane];
-                if (fl & kScale) {
+                const int dst = chk(w & kOffMask, t.lu_nnz + 2), l = chk((w >> 16) & kOffMask, t.lu_nnz + 2);
+                const int u = chk((w >> 32) & kOffMask, t.lu_nnz + 2), g = chk((w >> 48) & kOffMask, t.lu_nnz + 2);
+                const double a0 = (w & kLuFirst) ? lu[dst] : acc[lane];
+                if (w & kLuScale) {
                     acc[lane] = a0 * lu[g];
                     operand_reads.insert(g);
                 } else {
@@ -108,10 +107,10 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
                     operand_reads.insert(g);
                 }
                 double r = acc[lane];
-                if ((fl & kLast) && (fl & kRecip)) r = 1.0 / r;
+                if ((w & kLuLast) && (w & kLuRecip)) r = 1.0 / r;
                 res[lane * kBlk + i] = r;
                 dsts[lane * kBlk + i] = dst;
-                store[lane * kBlk + i] = (fl & kLast) != 0;
+                store[lane * kBlk + i] = (w & kLuLast) != 0;
             }
         for (int q = 0; q < kWave * kBlk; ++q)
             if (store[q]) {
@@ -125,8 +124,8 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
         // the barrier flag must be the same on every lane
         const uint64_t first_lane = t.lu_ops[((size_t)bk * kWave) * kBlk + kBlk - 1];
         for (int lane = 1; lane < kWave; ++lane)
-            if (((t.lu_ops[((size_t)bk * kWave + lane) * kBlk + kBlk - 1] ^ first_lane) >> 56) & kBarrier) bad++;
-        if ((first_lane >> 56) & kBarrier) {
+            if ((t.lu_ops[((size_t)bk * kWave + lane) * kBlk + kBlk - 1] ^ first_lane) & kLuBarrier) bad++;
+        if (first_lane & kLuBarrier) {
             // an operand (l, u or 1/U_kk) written in the same level is a hazard
             for (int rd : operand_reads)
                 if (rd != TRASH && rd != ZERO && step_writes.count(rd)) bad++;
