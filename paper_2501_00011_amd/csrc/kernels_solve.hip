@@ -37,25 +37,56 @@
 namespace mcc {
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return __shfl(v, 0);  // lane 0's sum on every lane: bitwise uniform
-}
-
-__device__ __forceinline__ double wave_min(double v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
-    return __shfl(v, 0);
-}
+// Every workgroup of the kernels below is one wavefront (64 lanes, one cell),
+// and a wavefront's local-memory instructions are performed in the order it
+// issues them.  A hand-over of local memory between its lanes therefore needs
+// only that the compiler keep the accesses in program order on either side:
+// a fence at wavefront scope, which emits no instruction and no wait (a
+// workgroup barrier would also wait for every outstanding local-memory access
+// to complete).
+__device__ __forceinline__ void lds_handover() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 __device__ __forceinline__ double lane_bcast(double v, int src_lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src_lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src_lane);
     return __hiloint2double(hi, lo);
+}
+
+// The value of another lane of the same row of 16, by a DPP lane pattern
+// (no local-memory round trip).
+template <int CTRL>
+__device__ __forceinline__ double row_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Reduction over the 64 lanes (all active): within each row of 16 lanes by
+// exchanges with lane ^ 1, lane ^ 2 (quad patterns), then the mirror lane of
+// the half row and of the row, so that every lane of a row holds the row's
+// result (each exchange combines two equal partial results, so the lanes of a
+// row agree bit for bit); then the four row results combined in one fixed
+// order on every lane.
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op)
+{
+    v = op(v, row_move<0xb1>(v));   // quad_perm [1, 0, 3, 2]
+    v = op(v, row_move<0x4e>(v));   // quad_perm [2, 3, 0, 1]
+    v = op(v, row_move<0x141>(v));  // row_half_mirror
+    v = op(v, row_move<0x140>(v));  // row_mirror
+    return op(op(lane_bcast(v, 0), lane_bcast(v, 16)), op(lane_bcast(v, 32), lane_bcast(v, 48)));
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    return wave_reduce(v, [](double a, double b) { return a + b; });
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
 
 // 1/x of a pivot (finite and not tiny: checked before use): the hardware's
@@ -145,11 +176,11 @@ struct Cell {
 
     __device__ __forceinline__ void put_y(const double (&v)[NS])
     {
-        __syncthreads();
+        lds_handover();
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (lane < p.slot_cols[s]) yv[p.ybase[s] + lane] = v[s];
-        __syncthreads();
+        lds_handover();
     }
 
     // f at v: reaction rates r_j = k_j y_a y_b y_c (lane per reaction), then
@@ -207,7 +238,7 @@ struct Cell {
             }
         }
         if (lane == 0) rv[p.R] = 0.0;  // the zero rate idle gather lanes read
-        __syncthreads();
+        lds_handover();
     }
 
     // Newton matrix M = I - c J(v) written over the LU storage (fill = 0).
@@ -233,7 +264,7 @@ struct Cell {
                 }
             }
         }
-        __syncthreads();
+        lds_handover();
     }
 
     // Rate partials d r_j / d y_s at v into pv (lane per partial); pv[P] = 0.
@@ -265,7 +296,7 @@ struct Cell {
             }
         }
         if (lane == 0) pv[p.P] = 0.0;  // the zero partial of fill entries and idle lanes
-        __syncthreads();
+        lds_handover();
     }
 
     // Front pivots: level-scheduled right-looking sparse LU with the static
@@ -323,8 +354,8 @@ struct Cell {
 #pragma unroll
             for (int i = 0; i < kBlk; ++i)
                 if (store[i]) lu[dst[i]] = res[i];
-            const bool barrier = op[kBlk - 1] & kLuBarrier;
-            if (__builtin_amdgcn_readfirstlane((int)barrier)) __syncthreads();
+            // the next level reads what this one wrote: keep the order
+            lds_handover();
         }
         const bool front_bad = __any(bad);
         schur();
@@ -401,7 +432,7 @@ struct Cell {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) tb[tat(16 * (i0 + i) + 4 * r + g, 16 * j + c16)] = acc[i][j][r];
             }
-            __syncthreads();
+            lds_handover();
         }
     }
 
@@ -449,7 +480,7 @@ struct Cell {
                 if (in && lane >= k0)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) T[tat(row, k0 + c)] = a[c];
-                __syncthreads();
+                lds_handover();
                 const int kt = k0 + 4;
                 if (kt >= M) break;
                 // 2. the panel's rows right of it (unit lower L11 from the panel)
@@ -469,7 +500,7 @@ struct Cell {
                     T[tat(k0 + 2, row)] = u2;
                     T[tat(k0 + 3, row)] = u3;
                 }
-                __syncthreads();
+                lds_handover();
                 // 3. trailing update on the tiles that meet rows and columns >= kt
                 const int t0 = kt / 16;
                 double af[NT], bf[NT];
@@ -492,7 +523,7 @@ struct Cell {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) T[tat(16 * i + 4 * r + g, 16 * j + c16)] = acc[r];
                     }
-                __syncthreads();
+                lds_handover();
             }
             return __any(bad);
         }
@@ -681,7 +712,7 @@ __device__ __forceinline__ void rescale(double (&D)[kMaxOrder + 3][NS], int orde
 {
     constexpr int M6 = kMaxOrder + 1;
     const int lane = (int)threadIdx.x;
-    __syncthreads();
+    lds_handover();
     if (lane < M6 * M6) {
         const int i = lane / M6, j = lane % M6;
         double acc = 0.0;
@@ -693,7 +724,7 @@ __device__ __forceinline__ void rescale(double (&D)[kMaxOrder + 3][NS], int orde
         }
         tm[lane] = acc;
     }
-    __syncthreads();
+    lds_handover();
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         double out[M6];
@@ -717,7 +748,7 @@ __device__ __forceinline__ void rescale_transposed(double (&L)[kMaxOrder + 3][NS
 {
     constexpr int M6 = kMaxOrder + 1;
     const int lane = (int)threadIdx.x;
-    __syncthreads();
+    lds_handover();
     if (lane < M6 * M6) {
         const int i = lane / M6, j = lane % M6;
         double acc = 0.0;
@@ -729,7 +760,7 @@ __device__ __forceinline__ void rescale_transposed(double (&L)[kMaxOrder + 3][NS
         }
         tm[lane] = acc;
     }
-    __syncthreads();
+    lds_handover();
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         double out[M6];
