@@ -105,10 +105,13 @@ __device__ __forceinline__ double pivot_rcp(double x)
 // of the FP64 power function keeps its temporaries out of the solver loop.
 __device__ __noinline__ double step_pow(double x, double y) { return pow(x, y); }
 
+// gamma_j = sum_{i=1..j} 1/i, summed in that order; the reciprocals are
+// compile-time constants, so a run-time j costs no division.
 __device__ __forceinline__ double bdf_gamma(int j)
 {
     double g = 0.0;
-    for (int i = 1; i <= j; ++i) g += 1.0 / i;
+#pragma unroll
+    for (int i = 1; i <= kMaxOrder; ++i) g = i <= j ? g + 1.0 / i : g;
     return g;
 }
 
@@ -707,23 +710,37 @@ struct Cell {
 // into differences by U = R(1), an involution).  Lane (i, j) of the first 36
 // lanes computes T_ij into LDS; every lane then applies T to its entries
 // with broadcast reads.
+//
+// T_ij without a division per factor: U_li = (-1)^l C(i, l) (the product
+// has the factor 0 once l > i), and R_jl = P_jl / j! with P_jl the product
+// of the j numerators, so T_ij = (sum_{l <= order} P_jl (-1)^l C(i, l)) / j!.
+__device__ __forceinline__ double rescale_entry(int i, int j, int order, double rho)
+{
+    double acc = 0.0, u = 1.0;  // u = (-1)^l C(i, l)
+    for (int l = 0; l <= order; ++l) {
+        // (-1)^l C(i, l) = (-1)^(l-1) C(i, l - 1) (l - 1 - i) / l, an integer of
+        // magnitude at most 10: the rounded product with the reciprocal
+        // estimate of l is exact
+        if (l > 0) u = rint(u * (l - 1 - i) * __builtin_amdgcn_rcp((double)l));
+        const double x = rho * l;
+        double num = 1.0;
+#pragma unroll
+        for (int m = 1; m <= kMaxOrder; ++m) num = m <= j ? num * ((m - 1) - x) : num;
+        acc = fma(num, u, acc);
+    }
+    int fact = 1;
+#pragma unroll
+    for (int m = 2; m <= kMaxOrder; ++m) fact = m <= j ? fact * m : fact;
+    return acc / fact;
+}
+
 template <int NS>
 __device__ __forceinline__ void rescale(double (&D)[kMaxOrder + 3][NS], int order, double rho, double *tm)
 {
     constexpr int M6 = kMaxOrder + 1;
     const int lane = (int)threadIdx.x;
     lds_handover();
-    if (lane < M6 * M6) {
-        const int i = lane / M6, j = lane % M6;
-        double acc = 0.0;
-        for (int l = 0; l <= order; ++l) {
-            double r = 1.0, u = 1.0;
-            for (int m = 1; m <= j; ++m) r *= ((m - 1) - rho * l) / m;
-            for (int m = 1; m <= l; ++m) u *= (double)((m - 1) - i) / m;
-            acc += r * u;
-        }
-        tm[lane] = acc;
-    }
+    if (lane < M6 * M6) tm[lane] = rescale_entry(lane / M6, lane % M6, order, rho);
     lds_handover();
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -749,17 +766,7 @@ __device__ __forceinline__ void rescale_transposed(double (&L)[kMaxOrder + 3][NS
     constexpr int M6 = kMaxOrder + 1;
     const int lane = (int)threadIdx.x;
     lds_handover();
-    if (lane < M6 * M6) {
-        const int i = lane / M6, j = lane % M6;
-        double acc = 0.0;
-        for (int l = 0; l <= order; ++l) {
-            double r = 1.0, u = 1.0;
-            for (int m = 1; m <= j; ++m) r *= ((m - 1) - rho * l) / m;
-            for (int m = 1; m <= l; ++m) u *= (double)((m - 1) - i) / m;
-            acc += r * u;
-        }
-        tm[lane] = acc;
-    }
+    if (lane < M6 * M6) tm[lane] = rescale_entry(lane / M6, lane % M6, order, rho);
     lds_handover();
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
