@@ -147,6 +147,32 @@ struct Prefetcher {
     }
 };
 
+// Entry e of a table of 16-bit LDS indices packed two to a 32-bit word,
+// read from the double array whose LDS byte address is base: index * 8 +
+// base is one v_mad_u32_u16 (its op_sel picks the word's high half), where
+// an extract and a shift-add take two vector instructions.  A generic
+// pointer into LDS carries the LDS byte address in its low 32 bits.
+__device__ __forceinline__ uint32_t lds_base(const double *p) { return (uint32_t)(uintptr_t)p; }
+
+// (e is a compile-time constant wherever this is inlined: the loops around
+// every use are unrolled)
+__device__ __forceinline__ double lds_field(const uint32_t *w, int e, uint32_t base)
+{
+    uint32_t a;
+    if (e & 1)
+        asm("v_mad_u32_u16 %0, %1, 8, %2 op_sel:[1,0,0,0]" : "=v"(a) : "v"(w[e >> 1]), "s"(base));
+    else
+        asm("v_mad_u32_u16 %0, %1, 8, %2" : "=v"(a) : "v"(w[e >> 1]), "s"(base));
+    return *reinterpret_cast<const __attribute__((address_space(3))) double *>(static_cast<uintptr_t>(a));
+}
+
+// the eight entries of a 16-byte group
+__device__ __forceinline__ void lds_fields8(const uint32_t (&w)[4], uint32_t base, double (&v)[8])
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = lds_field(w, e, base);
+}
+
 __device__ __forceinline__ int off_at(uint32_t v, int sh) { return (int)((v >> sh) & kOffMask); }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -390,6 +416,7 @@ struct Cell {
             const int g = lane >> 4, c16 = lane & 15;
             double *tb = lu + p.tail_base;
             const uint4 *tab = reinterpret_cast<const uint4 *>(p.schur_tab) + lane;
+            const uint32_t lub = lds_base(lu);
 #pragma unroll
             for (int i0 = 0; i0 < NT; i0 += TI) {
                 v4d acc[TI][NT];
@@ -412,15 +439,11 @@ struct Cell {
 #pragma unroll
                     for (int kk = 0; kk < SK; ++kk) {
                         if (k0 + kk >= KS) break;
-                        auto at = [&](int q) {
-                            const int e = kk * 2 * NT + q;
-                            return lu[(w[e >> 1] >> (16 * (e & 1))) & 0xffff];
-                        };
                         double a[TI], b[NT];
 #pragma unroll
-                        for (int i = 0; i < TI; ++i) a[i] = -at(i0 + i);
+                        for (int i = 0; i < TI; ++i) a[i] = -lds_field(w, kk * 2 * NT + i0 + i, lub);
 #pragma unroll
-                        for (int j = 0; j < NT; ++j) b[j] = at(NT + j);
+                        for (int j = 0; j < NT; ++j) b[j] = lds_field(w, kk * 2 * NT + NT + j, lub);
 #pragma unroll
                         for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -544,6 +567,7 @@ struct Cell {
         const uint4 *fw = reinterpret_cast<const uint4 *>(p.fwd_map);
         const uint4 *bw = reinterpret_cast<const uint4 *>(p.bwd_map);
         const double *T = lu + p.tail_base;
+        const uint32_t lub = lds_base(lu);
         const int trow = M > 0 && lane < M ? lane : 0;  // this lane's tail row
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
@@ -583,8 +607,7 @@ struct Cell {
                     if (ord(s) >= ord(ks)) {
                         const uint4 o = nxt[s];
                         const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                        lds_fields8(w, lub, v[s]);
                     }
                 if (blk + 1 < b1)
 #pragma unroll
@@ -618,8 +641,7 @@ struct Cell {
                     for (int s = 1; s < NS; ++s) {
                         const uint4 o = nxt[s];
                         const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                        lds_fields8(w, lub, v[s]);
                     }
                     if (blk > 0)
 #pragma unroll
@@ -653,8 +675,7 @@ struct Cell {
                     if (ord(s) <= ord(ks)) {
                         const uint4 o = nxt[s];
                         const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) v[s][i] = lu[(w[i >> 1] >> (16 * (i & 1))) & 0xffff];
+                        lds_fields8(w, lub, v[s]);
                     }
                 if (blk - 1 >= b0)
 #pragma unroll
