@@ -156,15 +156,22 @@ __device__ __forceinline__ uint32_t lds_base(const double *p) { return (uint32_t
 
 // (e is a compile-time constant wherever this is inlined: the loops around
 // every use are unrolled)
-__device__ __forceinline__ double lds_field(const uint32_t *w, int e, uint32_t base)
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t *w, int e, uint32_t base)
 {
     uint32_t a;
     if (e & 1)
         asm("v_mad_u32_u16 %0, %1, 8, %2 op_sel:[1,0,0,0]" : "=v"(a) : "v"(w[e >> 1]), "s"(base));
     else
         asm("v_mad_u32_u16 %0, %1, 8, %2" : "=v"(a) : "v"(w[e >> 1]), "s"(base));
-    return *reinterpret_cast<const __attribute__((address_space(3))) double *>(static_cast<uintptr_t>(a));
+    return a;
 }
+
+__device__ __forceinline__ __attribute__((address_space(3))) double &lds_ref(uint32_t a)
+{
+    return *reinterpret_cast<__attribute__((address_space(3))) double *>(static_cast<uintptr_t>(a));
+}
+
+__device__ __forceinline__ double lds_field(const uint32_t *w, int e, uint32_t base) { return lds_ref(lds_addr(w, e, base)); }
 
 // the eight entries of a 16-byte group
 __device__ __forceinline__ void lds_fields8(const uint32_t (&w)[4], uint32_t base, double (&v)[8])
@@ -173,7 +180,6 @@ __device__ __forceinline__ void lds_fields8(const uint32_t (&w)[4], uint32_t bas
     for (int e = 0; e < 8; ++e) v[e] = lds_field(w, e, base);
 }
 
-__device__ __forceinline__ int off_at(uint32_t v, int sh) { return (int)((v >> sh) & kOffMask); }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -276,20 +282,21 @@ struct Cell {
         partials(v);
         Prefetcher<Op16> st;
         st.start(p.nm_ops, lane, p.nm_blocks);
+        const uint32_t pvb = lds_base(pv), lub = lds_base(lu);
         double acc = 0.0;
         for (int b = 0; b < p.nm_blocks; ++b) {
             Op16 op[kBlk];
             st.take(op);
             double x[kBlk];
 #pragma unroll
-            for (int i = 0; i < kBlk; ++i) x[i] = pv[op[i].meta & kOffMask];
+            for (int i = 0; i < kBlk; ++i) x[i] = lds_field(&op[i].meta, 0, pvb);
 #pragma unroll
             for (int i = 0; i < kBlk; ++i) {
-                const uint32_t fl = op[i].meta >> 28;
+                const uint32_t fl = op[i].flags;
                 acc = (fl & kFirst) ? op[i].coef * x[i] : acc + op[i].coef * x[i];
                 if (fl & kLast) {
                     const double m = -c * acc;
-                    lu[off_at(op[i].meta, kOffBits)] = (fl & kDiag) ? 1.0 + m : m;
+                    lds_ref(lds_addr(&op[i].meta, 1, lub)) = (fl & kDiag) ? 1.0 + m : m;
                 }
             }
         }
@@ -340,6 +347,7 @@ struct Cell {
     {
         Prefetcher<uint64_t> st;
         st.start(p.lu_ops, lane, p.lu_blocks);
+        const uint32_t lub = lds_base(lu);
         double acc = 0.0;
         int bad = 0;
         for (int b = 0; b < p.lu_blocks; ++b) {
@@ -348,11 +356,11 @@ struct Cell {
             double ad[kBlk], al[kBlk], au[kBlk], ag[kBlk];
 #pragma unroll
             for (int i = 0; i < kBlk; ++i) {
-                const uint32_t lo = (uint32_t)op[i], hi = (uint32_t)(op[i] >> 32);
-                ad[i] = lu[lo & kOffMask];
-                al[i] = lu[(lo >> 16) & kOffMask];
-                au[i] = lu[hi & kOffMask];
-                ag[i] = lu[(hi >> 16) & kOffMask];
+                const uint32_t w[2] = {(uint32_t)op[i], (uint32_t)(op[i] >> 32)};
+                ad[i] = lu[w[0] & kOffMask];
+                al[i] = lu[(w[0] >> 16) & kOffMask];
+                au[i] = lds_field(w, 2, lub);  // bare 16-bit fields
+                ag[i] = lds_field(w, 3, lub);
             }
             bool any_recip = false;
             double res[kBlk];

@@ -28,14 +28,15 @@ __host__ __device__ constexpr int tail_at(int M, int row, int col)
 }
 constexpr int kOffBits = 14;  // bits of an LDS offset inside an op
 constexpr uint32_t kOffMask = (1u << kOffBits) - 1;
-// flags of a 16-byte op's meta word (bits 28..)
+// flags of a Newton-matrix op (Op16::flags)
 constexpr uint32_t kFirst = 1, kLast = 2, kDiag = 4;
 // An LU op (64 bits) is four 16-bit fields -- destination, l, u and the
 // stored 1/U_kk, each a 14-bit LDS index from bit 0 of its field, so that a
 // field is taken out with one mask or bit-field extract -- with the flags in
-// the fields' top bits.
-constexpr uint64_t kLuFirst = 1ull << 14, kLuLast = 1ull << 15, kLuScale = 1ull << 30, kLuRecip = 1ull << 31,
-                   kLuBarrier = 1ull << 46;
+// the top bits of the destination and l fields.  The u and 1/U_kk fields
+// carry nothing else (each is read with one multiply-add of the 16-bit
+// field); where a level ends is kept on the host (HostTables::lu_barrier).
+constexpr uint64_t kLuFirst = 1ull << 14, kLuLast = 1ull << 15, kLuScale = 1ull << 30, kLuRecip = 1ull << 31;
 
 // Streaming f/J kernel tables.  A work item is a run of chunks processed by
 // one wavefront in order.  A chunk computes its monomials -- the product of
@@ -70,11 +71,13 @@ constexpr int kFjGroup = 8;           // monomials whose loads are issued togeth
 constexpr int kFjRecGroup = 4;        // records whose table loads are issued together
 static_assert(kFjQmax % kFjGroup == 0 && kFjQmax < 256, "chunk size");
 
-// A 16-byte op of the gather streams: coefficient and packed indices/flags.
+// A 16-byte op of the gather streams: coefficient, packed indices, flags.
+// f gather: meta = the rate's index.  Newton matrix: meta = source index |
+// destination << 16 (two bare 16-bit fields), flags = kFirst | kLast | kDiag.
 struct alignas(16) Op16 {
     double coef;
-    uint32_t meta;  // source index | dst << kOffBits | flags << 28
-    uint32_t pad;
+    uint32_t meta;
+    uint32_t flags;
 };
 
 // A work item of the generated VJP kernel (reverse mode of f).  With
@@ -155,6 +158,7 @@ struct HostTables {
     // barrier flag ends a level.
     std::vector<uint64_t> lu_ops;
     int lu_blocks = 0, lu_steps = 0;
+    std::vector<uint8_t> lu_barrier;  // per LU block: 1 if a level ends with it (host checks only)
     // Schur complement of the front pivots onto the dense tail, as FP64
     // matrix-core products (16 x 16 x 4 blocks): the tail block T (M x M)
     // receives T -= L_TF U_FT, where L_TF holds the final L entries of the tail

@@ -114,12 +114,12 @@ std::vector<int32_t> markowitz_order(const std::vector<std::vector<char>> &pat)
     return order;
 }
 
-Op16 make_op16(double coef, uint32_t meta)
+Op16 make_op16(double coef, uint32_t meta, uint32_t flags = 0)
 {
     Op16 o;
     o.coef = coef;
     o.meta = meta;
-    o.pad = 0;
+    o.flags = flags;
     return o;
 }
 
@@ -588,12 +588,12 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
                 uint32_t fl = 0;
                 if (q == 0) fl |= kFirst;
                 if (q + 1 == tl.size()) fl |= kLast | (ediag[e] ? kDiag : 0u);
-                chains[e].push_back(make_op16(tl[q].second, (uint32_t)tl[q].first | ((uint32_t)e << kOffBits) | (fl << 28)));
+                chains[e].push_back(make_op16(tl[q].second, (uint32_t)tl[q].first | ((uint32_t)e << 16), fl));
             }
         }
         auto lanes = pack_chains(chains);
         t->nm_ops.clear();
-        t->nm_blocks = emit_blocks(lanes, make_op16(0.0, (uint32_t)P | ((uint32_t)TRASH << kOffBits)), &t->nm_ops);
+        t->nm_blocks = emit_blocks(lanes, make_op16(0.0, (uint32_t)P | ((uint32_t)TRASH << 16)), &t->nm_ops);
     }
 
     // ---- solver: level-scheduled right-looking LU of the front pivots ------
@@ -617,6 +617,7 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         for (int k = q + 1; k < F; ++k)
             if (lp[k][q] && lp[q][k]) diag_last[k] = std::max(diag_last[k], level[q]);
     t->lu_ops.clear();
+    t->lu_barrier.clear();
     t->lu_steps = 0;
     const uint64_t NOP = lu_op(TRASH, ZERO, ZERO, ZERO, kLuFirst | kLuLast);
     auto emit_step = [&](std::vector<std::vector<uint64_t>> &chains) {
@@ -625,11 +626,10 @@ mcc_status compile_mechanism(const mcc_mech_desc *d, int dense_tail, HostTables 
         size_t len = 0;
         for (auto &l : lanes) len = std::max(len, l.size());
         len = (len + kBlk - 1) / kBlk * kBlk;
-        for (auto &l : lanes) {
+        for (auto &l : lanes)
             while (l.size() < len) l.push_back(NOP);
-            l.back() |= kLuBarrier;
-        }
-        emit_blocks(lanes, NOP, &t->lu_ops);
+        const int nb = emit_blocks(lanes, NOP, &t->lu_ops);
+        for (int b = 0; b < nb; ++b) t->lu_barrier.push_back(b + 1 == nb ? 1 : 0);
         t->lu_steps++;
     };
     if (F > 0) {

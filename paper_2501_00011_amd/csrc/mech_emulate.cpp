@@ -69,11 +69,12 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
         for (int bk = 0; bk < t.nm_blocks; ++bk)
             for (int i = 0; i < kBlk; ++i) {
                 const Op16 &o = t.nm_ops[((size_t)bk * kWave + lane) * kBlk + i];
-                const uint32_t fl = o.meta >> 28;
-                const double x = pv[chk(o.meta & kOffMask, P + 1)];
+                const uint32_t fl = o.flags;
+                if (fl & ~(kFirst | kLast | kDiag)) bad++;
+                const double x = pv[chk(o.meta & 0xffff, P + 1)];
                 acc = (fl & kFirst) ? o.coef * x : acc + o.coef * x;
                 if (fl & kLast) {
-                    const int dst = chk((o.meta >> kOffBits) & kOffMask, t.lu_nnz + 2);
+                    const int dst = chk(o.meta >> 16, t.lu_nnz + 2);
                     if (dst == ZERO) bad++;
                     if (dst < t.lu_nnz) written[dst]++;
                     const double m = -c * acc;
@@ -96,6 +97,7 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
                 const uint64_t w = t.lu_ops[((size_t)bk * kWave + lane) * kBlk + i];
                 const int dst = chk(w & kOffMask, t.lu_nnz + 2), l = chk((w >> 16) & kOffMask, t.lu_nnz + 2);
                 const int u = chk((w >> 32) & kOffMask, t.lu_nnz + 2), g = chk((w >> 48) & kOffMask, t.lu_nnz + 2);
+                if ((w >> 46) & 3 || (w >> 62) & 3) bad++;  // the u and 1/U_kk fields are bare indices
                 const double a0 = (w & kLuFirst) ? lu[dst] : acc[lane];
                 if (w & kLuScale) {
                     acc[lane] = a0 * lu[g];
@@ -121,11 +123,11 @@ int emulate_cell(const HostTables &t, const double *k, const double *y_species, 
                 }
                 lu[dst] = res[q];
             }
-        // the barrier flag must be the same on every lane
-        const uint64_t first_lane = t.lu_ops[((size_t)bk * kWave) * kBlk + kBlk - 1];
-        for (int lane = 1; lane < kWave; ++lane)
-            if ((t.lu_ops[((size_t)bk * kWave + lane) * kBlk + kBlk - 1] ^ first_lane) & kLuBarrier) bad++;
-        if (first_lane & kLuBarrier) {
+        if ((size_t)bk >= t.lu_barrier.size()) {
+            bad++;
+            break;
+        }
+        if (t.lu_barrier[bk]) {
             // an operand (l, u or 1/U_kk) written in the same level is a hazard
             for (int rd : operand_reads)
                 if (rd != TRASH && rd != ZERO && step_writes.count(rd)) bad++;
