@@ -89,6 +89,19 @@ __device__ __forceinline__ double wave_min(double v)
     return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
 
+// This lane's index, taken afresh where a phase begins.  The empty asm makes
+// it a new value on every call, so the lane predicates of the phase (64-bit
+// masks in scalar registers) are formed where they are used: the compiler
+// would otherwise move them out of the solver loop, keep dozens of them live
+// across it and spill them to vector-register lanes, each use then costing
+// two readlane instructions instead of one compare.
+__device__ __forceinline__ int lane_here()
+{
+    int l = (int)threadIdx.x;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // 1/x of a pivot (finite and not tiny: checked before use): the hardware's
 // reciprocal estimate refined by two Newton steps r <- r + r (1 - x r),
 // within about an ulp, in five dependent instructions where an IEEE-rounded
@@ -101,9 +114,22 @@ __device__ __forceinline__ double pivot_rcp(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// A value the same on every lane, marked so for the compiler (readfirstlane
+// of both halves): decisions taken on it are then scalar branches, not
+// per-lane masks.
+__device__ __forceinline__ double uniform(double x)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+
 // The step-size factors need x^y a few times per step; one out-of-line copy
 // of the FP64 power function keeps its temporaries out of the solver loop.
-__device__ __noinline__ double step_pow(double x, double y) { return pow(x, y); }
+// Its arguments are uniform, but its result comes back in a vector register,
+// which the compiler would take as varying across lanes (and with it the
+// step size, the order and every decision on them).
+__device__ __noinline__ double step_pow_call(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ double step_pow(double x, double y) { return uniform(step_pow_call(x, y)); }
 
 // gamma_j = sum_{i=1..j} 1/i, summed in that order; the reciprocals are
 // compile-time constants, so a run-time j costs no division.
@@ -487,6 +513,7 @@ struct Cell {
             return false;
         } else {
             double *T = lu + p.tail_base;
+            const int lane = lane_here();
             const bool in = lane < M;
             const int row = in ? lane : 0;  // this lane's row (panel phase) or column (row phase)
             const int g = lane >> 4, c16 = lane & 15;
@@ -576,6 +603,7 @@ struct Cell {
         const uint4 *bw = reinterpret_cast<const uint4 *>(p.bwd_map);
         const double *T = lu + p.tail_base;
         const uint32_t lub = lds_base(lu);
+        const int lane = lane_here();
         const int trow = M > 0 && lane < M ? lane : 0;  // this lane's tail row
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
