@@ -227,6 +227,21 @@ struct Cell {
 
     __device__ __forceinline__ bool valid(int s) const { return vld[s]; }
 
+    // The launch parameters, read afresh where a phase begins (the empty asm
+    // makes the pointer a new value on every call): the compiler would
+    // otherwise load every field the loop uses once, keep them all in scalar
+    // registers across the loop and spill them to vector-register lanes; a
+    // scalar load per phase is cheaper than two readlanes per use.  Every
+    // kernel that builds a Cell takes its SolveParams, unchanged, as its first
+    // argument, at offset 0 of the kernel-argument segment.
+    typedef const __attribute__((address_space(4))) SolveParams KParams;
+    __device__ __forceinline__ KParams &params_here() const
+    {
+        KParams *q = (KParams *)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(q));
+        return *q;
+    }
+
     // offset of entry (row, col) in the tail block (column-major, the rows
     // of a column permuted against LDS bank conflicts: tail_at)
     static __device__ __forceinline__ int tat(int row, int col) { return tail_at(M, row, col); }
@@ -237,6 +252,7 @@ struct Cell {
 
     __device__ __forceinline__ void put_y(const double (&v)[NS])
     {
+        KParams &p = params_here();
         lds_handover();
 #pragma unroll
         for (int s = 0; s < NS; ++s)
@@ -248,6 +264,7 @@ struct Cell {
     // f_v = sum nu r gathered per virtual index (lane per index).
     __device__ __forceinline__ void deriv(const double (&v)[NS], double (&f)[NS])
     {
+        KParams &p = params_here();
         rates(v);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -270,6 +287,7 @@ struct Cell {
     // Reaction rates at v into rv (lane per reaction); rv[R] = 0.
     __device__ __forceinline__ void rates(const double (&v)[NS])
     {
+        KParams &p = params_here();
         // the first round's reactant ids are requested before y is stored,
         // so that their global-memory latency overlaps that store
         const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
@@ -305,6 +323,7 @@ struct Cell {
     // Newton matrix M = I - c J(v) written over the LU storage (fill = 0).
     __device__ __forceinline__ void newton_matrix(const double (&v)[NS], double c)
     {
+        KParams &p = params_here();
         partials(v);
         Prefetcher<Op16> st;
         st.start(p.nm_ops, lane, p.nm_blocks);
@@ -332,6 +351,7 @@ struct Cell {
     // Rate partials d r_j / d y_s at v into pv (lane per partial); pv[P] = 0.
     __device__ __forceinline__ void partials(const double (&v)[NS])
     {
+        KParams &p = params_here();
         const int4 *pt = reinterpret_cast<const int4 *>(p.part);
         int4 a[4];  // requested before y is stored, as in rates()
 #pragma unroll
@@ -371,6 +391,7 @@ struct Cell {
     // finite (uniform across the wavefront).
     __device__ __forceinline__ bool factor()
     {
+        KParams &p = params_here();
         Prefetcher<uint64_t> st;
         st.start(p.lu_ops, lane, p.lu_blocks);
         const uint32_t lub = lds_base(lu);
@@ -443,6 +464,7 @@ struct Cell {
 
     __device__ __forceinline__ void schur()
     {
+        KParams &p = params_here();
         if constexpr (M > 0) {
             constexpr int TI = NT <= 2 ? NT : 1;
             const int KS = p.schur_ks;
@@ -509,6 +531,7 @@ struct Cell {
     // Returns true if a pivot is zero, tiny or not finite (uniform).
     __device__ __forceinline__ bool dense_tail()
     {
+        KParams &p = params_here();
         if constexpr (M == 0) {
             return false;
         } else {
@@ -598,6 +621,7 @@ struct Cell {
     // (column-major, lane = row).
     __device__ __forceinline__ void solve(double (&b)[NS])
     {
+        KParams &p = params_here();
         const int NVB = p.NV / 8;
         const uint4 *fw = reinterpret_cast<const uint4 *>(p.fwd_map);
         const uint4 *bw = reinterpret_cast<const uint4 *>(p.bwd_map);
