@@ -154,8 +154,8 @@ struct HostTables {
     std::vector<Op16> nm_ops;
     int nm_blocks = 0;
     // LU: level-scheduled update / reciprocal / scale ops (kLu* layout:
-    // dst | l | u | d in 16-bit fields, flags in their top bits); the
-    // barrier flag ends a level.
+    // dst | l | u | d in 16-bit fields, the flags in the top bits of dst
+    // and l); lu_barrier marks the blocks that end a level.
     std::vector<uint64_t> lu_ops;
     int lu_blocks = 0, lu_steps = 0;
     std::vector<uint8_t> lu_barrier;  // per LU block: 1 if a level ends with it (host checks only)
