@@ -278,8 +278,13 @@ mcc_status mcc_mech_create_ex(const mcc_mech_desc *desc, int device, const mcc_m
         m->adj.unavailable = "the reverse-mode state of one cell needs " +
                              std::to_string((size_t)m->adj.lds_doubles * sizeof(double)) + " bytes of LDS";
     if (m->adj.unavailable.empty() && (e = prepare_adjoint_kernels(max_lds)) != hipSuccess) {
-        delete m;
-        return hip_error(e, "hipFuncSetAttribute");
+        if (e == hipErrorInvalidDeviceFunction) {
+            // a two-wavefront reverse-mode build that spills is not trusted
+            m->adj.unavailable = "the reverse-mode kernel was built with spilled registers";
+        } else {
+            delete m;
+            return hip_error(e, "hipFuncSetAttribute");
+        }
     }
 
     Packer pk;

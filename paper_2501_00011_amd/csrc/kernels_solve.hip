@@ -899,13 +899,15 @@ template <int NS, int M>
 constexpr int kSolveWaves = (NS <= 2 && M <= 48) ? 2 : 1;
 
 // The reverse-mode kernel holds the multipliers of the backward differences
-// and the per-reaction gradient in registers besides the solver's own state;
-// compiled for two wavefronts per SIMD it spills, and the 32-row-tail build
-// then returned wrong d L / d ln k (the multipliers stayed right; measured
-// against the oracle's adjoint).  It is compiled for one wavefront per SIMD,
-// where nothing spills.
+// and the per-reaction gradient in registers besides the solver's own state.
+// For one or two slots and a tail of at most 48 rows it fits two wavefronts
+// per SIMD without spilling (232 vector registers for 72 species), and is
+// compiled so; one wavefront for the larger shapes.  An earlier build that
+// spilled at two wavefronts returned wrong d L / d ln k with the 32-row tail
+// (the multipliers stayed right; cause not identified), so setting up the
+// kernels refuses a two-wavefront build that uses scratch memory.
 template <int NS, int M>
-constexpr int kAdjointWaves = 1;
+constexpr int kAdjointWaves = (NS <= 2 && M <= 48) ? 2 : 1;
 
 // MC: Multi-cells (one system over all cells); TAPE: record the step tape;
 // W: wavefronts per SIMD the registers are budgeted for.
@@ -1687,7 +1689,12 @@ hipError_t prepare_adjoint_kernels(int max_lds_bytes)
 #define MCC_SET_LDS_ADJ(ns, m)                                                                           \
     if (e == hipSuccess)                                                                                \
         e = hipFuncSetAttribute((const void *)adjoint_kernel<ns, m>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                max_lds_bytes);
+                                max_lds_bytes);                                                          \
+    if (e == hipSuccess && kAdjointWaves<ns, m> == 2) {                                                 \
+        hipFuncAttributes fa;                                                                           \
+        e = hipFuncGetAttributes(&fa, (const void *)adjoint_kernel<ns, m>);                             \
+        if (e == hipSuccess && fa.localSizeBytes > 0) e = hipErrorInvalidDeviceFunction;                \
+    }
     MCC_ADJOINT_VARIANTS(MCC_SET_LDS_ADJ)
 #undef MCC_SET_LDS_ADJ
 #define MCC_SET_LDS_REPLAY(ns, m)                                                                       \
