@@ -252,7 +252,6 @@ struct Cell {
 
     __device__ __forceinline__ void put_y(const double (&v)[NS])
     {
-        KParams &p = params_here();
         lds_handover();
 #pragma unroll
         for (int s = 0; s < NS; ++s)
@@ -264,7 +263,6 @@ struct Cell {
     // f_v = sum nu r gathered per virtual index (lane per index).
     __device__ __forceinline__ void deriv(const double (&v)[NS], double (&f)[NS])
     {
-        KParams &p = params_here();
         rates(v);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -287,7 +285,6 @@ struct Cell {
     // Reaction rates at v into rv (lane per reaction); rv[R] = 0.
     __device__ __forceinline__ void rates(const double (&v)[NS])
     {
-        KParams &p = params_here();
         // the first round's reactant ids are requested before y is stored,
         // so that their global-memory latency overlaps that store
         const int4 *rx = reinterpret_cast<const int4 *>(p.rx_reac);
