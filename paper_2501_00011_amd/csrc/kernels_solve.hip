@@ -615,7 +615,11 @@ struct Cell {
     // each column's value is broadcast from its lane with readlane.  For the
     // front columns, the LU offsets of 8 columns come with one 16-byte load
     // per slot, one block ahead; the dense tail block is addressed directly
-    // (column-major, lane = row).
+    // (column-major, lane = row).  Every block loop is unrolled (a slot has
+    // at most eight blocks of eight columns), so each column's lane is a
+    // compile-time constant: the broadcasts read a fixed lane, the lane
+    // predicates compare with constants and the tail addresses are fixed
+    // offsets.
     __device__ __forceinline__ void solve(double (&b)[NS])
     {
         KParams &p = params_here();
@@ -635,7 +639,7 @@ struct Cell {
                 // dependent chain of broadcasts (the scheduling barrier keeps
                 // the compiler from sinking each load to its use, which put a
                 // local-memory round trip into every column).
-#pragma unroll 1
+#pragma unroll
                 for (int k8 = 0; k8 < M; k8 += 8) {
                     double tv[8];
 #pragma unroll
@@ -657,7 +661,10 @@ struct Cell {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
                 if (ord(s) >= ord(ks)) nxt[s] = fw[(size_t)(s * kWave + lane) * NVB + b0];
-            for (int blk = b0; blk < b1; ++blk) {
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                const int blk = b0 + bb;
+                if (blk >= b1) break;
                 double v[NS][8];
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
@@ -691,7 +698,7 @@ struct Cell {
                 uint4 nxt[NS];
 #pragma unroll
                 for (int s = 1; s < NS; ++s) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + M / 8 - 1];
-#pragma unroll 1
+#pragma unroll
                 for (int blk = M / 8 - 1; blk >= 0; --blk) {
                     double v[NS][8];
 #pragma unroll
@@ -725,7 +732,10 @@ struct Cell {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
                 if (ord(s) <= ord(ks)) nxt[s] = bw[(size_t)(s * kWave + lane) * NVB + b1 - 1];
-            for (int blk = b1 - 1; blk >= b0; --blk) {
+#pragma unroll
+            for (int bb = 7; bb >= 0; --bb) {
+                const int blk = b0 + bb;
+                if (blk >= b1) continue;
                 double v[NS][8];
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
